@@ -1,0 +1,177 @@
+/*
+ * paraexp.h -- C ABI of the MI355X (gfx950) block-Krylov Paraexp exp-action library.
+ *
+ * Method: Kooij, Botchev & Geurts, "A block Krylov subspace implementation of the
+ * time-parallel Paraexp method and its extension for nonlinear partial differential
+ * equations" (arXiv 1509.04567).  The library solves, per Paraexp window,
+ *
+ *     u'(t) = L u(t) + g(t),  t in [t0, t1];   u'(t) = L u(t) after t1          (eq. 2.1)
+ *
+ * where L is a periodic 3-point finite-difference stencil (Sec. 3, eq. 3.2) and g is
+ * given by s time samples (eq. 2.2).  The samples are compressed by a truncated SVD
+ * into U p(t) (eq. 2.3, Sec. 2.1), p is a least-squares polynomial in time, and the
+ * solution is advanced by restarted block Arnoldi on the Krylov space of [x | U]
+ * (eq. 2.4) with the exponential of the projected, source-augmented block-Hessenberg
+ * matrix.  With shift = 1 the window is the Paraexp subproblem of eqs. (2.5)-(2.8):
+ * v(t0) = 0, source L u0 + g, and the outputs are v(t_k); u = u0 + sum_j v_j
+ * (eq. 2.9, pe_superpose).
+ *
+ * Sign convention: `L` is the right-hand-side operator, the paper's A in u' = A u + g.
+ *
+ * Conventions for every entry point:
+ *   - pointers documented "device" are HIP device pointers on the context's device;
+ *     "host" pointers are ordinary host memory read during the call;
+ *   - the caller owns every buffer it passes; the library owns only the memory inside
+ *     a pe_ctx (workspace, grown on demand, released by pe_destroy);
+ *   - all matrices are column-major with the stated leading dimension;
+ *   - `stream` is a hipStream_t (NULL = the null stream).  Calls enqueue work on it and
+ *     return after it has completed (the solver's step control reads scalars back);
+ *   - errors are negative pe_status values with a message in pe_last_error(); a
+ *     non-converged solve is not an error: its report carries PE_FLAG_* bits and the
+ *     outputs are still written.
+ */
+#ifndef PARAEXP_H
+#define PARAEXP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PE_OK = 0,
+  PE_ERR_ARG = -1,          /* invalid argument (sizes, ordering, null pointers)      */
+  PE_ERR_NONFINITE = -2,    /* NaN/Inf found in u0, G or the stencil coefficients     */
+  PE_ERR_DEVICE = -3,       /* a HIP runtime call failed                              */
+  PE_ERR_OOM = -4,          /* device workspace allocation failed                     */
+  PE_ERR_UNSUPPORTED = -5   /* valid request outside what this build implements      */
+} pe_status;
+
+/* report flags (informational, outputs are written) */
+enum {
+  PE_FLAG_NOT_CONVERGED = 1,  /* a step was taken at the minimum step with error above tol */
+  PE_FLAG_BREAKDOWN = 2,      /* Krylov space became invariant (exact, "happy") early      */
+  PE_FLAG_RANK_CAPPED = 4,    /* truncation wanted more than rank_max singular vectors     */
+  PE_FLAG_FIT_CAPPED = 8      /* fit residual above fit_tol at q_max terms                 */
+};
+
+typedef enum { PE_FP64 = 0, PE_MIXED = 1 } pe_precision;
+
+typedef struct pe_ctx pe_ctx; /* opaque: device, stream-independent workspace */
+
+/* The operator L (Sec. 3, eq. 3.2):
+ *   (L u)_i = c_minus[i] u_{i-1} + c_zero[i] u_i + c_plus[i] u_{i+1},  indices mod n.
+ * per_point = 0: coeffs points to 3 HOST doubles {c_minus, c_zero, c_plus};
+ * per_point = 1: coeffs points to 3*n DEVICE doubles, rows c_minus[0..n), c_zero, c_plus. */
+typedef struct {
+  int64_t n;
+  int32_t per_point;
+  const double* coeffs;
+} pe_stencil;
+
+/* One window subproblem (Sec. 2.1-2.2; Fig. 2.1 "Given: A, u0, g(t)").
+ *   u0        device, n: initial condition of the whole problem (shifted: used for L u0)
+ *   t0, t1    window; the source acts on [t0, t1] and is zero after t1
+ *   t_samples host, s ascending, t_samples[0] = t0, t_samples[s-1] = t1, s >= 1
+ *   G         device, n x s (ldG >= n): raw source samples g(t_i)
+ *   shift     1: Paraexp shift (v(t0) = 0, source L u0 + g, outputs v); 0: outputs u
+ *   t_out     host, n_out non-decreasing absolute times; with shift = 0 all >= t0,
+ *             with shift = 1 times before t0 give zero columns
+ *   out       device, n x n_out (ldOut >= n), written
+ *   krylov_steps  block Arnoldi steps per restart cycle (l >= 1)
+ *   rank_max  cap on the retained singular vectors; q_max cap on polynomial terms
+ *   tol       accuracy target of the time integration, relative to max(|u0|, |state|)
+ *   svd_tol   truncation: keep m singular vectors with dropped energy <= svd_tol |G^|_F
+ *   fit_tol   polynomial degree: smallest with relative fit residual <= fit_tol
+ *   prec      PE_FP64, or PE_MIXED (Krylov basis stored in fp32, fp64 arithmetic). */
+typedef struct {
+  pe_stencil op;
+  const double* u0;
+  double t0, t1;
+  const double* t_samples;
+  int32_t s;
+  const double* G;
+  int64_t ldG;
+  int32_t shift;
+  const double* t_out;
+  int32_t n_out;
+  double* out;
+  int64_t ldOut;
+  int32_t krylov_steps;
+  int32_t rank_max;
+  int32_t q_max;
+  double tol;
+  double svd_tol;
+  double fit_tol;
+  pe_precision prec;
+} pe_problem;
+
+/* Per-problem report (host). */
+typedef struct {
+  int32_t rank;        /* m, retained singular vectors                            */
+  int32_t q;           /* polynomial terms of p(t)                                */
+  int32_t cycles;      /* accepted restart cycles (time sub-steps)                */
+  int32_t rejected;    /* rejected step-size trials                               */
+  int32_t block_steps; /* block Arnoldi steps performed                           */
+  int32_t flags;       /* PE_FLAG_* bits                                          */
+  double resid_est;    /* largest accepted per-cycle error estimate (absolute)    */
+  double fit_resid;    /* relative fit residual of the chosen q                   */
+  double svd_tail;     /* dropped singular energy relative to |G^|_F              */
+  double sigma1;       /* largest singular value of the shifted samples           */
+} pe_report;
+
+/* Create a context on HIP device `device`.  *ctx receives the handle. */
+pe_status pe_create(pe_ctx** ctx, int device);
+/* Release the context and its workspace (synchronises the device first). */
+pe_status pe_destroy(pe_ctx* ctx);
+/* Message for the last non-OK status returned on this context (never NULL). */
+const char* pe_last_error(const pe_ctx* ctx);
+/* Library version string, e.g. "paraexp-gfx950 0.1". */
+const char* pe_version(void);
+
+/* Step S0 (Sec. 3, eq. 3.2): Y = L X for an n x ncols block.
+ * X, Y device, column-major with leading dimensions ldx, ldy >= n; X and Y must not
+ * overlap.  Exposed for tests and for the stencil bandwidth measurement. */
+pe_status pe_stencil_apply(pe_ctx* ctx, const pe_stencil* op, const double* X, int64_t ldx,
+                           double* Y, int64_t ldy, int32_t ncols, void* stream);
+
+/* Steps S1-S4 (Sec. 2.1, eqs. 2.2-2.3, 2.6): shifted samples, truncated SVD and the
+ * Chebyshev fit of the coefficients, for one problem.
+ *   U     device, n x rank_max (ldU = n): the m retained left singular vectors
+ *   Pi    device, rank_max x q_max (ld = rank_max): p(t) = sum_k Pi[:,k] T_k(x(t)),
+ *         x = (2t - t0 - t1)/(t1 - t0)
+ *   sigma host, s entries (may be NULL): singular values of the shifted samples that
+ *         the routine resolved (zeros beyond the numerical rank), descending
+ *   m, q  host out; report host out (rank, q, fit_resid, svd_tail, sigma1, flags). */
+pe_status pe_compress(pe_ctx* ctx, const pe_problem* prob, double* U, double* Pi, int32_t* m,
+                      int32_t* q, double* sigma, pe_report* report, void* stream);
+
+/* Steps S5-S8 for nprob independent problems with a given compressed source
+ * (stage parity: every problem uses U[i] (n x m[i], ld n) and Pi[i] (m[i] x q[i],
+ * ld m[i]) -- device pointers; U[i]/Pi[i] may be NULL when m[i] = 0).  The sample
+ * fields of the problems (t_samples, G, svd_tol, fit_tol) are ignored; t0, t1 still
+ * define the window and the polynomial variable.  Outputs and reports as in
+ * pe_solve_batch.  All problems advance together, one restart cycle at a time. */
+pe_status pe_expaction_batch(pe_ctx* ctx, const pe_problem* probs, const double* const* U,
+                             const double* const* Pi, const int32_t* m, const int32_t* q,
+                             int32_t nprob, pe_report* reports, void* stream);
+
+/* Steps S1-S8 for nprob independent window subproblems (instances and/or Paraexp
+ * windows) in one batched pipeline.  reports: host array of nprob. */
+pe_status pe_solve_batch(pe_ctx* ctx, const pe_problem* probs, int32_t nprob,
+                         pe_report* reports, void* stream);
+
+/* Step S8 (eq. 2.9): u[:, k] = u0 + sum_{j<P} v_j[:, k], summed in window order.
+ * u0 device n; v host array of P device pointers, each n x n_out with ld ldv;
+ * u device n x n_out with ld ldu (may alias none of the inputs). */
+pe_status pe_superpose(pe_ctx* ctx, const double* u0, const double* const* v, int32_t P,
+                       int64_t n, int32_t n_out, int64_t ldv, double* u, int64_t ldu,
+                       void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PARAEXP_H */

@@ -1,0 +1,18 @@
+"""MI355X (gfx950) block-Krylov Paraexp exp-action library (Python side).
+
+The numerical work lives in libparaexp.so (HIP, see include/paraexp.h); this package
+only binds it.  Kooij, Botchev & Geurts, arXiv 1509.04567.
+"""
+from .binding import (  # noqa: F401
+    Context,
+    PeError,
+    load_library,
+    LIB_PATH,
+    EXPORTED,
+    PE_FP64,
+    PE_MIXED,
+    FLAG_NOT_CONVERGED,
+    FLAG_BREAKDOWN,
+    FLAG_RANK_CAPPED,
+    FLAG_FIT_CAPPED,
+)

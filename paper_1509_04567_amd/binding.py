@@ -1,0 +1,332 @@
+"""ctypes binding of libparaexp.so (C ABI declared in include/paraexp.h).
+
+Argument marshalling only: every numerical step runs in the HIP library.  PyTorch
+(ROCm) provides device memory and the current stream.  Matrices that the ABI takes
+column-major (n x k, leading dimension n) are held as contiguous torch tensors of shape
+(k, n): row i of the tensor is column i of the matrix.
+
+The library must be built (``python -m paper_1509_04567_amd.build``); importing a
+missing or unloadable library raises immediately -- there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libparaexp.so")
+
+PE_OK = 0
+PE_ERR_ARG = -1
+PE_ERR_NONFINITE = -2
+PE_ERR_DEVICE = -3
+PE_ERR_OOM = -4
+PE_ERR_UNSUPPORTED = -5
+PE_FP64 = 0
+PE_MIXED = 1
+FLAG_NOT_CONVERGED = 1
+FLAG_BREAKDOWN = 2
+FLAG_RANK_CAPPED = 4
+FLAG_FIT_CAPPED = 8
+
+EXPORTED = ["pe_create", "pe_destroy", "pe_last_error", "pe_version", "pe_stencil_apply", "pe_compress",
+            "pe_expaction_batch", "pe_solve_batch", "pe_superpose"]
+
+
+class PeStencil(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("per_point", ctypes.c_int32), ("coeffs", ctypes.c_void_p)]
+
+
+class PeProblem(ctypes.Structure):
+    _fields_ = [
+        ("op", PeStencil),
+        ("u0", ctypes.c_void_p),
+        ("t0", ctypes.c_double),
+        ("t1", ctypes.c_double),
+        ("t_samples", ctypes.c_void_p),
+        ("s", ctypes.c_int32),
+        ("G", ctypes.c_void_p),
+        ("ldG", ctypes.c_int64),
+        ("shift", ctypes.c_int32),
+        ("t_out", ctypes.c_void_p),
+        ("n_out", ctypes.c_int32),
+        ("out", ctypes.c_void_p),
+        ("ldOut", ctypes.c_int64),
+        ("krylov_steps", ctypes.c_int32),
+        ("rank_max", ctypes.c_int32),
+        ("q_max", ctypes.c_int32),
+        ("tol", ctypes.c_double),
+        ("svd_tol", ctypes.c_double),
+        ("fit_tol", ctypes.c_double),
+        ("prec", ctypes.c_int32),
+    ]
+
+
+class PeReport(ctypes.Structure):
+    _fields_ = [
+        ("rank", ctypes.c_int32),
+        ("q", ctypes.c_int32),
+        ("cycles", ctypes.c_int32),
+        ("rejected", ctypes.c_int32),
+        ("block_steps", ctypes.c_int32),
+        ("flags", ctypes.c_int32),
+        ("resid_est", ctypes.c_double),
+        ("fit_resid", ctypes.c_double),
+        ("svd_tail", ctypes.c_double),
+        ("sigma1", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class PeError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"paraexp status {status}: {msg}")
+        self.status = status
+
+
+_LIB = None
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libparaexp.so and declare the C signatures (raises if it is missing)."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is not built; run `python -m paper_1509_04567_amd.build`")
+    # torch (ROCm) ships its own HIP runtime; loading it first makes the library bind to
+    # that same runtime (same soname), so torch's memory and streams are valid here.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+    lib = ctypes.CDLL(path)
+    vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    lib.pe_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int]
+    lib.pe_destroy.argtypes = [vp]
+    lib.pe_last_error.argtypes = [vp]
+    lib.pe_last_error.restype = ctypes.c_char_p
+    lib.pe_version.restype = ctypes.c_char_p
+    lib.pe_stencil_apply.argtypes = [vp, ctypes.POINTER(PeStencil), vp, i64, vp, i64, i32, vp]
+    lib.pe_compress.argtypes = [vp, ctypes.POINTER(PeProblem), vp, vp, ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                ctypes.POINTER(ctypes.c_double), ctypes.POINTER(PeReport), vp]
+    lib.pe_expaction_batch.argtypes = [vp, ctypes.POINTER(PeProblem), ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                       ctypes.POINTER(i32), ctypes.POINTER(i32), i32, ctypes.POINTER(PeReport), vp]
+    lib.pe_solve_batch.argtypes = [vp, ctypes.POINTER(PeProblem), i32, ctypes.POINTER(PeReport), vp]
+    lib.pe_superpose.argtypes = [vp, vp, ctypes.POINTER(vp), i32, i64, i32, i64, vp, i64, vp]
+    for name in ["pe_create", "pe_destroy", "pe_stencil_apply", "pe_compress", "pe_expaction_batch",
+                 "pe_solve_batch", "pe_superpose"]:
+        getattr(lib, name).restype = ctypes.c_int
+    _LIB = lib
+    return lib
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev(x, device):
+    """float64 contiguous device tensor (copies host arrays)."""
+    torch = _torch()
+    if isinstance(x, torch.Tensor):
+        return x.to(device=device, dtype=torch.float64).contiguous()
+    return torch.as_tensor(np.ascontiguousarray(x, dtype=np.float64), device=device)
+
+
+def _host_doubles(a):
+    arr = np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+    return arr, arr.ctypes.data_as(ctypes.c_void_p)
+
+
+@dataclasses.dataclass
+class DeviceProblem:
+    """Device-side buffers of one window subproblem plus the host arrays the ABI reads.
+    `src` is any object with the fields of the ABI's pe_problem (numpy or torch arrays)."""
+
+    struct: PeProblem
+    out: "object"               # torch (n_out, n): row k = solution at t_out[k]
+    keep: list
+
+
+def make_problem(src, device, precision: int = PE_FP64, out=None) -> DeviceProblem:
+    torch = _torch()
+    n = int(src.n)
+    keep = []
+    coeffs = np.asarray(src.coeffs, dtype=np.float64) if not isinstance(src.coeffs, torch.Tensor) else src.coeffs
+    per_point = 1 if np.ndim(coeffs) == 2 else 0
+    if per_point:
+        c_dev = _dev(coeffs, device).reshape(3, n)
+        keep.append(c_dev)
+        cptr = ctypes.c_void_p(c_dev.data_ptr())
+    else:
+        c_host, cptr = _host_doubles(coeffs)
+        keep.append(c_host)
+    u0 = _dev(src.u0, device).reshape(n)
+    keep.append(u0)
+    G = getattr(src, "G", None)
+    ts = getattr(src, "t_samples", None)
+    if G is not None:
+        Gt = _dev(np.asarray(G).T if not isinstance(G, torch.Tensor) else G.T, device)  # (s, n)
+        keep.append(Gt)
+        s = int(Gt.shape[0])
+        ts_host, ts_ptr = _host_doubles(ts)
+        keep.append(ts_host)
+        gptr = ctypes.c_void_p(Gt.data_ptr())
+    else:
+        s, ts_ptr, gptr = 0, None, None
+    to_host, to_ptr = _host_doubles(src.t_out)
+    keep.append(to_host)
+    n_out = int(to_host.shape[0])
+    if out is None:
+        out = torch.empty((max(n_out, 1), n), dtype=torch.float64, device=device)
+    keep.append(out)
+    st = PeProblem()
+    st.op = PeStencil(n, per_point, cptr)
+    st.u0 = u0.data_ptr()
+    st.t0 = float(src.t0)
+    st.t1 = float(src.t1)
+    st.t_samples = ts_ptr
+    st.s = s
+    st.G = gptr
+    st.ldG = n
+    st.shift = 1 if bool(getattr(src, "shift", True)) else 0
+    st.t_out = to_ptr
+    st.n_out = n_out
+    st.out = out.data_ptr()
+    st.ldOut = n
+    st.krylov_steps = int(src.krylov_steps)
+    st.rank_max = int(src.rank_max)
+    st.q_max = int(src.q_max)
+    st.tol = float(src.tol)
+    st.svd_tol = float(getattr(src, "svd_tol", 1e-13))
+    st.fit_tol = float(getattr(src, "fit_tol", 1e-13))
+    st.prec = int(precision)
+    return DeviceProblem(struct=st, out=out[:n_out], keep=keep)
+
+
+class Context:
+    """One library context on a HIP device (workspace is cached across calls)."""
+
+    def __init__(self, device: int = 0):
+        self.lib = load_library()
+        self.device_index = device
+        torch = _torch()
+        self.device = torch.device("cuda", device)
+        h = ctypes.c_void_p()
+        st = self.lib.pe_create(ctypes.byref(h), device)
+        if st != PE_OK:
+            raise PeError(st, "pe_create failed")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.pe_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st):
+        if st != PE_OK:
+            raise PeError(st, self.lib.pe_last_error(self.h).decode())
+
+    # -- S0
+    def stencil_apply(self, coeffs, X):
+        """Y = L X for X a torch (k, n) device tensor (k columns of length n)."""
+        torch = _torch()
+        X = _dev(X, self.device)
+        k, n = X.shape
+        Y = torch.empty_like(X)
+        keep = []
+        if np.ndim(coeffs) == 2:
+            cd = _dev(coeffs, self.device)
+            keep.append(cd)
+            op = PeStencil(n, 1, ctypes.c_void_p(cd.data_ptr()))
+        else:
+            ch, cp = _host_doubles(coeffs)
+            keep.append(ch)
+            op = PeStencil(n, 0, cp)
+        self._check(self.lib.pe_stencil_apply(self.h, ctypes.byref(op), ctypes.c_void_p(X.data_ptr()), n,
+                                              ctypes.c_void_p(Y.data_ptr()), n, k, _stream_ptr()))
+        return Y
+
+    # -- S1-S4
+    def compress(self, src, precision: int = PE_FP64):
+        torch = _torch()
+        dp = make_problem(src, self.device, precision)
+        n, rmax, qmax = int(src.n), int(src.rank_max), int(src.q_max)
+        U = torch.zeros((max(rmax, 1), n), dtype=torch.float64, device=self.device)
+        Pi = torch.zeros((qmax, max(rmax, 1)), dtype=torch.float64, device=self.device)
+        m, q = ctypes.c_int32(), ctypes.c_int32()
+        sig = (ctypes.c_double * max(dp.struct.s, 1))()
+        rep = PeReport()
+        self._check(self.lib.pe_compress(self.h, ctypes.byref(dp.struct), ctypes.c_void_p(U.data_ptr()),
+                                         ctypes.c_void_p(Pi.data_ptr()), ctypes.byref(m), ctypes.byref(q), sig,
+                                         ctypes.byref(rep), _stream_ptr()))
+        mm, qq = m.value, q.value
+        # U rows 0..m-1 are the retained columns; Pi is (rank_max x q_max) column-major
+        return dict(U=U[:mm], Pi=Pi[:qq, :mm].T.contiguous() if mm else Pi[:0, :0], m=mm, q=qq,
+                    sigma=np.array(sig[:dp.struct.s]), report=rep.as_dict())
+
+    # -- S1-S8
+    def solve_batch(self, problems: Sequence, precision: int = PE_FP64):
+        dps = [make_problem(p, self.device, precision) for p in problems]
+        arr = (PeProblem * len(dps))(*[d.struct for d in dps])
+        reps = (PeReport * len(dps))()
+        self._check(self.lib.pe_solve_batch(self.h, arr, len(dps), reps, _stream_ptr()))
+        return [d.out for d in dps], [r.as_dict() for r in reps]
+
+    # -- S5-S8 with a given compressed source
+    def expaction_batch(self, problems: Sequence, Us: Sequence, Pis: Sequence, precision: int = PE_FP64):
+        """Us[i]: torch (m, n) rows = columns of U; Pis[i]: (m, q) numpy/torch Chebyshev coefficients."""
+        torch = _torch()
+        dps = [make_problem(p, self.device, precision) for p in problems]
+        keep = []
+        Uptr = (ctypes.c_void_p * len(dps))()
+        Pptr = (ctypes.c_void_p * len(dps))()
+        ms = (ctypes.c_int32 * len(dps))()
+        qs = (ctypes.c_int32 * len(dps))()
+        for i, (U, Pi) in enumerate(zip(Us, Pis)):
+            U = _dev(U, self.device)
+            Pi = _dev(Pi, self.device)
+            m = int(U.shape[0]) if U.numel() else 0
+            q = int(Pi.shape[1]) if m else 0
+            Pcm = Pi.T.contiguous() if m else Pi   # column-major m x q == torch (q, m)
+            keep += [U, Pcm]
+            Uptr[i] = U.data_ptr() if m else None
+            Pptr[i] = Pcm.data_ptr() if m else None
+            ms[i], qs[i] = m, q
+        arr = (PeProblem * len(dps))(*[d.struct for d in dps])
+        reps = (PeReport * len(dps))()
+        self._check(self.lib.pe_expaction_batch(self.h, arr, Uptr, Pptr, ms, qs, len(dps), reps, _stream_ptr()))
+        return [d.out for d in dps], [r.as_dict() for r in reps]
+
+    # -- S8
+    def superpose(self, u0, vs: Sequence):
+        """u(t_k) = u0 + sum_j v_j(t_k); vs are torch (n_out, n) tensors."""
+        torch = _torch()
+        u0 = _dev(u0, self.device)
+        n = int(u0.shape[0])
+        n_out = int(vs[0].shape[0]) if vs else 0
+        vs = [_dev(v, self.device) for v in vs]
+        ptrs = (ctypes.c_void_p * max(len(vs), 1))(*[v.data_ptr() for v in vs])
+        u = torch.empty((max(n_out, 1), n), dtype=torch.float64, device=self.device)
+        self._check(self.lib.pe_superpose(self.h, ctypes.c_void_p(u0.data_ptr()), ptrs, len(vs), n, n_out, n,
+                                          ctypes.c_void_p(u.data_ptr()), n, _stream_ptr()))
+        return u[:n_out]

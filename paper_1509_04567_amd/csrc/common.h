@@ -1,0 +1,95 @@
+// Shared device/host definitions of the gfx950 Paraexp library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#define PE_WAVE 64
+
+// ---------------------------------------------------------------------------------
+// Per-problem descriptor, resident in device memory and rewritten by the host at the
+// start of each restart cycle.  All device pointers belong to the context workspace
+// except u0 / G / out / coef which belong to the caller.
+// ---------------------------------------------------------------------------------
+struct ProbDev {
+  // operator (paper Sec. 3, eq. 3.2): (L u)_i = cm[i] u_{i-1} + cz[i] u_i + cp[i] u_{i+1}
+  int64_t n;
+  int32_t per_point;
+  double c3[3];            // constant coefficients when per_point == 0
+  const double* coef;      // 3*n rows when per_point == 1
+
+  // Krylov basis: (lmax+1) blocks of n*bw, row-major inside a block; fp64 or fp32 storage
+  double* V;
+  float* V32;
+  int32_t mixed;           // 1: basis stored in fp32 (V32), arithmetic in fp64
+  double* Qloc1;           // n*bw local Q factors of the two TSQR passes
+  double* Qloc2;
+  double* Rloc;            // Cu*bw*bw local R factors (reused by both passes)
+  double* Cn;              // Cu*bw squared column norms of the chunks before projection
+  double* Qs1;             // Cu*bw*bw combine factors
+  double* Qs2;
+  double* Rf;              // 3 * bw*bw: final R of pass 1, pass 2, init
+  double* Part;            // 2 * Cp*(nbmax)*bw*bw projection partials (pass 1, pass 2)
+  double* S;               // 2 * nbmax*bw*bw reduced projection coefficients
+  double* H;               // ((l+1)*bw) x (l*bw) column-major, ldH = (l+1)*bw
+  int64_t ldH;
+  unsigned* cnt;           // counters: [0..nbmax) pass-1 slots, [nbmax..2nbmax) pass 2, [2nbmax] update
+  int32_t nbmax;           // capacity of slots (lmax + 1)
+
+  // sources used by the first block of a cycle / by given-block mode
+  const double* U;         // n x m column-major (ld n)
+  const double* x;         // current state, n
+  int32_t m;               // source columns in the first block
+  int32_t with_x;          // 1: the state is the last column of the first block
+  const double* Xg;        // given-block mode: column-major source matrix
+  int64_t ldXg;
+
+  double* xstate;          // writable state (same buffer as x)
+  double* outcol;          // output column to receive the new state, or null
+  int32_t proj;            // 1: project the state with this cycle's accepted y
+
+  // cycle geometry
+  int32_t bw;              // block width this cycle
+  int32_t l;               // block steps this cycle
+  int32_t active;          // 1: participates in this cycle's kernels
+  int32_t rows_u;          // rows per update chunk (>= bw); last chunk takes the remainder
+  int32_t Cu;              // number of update chunks
+  int32_t rows_p;          // rows per projection chunk
+  int32_t Cp;              // number of projection chunks
+};
+
+struct ExpmDev {
+  int32_t N;               // dimension of the augmented projected matrix (l*bw + q)
+  int32_t active;          // 1: this problem runs the current trial
+  int32_t nsq;             // squarings for this trial
+  int32_t l, bw, m, q, with_x;
+  int32_t lbw;             // l*bw: start of the polynomial block
+  int32_t ldPi;
+  double alpha;            // delta / 2^nsq
+  double kscale;           // 2 / (t1 - t0): time derivative of the Chebyshev variable
+  double* Ht;              // N x N column-major (unscaled augmented matrix)
+  double* A;               // work matrices, N x N each
+  double* A2;
+  double* A3;
+  double* A4;
+  double* P;
+  double* T;
+  double* b;               // N: initial projected vector
+  double* y;               // N: exp(delta Ht) b
+  double* out;             // 2 doubles: error estimate, |y[0:lbw]|
+  const double* H;         // Arnoldi Hessenberg, column-major, ldH
+  int64_t ldH;
+  const double* R0;        // bw x bw row-major: [U | x] = V_0 R0
+  const double* Pi;        // m x q column-major (ldPi): Chebyshev coefficients of p(t)
+  const double* w;         // q: T_k(x(tau)) at the start of the cycle
+  const double* Dm;        // qmax x qmax row-major Chebyshev derivative matrix
+  int32_t qmax;
+};
+
+// Host-visible helpers ---------------------------------------------------------
+#define PE_CHECK_HIP(expr)                                                        \
+  do {                                                                            \
+    hipError_t _e = (expr);                                                       \
+    if (_e != hipSuccess) return pe_fail(ctx, PE_ERR_DEVICE, #expr, _e);         \
+  } while (0)

@@ -1,0 +1,54 @@
+// Kernel launchers of the gfx950 Paraexp library (host-callable, defined in kernels.hip).
+#pragma once
+
+#include "common.h"
+
+namespace pe {
+
+// modes of the block orthogonalisation kernels
+enum BlockMode : int { MODE_ARNOLDI = 0, MODE_GIVEN = 1, MODE_INIT = 2 };
+
+// dynamic LDS requested by the update kernel at most (bytes)
+constexpr int kUpdateLdsMax = 64 * 1024;
+
+// Y[:, c] = L X[:, c]
+void launch_stencil_cols(int64_t n, int per_point, const double* c3, const double* coef, const double* X,
+                         int64_t ldx, double* Y, int64_t ldy, int ncols, hipStream_t st);
+// Gh[:, i] = G[:, i] + add[:]   (add may be null)
+void launch_add_column(int64_t n, int s, const double* G, int64_t ldG, const double* add, double* Gh,
+                       int64_t ldGh, hipStream_t st);
+
+// block orthogonalisation (batched over problems; basis storage fp32 when `mixed`)
+void launch_block_proj(ProbDev* d, int nprob, int grid_x, size_t smem, int j, int nb, int pass, int mode,
+                       int mixed, hipStream_t st);
+void launch_block_update(ProbDev* d, int nprob, int grid_x, size_t smem, int j, int nb, int pass, int mode,
+                         int mixed, hipStream_t st);
+void launch_block_commit(ProbDev* d, int nprob, int grid_x, int j, int mixed, hipStream_t st);
+
+// exponential of the projected augmented matrix
+void launch_build_aug(ExpmDev* e, int nprob, int64_t maxNN, hipStream_t st);
+void launch_norm1(ExpmDev* e, double* out, int nprob, hipStream_t st);
+void launch_elementwise(ExpmDev* e, int op, int nprob, int64_t maxNN, hipStream_t st);
+void launch_gemm(ExpmDev* e, int op, int k, int nprob, int tiles_max, hipStream_t st);
+void launch_expm_apply(ExpmDev* e, int nprob, int maxN, hipStream_t st);
+
+// x = V y (+ output column)
+void launch_project(ProbDev* d, ExpmDev* e, int nprob, int64_t maxn, int max_lbw, int mixed, hipStream_t st);
+
+// compression helpers (single problem)
+void launch_row_norms(const double* R, int64_t ldR, int rows, int cols, double* rn, hipStream_t st);
+void launch_jacobi_svd(const double* R, int64_t ldR, const int* sel, int s, int r, double* A, double* J,
+                       double* sig, int* perm, int* info, hipStream_t st);
+void launch_form_u(const double* Q, int bwc, int64_t n, const int* sel, int r, const double* J, const int* perm,
+                   int m, double* U, int64_t ldU, hipStream_t st);
+void launch_fit(const double* A, int s, const int* perm, int m, const double* ts, double t0, double t1, int qcap,
+                double fit_tol, double* Pi, int ldPi, double* work, double* info, hipStream_t st);
+
+// utilities
+void launch_superpose(const double* u0, const double* const* v, int P, int64_t n, int n_out, int64_t ldv,
+                      double* u, int64_t ldu, hipStream_t st);
+void launch_check_finite(const double* x, int64_t n, int cols, int64_t ld, int* flag, hipStream_t st);
+void launch_fill(double* x, int64_t n, int cols, int64_t ld, double v, hipStream_t st);
+void launch_copy(const double* a, double* b, int64_t n, hipStream_t st);
+
+}  // namespace pe

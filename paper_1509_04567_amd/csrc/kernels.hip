@@ -1,0 +1,1111 @@
+// HIP kernels (gfx950) of the block-Krylov Paraexp exp-action path.
+//
+// Steps covered here (Kooij, Botchev & Geurts, arXiv 1509.04567):
+//   S0  stencil operator (Sec. 3, eq. 3.2)                       k_stencil_cols, fused in k_block_*
+//   S3  QR of the source samples (Sec. 2.1, eq. 2.2-2.3)         k_block_* in MODE_GIVEN
+//   S5  block Arnoldi on K_l(A, [x|U]) (eq. 2.4)                 k_block_* in MODE_ARNOLDI / MODE_INIT
+//   S6  exponential of the projected augmented matrix            k_gemm (MFMA f64), k_lincomb, ...
+//   S7  state/output projection V y                              k_project
+//   S8  superposition u = u0 + sum_j v_j (eq. 2.9)               k_superpose
+//
+// Block orthogonalisation = two passes of block classical Gram-Schmidt, each followed by
+// a tall-skinny QR (TSQR: per-chunk wave-level MGS2, then a QR of the stacked chunk R
+// factors done by the last workgroup to finish).  The intra-block QR must be
+// Householder-quality: Cholesky-based block normalisation loses orthogonality when the
+// new block is nearly rank deficient, which the Fourier-mode sources of these problems
+// produce in the first Krylov steps.
+#include "kernels.h"
+
+#include <cmath>
+
+namespace pe {
+
+// ------------------------------------------------------------------------------------
+// reductions and helpers
+// ------------------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// sum over a workgroup whose size is a multiple of 64; `red` holds >= 16 doubles of LDS
+__device__ double block_sum(double v, double* red) {
+  v = wave_sum(v);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  __syncthreads();
+  if (l == 0) red[w] = v;
+  __syncthreads();
+  double t = 0.0;
+  const int nw = blockDim.x >> 6;
+  for (int i = 0; i < nw; ++i) t += red[i];
+  return t;
+}
+
+__device__ double block_max(double v, double* red) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  __syncthreads();
+  if (l == 0) red[w] = v;
+  __syncthreads();
+  double t = 0.0;
+  const int nw = blockDim.x >> 6;
+  for (int i = 0; i < nw; ++i) t = fmax(t, red[i]);
+  return t;
+}
+
+// splitmix64 finaliser (Steele, Lea & Flood 2014) -> uniform double in [-1, 1)
+__device__ __forceinline__ double hash_unit(uint64_t a, uint64_t b) {
+  uint64_t z = a * 0x9E3779B97F4A7C15ull + (b + 1) * 0xD1B54A32D192ED03ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z ^= z >> 31;
+  return (double)(z >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+}
+
+template <typename TS>
+__device__ __forceinline__ TS* basis_ptr(const ProbDev& p);
+template <>
+__device__ __forceinline__ double* basis_ptr<double>(const ProbDev& p) { return p.V; }
+template <>
+__device__ __forceinline__ float* basis_ptr<float>(const ProbDev& p) { return p.V32; }
+
+__device__ __forceinline__ void stencil_coefs(const ProbDev& p, int64_t r, double& cm, double& cz, double& cp) {
+  if (p.per_point) {
+    cm = p.coef[r];
+    cz = p.coef[p.n + r];
+    cp = p.coef[2 * p.n + r];
+  } else {
+    cm = p.c3[0];
+    cz = p.c3[1];
+    cp = p.c3[2];
+  }
+}
+
+// chunk of a row for the update (TSQR) partition: the last chunk takes the remainder
+__device__ __forceinline__ int chunk_of(const ProbDev& p, int64_t r) {
+  int64_t u = r / p.rows_u;
+  return (int)(u < p.Cu - 1 ? u : p.Cu - 1);
+}
+
+// entry (r, col) of a TSQR output block: Qloc[r, :] . Qs[u(r)][:, col]
+__device__ __forceinline__ double tsqr_entry(const ProbDev& p, const double* Qloc, const double* Qs, int64_t r,
+                                             int col) {
+  const int bw = p.bw;
+  const int u = chunk_of(p, r);
+  const double* q = Qloc + r * bw;
+  const double* s = Qs + (int64_t)u * bw * bw + col;
+  double acc = 0.0;
+  for (int k = 0; k < bw; ++k) acc += q[k] * s[k * bw];
+  return acc;
+}
+
+// Modified Gram-Schmidt with reorthogonalisation on a row-major rows x bw array with
+// leading dimension ld.  A "team" (one wave, or the whole workgroup when BLOCK) owns the
+// array; thread t handles rows t, t+T, ...  R (bw x bw, row-major, pre-zeroed) receives
+// the triangular factor (written by team thread 0).
+// A column is numerically dependent when its remainder is <= kDepTol times its reference
+// norm ref[b] (the column norm before the block projections; when ref is null, the norm
+// of the column as given).  Such a column gets a zero diagonal in R and is replaced by a
+// pseudo-random unit vector orthogonal to the previous columns, so Q stays orthonormal;
+// with stack > 0 the replacement lives on rows r = b (mod stack) only, i.e. on the
+// replacement directions of the chunk factors in a TSQR combine.
+#define PE_DEP_TOL 1e-12
+template <bool BLOCK, typename Ptr>
+__device__ void mgs2_qr(Ptr X, int rows, int ld, int bw, double* R, uint64_t seed, double* red, const double* ref,
+                        int stack) {
+  const int T = BLOCK ? (int)blockDim.x : 64;
+  const int t = BLOCK ? (int)threadIdx.x : (int)(threadIdx.x & 63);
+  auto rsum = [&](double v) -> double { return BLOCK ? block_sum(v, red) : wave_sum(v); };
+  for (int b = 0; b < bw; ++b) {
+    double n0;
+    if (ref) {
+      n0 = ref[b];
+    } else {
+      double s0 = 0.0;
+      for (int r = t; r < rows; r += T) {
+        double v = X[(int64_t)r * ld + b];
+        s0 += v * v;
+      }
+      n0 = sqrt(rsum(s0));
+    }
+    for (int pass = 0; pass < 2; ++pass) {
+      for (int a = 0; a < b; ++a) {
+        double s = 0.0;
+        for (int r = t; r < rows; r += T) s += X[(int64_t)r * ld + a] * X[(int64_t)r * ld + b];
+        const double d = rsum(s);
+        for (int r = t; r < rows; r += T) X[(int64_t)r * ld + b] -= d * X[(int64_t)r * ld + a];
+        if (t == 0) R[a * bw + b] += d;
+      }
+    }
+    double s1 = 0.0;
+    for (int r = t; r < rows; r += T) {
+      double v = X[(int64_t)r * ld + b];
+      s1 += v * v;
+    }
+    const double nr = sqrt(rsum(s1));
+    if (nr > PE_DEP_TOL * n0 && nr > 1e-300) {
+      const double inv = 1.0 / nr;
+      for (int r = t; r < rows; r += T) X[(int64_t)r * ld + b] *= inv;
+      if (t == 0) R[b * bw + b] = nr;
+    } else {
+      if (t == 0) R[b * bw + b] = 0.0;
+      for (int r = t; r < rows; r += T)
+        X[(int64_t)r * ld + b] = (stack > 0 && (r % stack) != b) ? 0.0 : hash_unit(seed + (uint64_t)r, (uint64_t)b);
+      for (int pass = 0; pass < 3; ++pass) {
+        for (int a = 0; a < b; ++a) {
+          double s = 0.0;
+          for (int r = t; r < rows; r += T) s += X[(int64_t)r * ld + a] * X[(int64_t)r * ld + b];
+          const double d = rsum(s);
+          for (int r = t; r < rows; r += T) X[(int64_t)r * ld + b] -= d * X[(int64_t)r * ld + a];
+        }
+      }
+      double s2 = 0.0;
+      for (int r = t; r < rows; r += T) {
+        double v = X[(int64_t)r * ld + b];
+        s2 += v * v;
+      }
+      const double n2 = sqrt(rsum(s2));
+      const double inv = n2 > 0.0 ? 1.0 / n2 : 0.0;
+      for (int r = t; r < rows; r += T) X[(int64_t)r * ld + b] *= inv;
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------
+// S0: Y = L X, column-major blocks
+// ------------------------------------------------------------------------------------
+__global__ void k_stencil_cols(int64_t n, int per_point, double c0, double c1, double c2, const double* coef,
+                               const double* __restrict__ X, int64_t ldx, double* __restrict__ Y, int64_t ldy) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = blockIdx.y;
+  if (r >= n) return;
+  const double* x = X + (int64_t)c * ldx;
+  const int64_t rm = r == 0 ? n - 1 : r - 1;
+  const int64_t rp = r == n - 1 ? 0 : r + 1;
+  double cm = c0, cz = c1, cp = c2;
+  if (per_point) {
+    cm = coef[r];
+    cz = coef[n + r];
+    cp = coef[2 * n + r];
+  }
+  Y[(int64_t)c * ldy + r] = cm * x[rm] + cz * x[r] + cp * x[rp];
+}
+
+void launch_stencil_cols(int64_t n, int per_point, const double* c3, const double* coef, const double* X,
+                         int64_t ldx, double* Y, int64_t ldy, int ncols, hipStream_t st) {
+  if (n <= 0 || ncols <= 0) return;
+  dim3 grid((unsigned)((n + 255) / 256), (unsigned)ncols);
+  double a = per_point ? 0.0 : c3[0], b = per_point ? 0.0 : c3[1], c = per_point ? 0.0 : c3[2];
+  hipLaunchKernelGGL(k_stencil_cols, grid, dim3(256), 0, st, n, per_point, a, b, c, coef, X, ldx, Y, ldy);
+}
+
+__global__ void k_add_column(int64_t n, const double* __restrict__ G, int64_t ldG, const double* __restrict__ add,
+                             double* __restrict__ Gh, int64_t ldGh) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = blockIdx.y;
+  if (r >= n) return;
+  Gh[(int64_t)c * ldGh + r] = G[(int64_t)c * ldG + r] + (add ? add[r] : 0.0);
+}
+
+void launch_add_column(int64_t n, int s, const double* G, int64_t ldG, const double* add, double* Gh,
+                       int64_t ldGh, hipStream_t st) {
+  dim3 grid((unsigned)((n + 255) / 256), (unsigned)s);
+  hipLaunchKernelGGL(k_add_column, grid, dim3(256), 0, st, n, G, ldG, add, Gh, ldGh);
+}
+
+// ------------------------------------------------------------------------------------
+// Block orthogonalisation: projection partials  S_i = V_i^T X  (i < nb)
+//   pass 0, MODE_ARNOLDI: X = L V_j with V_j = TSQR(pass-2 buffers) formed on the fly;
+//                         slot-0 workgroups commit V_j to the basis
+//   pass 0, MODE_GIVEN:   X = columns [j*bw, j*bw+bw) of the given matrix
+//   pass 1:               X = Q1 of the pass-0 TSQR, formed on the fly
+// Grid: x = nb*Cp (slot, chunk), y = problem.  The last workgroup of a slot reduces the
+// Cp partials into S[pass][slot].
+// ------------------------------------------------------------------------------------
+template <typename TS>
+__global__ __launch_bounds__(256) void k_block_proj(ProbDev* probs, int j, int nb, int pass, int mode) {
+  const ProbDev& p = probs[blockIdx.y];
+  if (!p.active || j >= p.l) return;
+  const int bw = p.bw;
+  const int slot = blockIdx.x / p.Cp;
+  const int c = blockIdx.x % p.Cp;
+  if (slot >= nb) return;
+  const int64_t n = p.n;
+  const int64_t r0 = (int64_t)c * p.rows_p;
+  if (r0 >= n) return;
+  const int64_t r1 = r0 + p.rows_p < n ? r0 + p.rows_p : n;
+  const int rows = (int)(r1 - r0);
+  const int ld = bw + 1;
+  const int t = threadIdx.x;
+  extern __shared__ double smem[];
+  double* Xs = smem;                                // rows_p * ld
+  double* Vh = Xs + (int64_t)p.rows_p * ld;         // (rows_p + 2) * ld : V_j with halo, or V_slot
+  double* red = Vh + (int64_t)(p.rows_p + 2) * ld;  // 256 * ... reduction scratch
+  __shared__ int is_last;
+  TS* V = basis_ptr<TS>(p);
+  const int64_t blk = n * bw;
+  const bool arn0 = (mode == MODE_ARNOLDI && pass == 0);
+
+  if (arn0) {
+    // V_j rows r0-1 .. r1 (periodic), from the TSQR that produced block j
+    const int tot = (rows + 2) * bw;
+    for (int e = t; e < tot; e += blockDim.x) {
+      const int rr = e / bw, col = e % bw;
+      int64_t g = r0 - 1 + rr;
+      if (g < 0) g += n;
+      if (g >= n) g -= n;
+      const double v = tsqr_entry(p, p.Qloc2, p.Qs2, g, col);
+      Vh[rr * ld + col] = v;
+      if (slot == 0 && rr >= 1 && rr <= rows) V[(int64_t)j * blk + (r0 + rr - 1) * bw + col] = (TS)v;
+    }
+    __syncthreads();
+    for (int e = t; e < rows * bw; e += blockDim.x) {
+      const int rr = e / bw, col = e % bw;
+      double cm, cz, cp;
+      stencil_coefs(p, r0 + rr, cm, cz, cp);
+      Xs[rr * ld + col] = cm * Vh[rr * ld + col] + cz * Vh[(rr + 1) * ld + col] + cp * Vh[(rr + 2) * ld + col];
+    }
+  } else if (pass == 0) {  // MODE_GIVEN
+    for (int e = t; e < rows * bw; e += blockDim.x) {
+      const int rr = e / bw, col = e % bw;
+      const int gc = j * bw + col;
+      Xs[rr * ld + col] = gc < p.m ? p.Xg[(int64_t)gc * p.ldXg + r0 + rr] : 0.0;
+    }
+  } else {
+    for (int e = t; e < rows * bw; e += blockDim.x) {
+      const int rr = e / bw, col = e % bw;
+      Xs[rr * ld + col] = tsqr_entry(p, p.Qloc1, p.Qs1, r0 + rr, col);
+    }
+  }
+  // V_slot chunk (rows r0..r1) into Vh rows 1..rows unless it already is there
+  const bool have = arn0 && slot == j;
+  if (!have) {
+    __syncthreads();
+    for (int e = t; e < rows * bw; e += blockDim.x) {
+      const int rr = e / bw, col = e % bw;
+      Vh[(rr + 1) * ld + col] = (double)V[(int64_t)slot * blk + (r0 + rr) * bw + col];
+    }
+  }
+  __syncthreads();
+
+  // partial[a][b] = sum_r V[r][a] X[r][b]
+  const int nout = bw * bw;
+  double* part = p.Part + (int64_t)pass * p.Cp * p.nbmax * nout;  // capacity checked on host
+  double* mine = part + ((int64_t)slot * p.Cp + c) * nout;
+  if (nout <= 256) {
+    const int G = 256 / nout;
+    const int o = t % nout, g = t / nout;
+    double acc = 0.0;
+    if (g < G) {
+      const int a = o / bw, b = o % bw;
+      for (int rr = g; rr < rows; rr += G) acc += Vh[(rr + 1) * ld + a] * Xs[rr * ld + b];
+    }
+    __syncthreads();
+    if (g < G) red[g * nout + o] = acc;
+    __syncthreads();
+    if (t < nout) {
+      double s = 0.0;
+      for (int gg = 0; gg < G; ++gg) s += red[gg * nout + t];
+      mine[t] = s;
+    }
+  } else {
+    for (int o = t; o < nout; o += blockDim.x) {
+      const int a = o / bw, b = o % bw;
+      double acc = 0.0;
+      for (int rr = 0; rr < rows; ++rr) acc += Vh[(rr + 1) * ld + a] * Xs[rr * ld + b];
+      mine[o] = acc;
+    }
+  }
+  // last workgroup of this slot reduces the Cp partials
+  __threadfence();
+  __syncthreads();
+  if (t == 0) {
+    unsigned* cnt = p.cnt + pass * p.nbmax + slot;
+    const unsigned old = atomicAdd(cnt, 1u);
+    is_last = (old == (unsigned)(p.Cp - 1));
+  }
+  __syncthreads();
+  if (is_last) {
+    __threadfence();
+    double* Sout = p.S + (int64_t)pass * p.nbmax * nout + (int64_t)slot * nout;
+    const double* ps = part + (int64_t)slot * p.Cp * nout;
+    for (int o = t; o < nout; o += blockDim.x) {
+      double s = 0.0;
+      for (int cc = 0; cc < p.Cp; ++cc) s += __builtin_nontemporal_load(ps + (int64_t)cc * nout + o);
+      Sout[o] = s;
+    }
+    if (t == 0) atomicExch(p.cnt + pass * p.nbmax + slot, 0u);
+  }
+}
+
+// ------------------------------------------------------------------------------------
+// Block orthogonalisation: update + local QR + TSQR combine.
+//   X chunk (as in k_block_proj; MODE_INIT: X = [U | x]) minus sum_i V_i S[pass][i],
+//   then MGS2 of the chunk -> Qloc_pass, Rloc[u]; the last workgroup QR-factorises the
+//   stacked Rloc -> Qs_pass, Rf[pass] and (second pass) writes the Hessenberg column.
+// Grid: x = Cu, y = problem.  One wave per workgroup.
+// ------------------------------------------------------------------------------------
+template <typename TS>
+__global__ __launch_bounds__(64) void k_block_update(ProbDev* probs, int j, int nb, int pass, int mode) {
+  const ProbDev& p = probs[blockIdx.y];
+  if (!p.active || (mode != MODE_INIT && j >= p.l)) return;
+  const int bw = p.bw;
+  const int u = blockIdx.x;
+  if (u >= p.Cu) return;
+  const int64_t n = p.n;
+  const int64_t r0 = (int64_t)u * p.rows_u;
+  const int64_t r1 = (u == p.Cu - 1) ? n : r0 + p.rows_u;
+  const int rows = (int)(r1 - r0);
+  const int ld = bw + 1;
+  const int t = threadIdx.x;
+  extern __shared__ double smem[];
+  // X region holds the chunk (< 2*rows_u rows) and later the stacked R factors (Cu*bw rows)
+  const int64_t xs_cap = (int64_t)ld * ((int64_t)2 * p.rows_u > (int64_t)p.Cu * bw ? (int64_t)2 * p.rows_u
+                                                                                  : (int64_t)p.Cu * bw);
+  double* X = smem;
+  double* Ss = X + xs_cap;                           // bw*bw
+  double* Rl = Ss + bw * bw;                         // bw*bw
+  __shared__ int is_last;
+  TS* V = basis_ptr<TS>(p);
+  const int64_t blk = n * bw;
+
+  // 1. X chunk
+  if (mode == MODE_INIT) {
+    for (int e = t; e < rows * bw; e += 64) {
+      const int rr = e / bw, col = e % bw;
+      const int64_t g = r0 + rr;
+      X[rr * ld + col] = col < p.m ? p.U[(int64_t)col * n + g] : p.x[g];
+    }
+  } else if (pass == 0 && mode == MODE_ARNOLDI) {
+    for (int e = t; e < rows * bw; e += 64) {
+      const int rr = e / bw, col = e % bw;
+      const int64_t g = r0 + rr;
+      const int64_t gm = g == 0 ? n - 1 : g - 1, gp = g == n - 1 ? 0 : g + 1;
+      double cm, cz, cp;
+      stencil_coefs(p, g, cm, cz, cp);
+      const TS* vj = V + (int64_t)j * blk;
+      X[rr * ld + col] = cm * (double)vj[gm * bw + col] + cz * (double)vj[g * bw + col] + cp * (double)vj[gp * bw + col];
+    }
+  } else if (pass == 0) {  // MODE_GIVEN
+    for (int e = t; e < rows * bw; e += 64) {
+      const int rr = e / bw, col = e % bw;
+      const int gc = j * bw + col;
+      X[rr * ld + col] = gc < p.m ? p.Xg[(int64_t)gc * p.ldXg + r0 + rr] : 0.0;
+    }
+  } else {
+    for (int e = t; e < rows * bw; e += 64) {
+      const int rr = e / bw, col = e % bw;
+      X[rr * ld + col] = tsqr_entry(p, p.Qloc1, p.Qs1, r0 + rr, col);
+    }
+  }
+  __syncthreads();
+  // reference column norms of the chunk before the block projections
+  double* Rn = Rl + bw * bw;                         // bw: chunk reference norms, then global
+  for (int b = 0; b < bw; ++b) {
+    double s0 = 0.0;
+    for (int rr = t; rr < rows; rr += 64) s0 += X[rr * ld + b] * X[rr * ld + b];
+    s0 = wave_sum(s0);
+    if (t == 0) {
+      Rn[b] = sqrt(s0);
+      p.Cn[(int64_t)u * bw + b] = s0;
+    }
+  }
+  __syncthreads();
+  // 2. subtract projections
+  const int nout = bw * bw;
+  if (mode != MODE_INIT) {
+    const double* Sp = p.S + (int64_t)pass * p.nbmax * nout;
+    for (int i = 0; i < nb; ++i) {
+      for (int o = t; o < nout; o += 64) Ss[o] = Sp[(int64_t)i * nout + o];
+      __syncthreads();
+      const TS* vi = V + (int64_t)i * blk;
+      for (int rr = t; rr < rows; rr += 64) {
+        const TS* vrow = vi + (r0 + rr) * bw;
+        for (int b = 0; b < bw; ++b) {
+          double acc = X[rr * ld + b];
+          for (int a = 0; a < bw; ++a) acc -= (double)vrow[a] * Ss[a * bw + b];
+          X[rr * ld + b] = acc;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  // 3. local QR
+  for (int o = t; o < nout; o += 64) Rl[o] = 0.0;
+  __syncthreads();
+  // replacement directions must differ between blocks, passes and chunks
+  const uint64_t seed = ((uint64_t)(j + 1) * 1000003ull + (uint64_t)pass * 7919ull + (uint64_t)mode * 104729ull) *
+                            0x100000001B3ull + (uint64_t)r0;
+  mgs2_qr<false>(X, rows, ld, bw, Rl, seed, nullptr, Rn, 0);
+  __syncthreads();
+  double* Qloc = pass == 0 ? p.Qloc1 : p.Qloc2;
+  for (int e = t; e < rows * bw; e += 64) {
+    const int rr = e / bw, col = e % bw;
+    Qloc[(r0 + rr) * bw + col] = X[rr * ld + col];
+  }
+  for (int o = t; o < nout; o += 64) p.Rloc[(int64_t)u * nout + o] = Rl[o];
+  // 4. combine
+  __threadfence();
+  __syncthreads();
+  if (t == 0) {
+    unsigned* cnt = p.cnt + 2 * p.nbmax;
+    const unsigned old = atomicAdd(cnt, 1u);
+    is_last = (old == (unsigned)(p.Cu - 1));
+  }
+  __syncthreads();
+  if (!is_last) return;
+  __threadfence();
+  double* Qs = pass == 0 ? p.Qs1 : p.Qs2;
+  const int srows = p.Cu * bw;
+  for (int e = t; e < srows * bw; e += 64) {
+    const int rr = e / bw, col = e % bw;
+    X[rr * ld + col] = __builtin_nontemporal_load(p.Rloc + e);
+  }
+  for (int o = t; o < nout; o += 64) Rl[o] = 0.0;
+  for (int b = t; b < bw; b += 64) {
+    double s0 = 0.0;
+    for (int uu = 0; uu < p.Cu; ++uu) s0 += __builtin_nontemporal_load(p.Cn + (int64_t)uu * bw + b);
+    Rn[b] = sqrt(s0);
+  }
+  __syncthreads();
+  mgs2_qr<false>(X, srows, ld, bw, Rl, seed ^ 0x5bd1e995ull, nullptr, Rn, bw);
+  __syncthreads();
+  for (int e = t; e < srows * bw; e += 64) {
+    const int rr = e / bw, col = e % bw;
+    Qs[e] = X[rr * ld + col];
+  }
+  double* Rout = p.Rf + (mode == MODE_INIT ? 2 : pass) * nout;
+  for (int o = t; o < nout; o += 64) Rout[o] = Rl[o];
+  if (mode != MODE_INIT && pass == 1) {
+    // W = V (S1 + S2 Rf1) + Q2 (Rf2 Rf1): column block j of H (or of R in MODE_GIVEN)
+    const double* R1 = p.Rf;
+    const double* S1 = p.S;
+    const double* S2 = p.S + (int64_t)p.nbmax * nout;
+    // rows below the new subdiagonal block of this column block are zero
+    const int64_t r_lo = (int64_t)(nb + 1) * bw;
+    for (int64_t e = t; e < (p.ldH - r_lo) * bw; e += 64) {
+      const int64_t rr = r_lo + e / bw, b = e % bw;
+      p.H[rr + p.ldH * (int64_t)(j * bw + b)] = 0.0;
+    }
+    for (int e = t; e < (nb + 1) * nout; e += 64) {
+      const int i = e / nout, o = e % nout, a = o / bw, b = o % bw;
+      double v = 0.0;
+      if (i < nb) {
+        v = S1[(int64_t)i * nout + o];
+        for (int k = 0; k < bw; ++k) v += S2[(int64_t)i * nout + a * bw + k] * R1[k * bw + b];
+      } else {
+        for (int k = 0; k < bw; ++k) v += Rl[a * bw + k] * R1[k * bw + b];
+      }
+      p.H[(int64_t)(i * bw + a) + p.ldH * (int64_t)(j * bw + b)] = v;
+    }
+  }
+  if (t == 0) atomicExch(p.cnt + 2 * p.nbmax, 0u);
+}
+
+// V_j = Qloc2 . Qs2 committed to basis block j
+template <typename TS>
+__global__ void k_block_commit(ProbDev* probs, int j) {
+  const ProbDev& p = probs[blockIdx.y];
+  if (!p.active) return;
+  const int bw = p.bw;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= p.n * bw) return;
+  const int64_t r = e / bw;
+  const int col = (int)(e % bw);
+  basis_ptr<TS>(p)[(int64_t)j * p.n * bw + e] = (TS)tsqr_entry(p, p.Qloc2, p.Qs2, r, col);
+}
+
+void launch_block_proj(ProbDev* d, int nprob, int grid_x, size_t smem, int j, int nb, int pass, int mode,
+                       int mixed, hipStream_t st) {
+  if (grid_x <= 0 || nprob <= 0 || nb <= 0) return;
+  dim3 grid((unsigned)grid_x, (unsigned)nprob);
+  if (mixed)
+    hipLaunchKernelGGL(k_block_proj<float>, grid, dim3(256), smem, st, d, j, nb, pass, mode);
+  else
+    hipLaunchKernelGGL(k_block_proj<double>, grid, dim3(256), smem, st, d, j, nb, pass, mode);
+}
+
+void launch_block_update(ProbDev* d, int nprob, int grid_x, size_t smem, int j, int nb, int pass, int mode,
+                         int mixed, hipStream_t st) {
+  if (grid_x <= 0 || nprob <= 0) return;
+  static bool attr_set = false;
+  if (!attr_set) {
+    // opt in to large dynamic LDS (gfx950 has 160 KiB per CU); a refusal leaves the
+    // 64 KiB default, which the host-side geometry check then enforces
+    if (hipFuncSetAttribute((const void*)k_block_update<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            kUpdateLdsMax) != hipSuccess)
+      (void)hipGetLastError();
+    if (hipFuncSetAttribute((const void*)k_block_update<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            kUpdateLdsMax) != hipSuccess)
+      (void)hipGetLastError();
+    attr_set = true;
+  }
+  dim3 grid((unsigned)grid_x, (unsigned)nprob);
+  if (mixed)
+    hipLaunchKernelGGL(k_block_update<float>, grid, dim3(64), smem, st, d, j, nb, pass, mode);
+  else
+    hipLaunchKernelGGL(k_block_update<double>, grid, dim3(64), smem, st, d, j, nb, pass, mode);
+}
+
+void launch_block_commit(ProbDev* d, int nprob, int grid_x, int j, int mixed, hipStream_t st) {
+  if (grid_x <= 0 || nprob <= 0) return;
+  dim3 grid((unsigned)grid_x, (unsigned)nprob);
+  if (mixed)
+    hipLaunchKernelGGL(k_block_commit<float>, grid, dim3(256), 0, st, d, j);
+  else
+    hipLaunchKernelGGL(k_block_commit<double>, grid, dim3(256), 0, st, d, j);
+}
+
+// ------------------------------------------------------------------------------------
+// S6: exponential of the projected, source-augmented matrix
+//   Ht = [[H_l, E_1 R0[:, :m] Pi], [0, kscale * D]],  b = [R0[:, m] (state) ; 0 ; w(tau)]
+// Taylor polynomial of degree 16 (Paterson-Stockmeyer with A^2, A^3, A^4) on
+// A = (delta / 2^s) Ht, then s squarings; y = exp(delta Ht) b.
+// ------------------------------------------------------------------------------------
+__global__ void k_build_aug(ExpmDev* E) {
+  const ExpmDev& e = E[blockIdx.y];
+  if (!e.active) return;
+  const int N = e.N;
+  const int64_t NN = (int64_t)N * N;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int lbw = e.lbw, bw = e.bw;
+  if (idx < NN) {
+    const int r = (int)(idx % N), c = (int)(idx / N);
+    double v = 0.0;
+    if (r < lbw && c < lbw) {
+      v = e.H[(int64_t)r + e.ldH * c];
+    } else if (r < bw && c >= lbw) {
+      const int k = c - lbw;
+      for (int cc = 0; cc < e.m; ++cc) v += e.R0[r * bw + cc] * e.Pi[cc + (int64_t)e.ldPi * k];
+    } else if (r >= lbw && c >= lbw) {
+      v = e.kscale * e.Dm[(r - lbw) * e.qmax + (c - lbw)];
+    }
+    e.Ht[idx] = v;
+  }
+  if (idx < N) {
+    const int r = (int)idx;
+    double v = 0.0;
+    if (r < bw) v = e.with_x ? e.R0[r * bw + e.m] : 0.0;
+    else if (r >= lbw) v = e.w[r - lbw];
+    e.b[r] = v;
+  }
+}
+
+void launch_build_aug(ExpmDev* e, int nprob, int64_t maxNN, hipStream_t st) {
+  dim3 grid((unsigned)((maxNN + 255) / 256), (unsigned)nprob);
+  hipLaunchKernelGGL(k_build_aug, grid, dim3(256), 0, st, e);
+}
+
+// out[p] = ||Ht||_1 (largest absolute column sum)
+__global__ __launch_bounds__(256) void k_norm1(ExpmDev* E, double* out) {
+  const ExpmDev& e = E[blockIdx.x];
+  __shared__ double red[16];
+  if (!e.active) {
+    if (threadIdx.x == 0) out[blockIdx.x] = 0.0;
+    return;
+  }
+  const int N = e.N;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  double mx = 0.0;
+  for (int c = w; c < N; c += 4) {
+    double s = 0.0;
+    for (int r = lane; r < N; r += 64) s += fabs(e.Ht[(int64_t)r + (int64_t)N * c]);
+    s = wave_sum(s);
+    mx = fmax(mx, s);
+  }
+  mx = block_max(mx, red);
+  if (threadIdx.x == 0) out[blockIdx.x] = mx;
+}
+
+void launch_norm1(ExpmDev* e, double* out, int nprob, hipStream_t st) {
+  hipLaunchKernelGGL(k_norm1, dim3((unsigned)nprob), dim3(256), 0, st, e, out);
+}
+
+__device__ __constant__ double c_taylor[17] = {
+    1.0, 1.0, 1.0 / 2, 1.0 / 6, 1.0 / 24, 1.0 / 120, 1.0 / 720, 1.0 / 5040, 1.0 / 40320, 1.0 / 362880,
+    1.0 / 3628800, 1.0 / 39916800, 1.0 / 479001600, 1.0 / 6227020800.0, 1.0 / 87178291200.0,
+    1.0 / 1307674368000.0, 1.0 / 20922789888000.0};
+
+// A = alpha Ht (op 0) or P = c16 A4 + c15 A3 + c14 A2 + c13 A + c12 I (op 1)
+__global__ void k_elementwise(ExpmDev* E, int op) {
+  const ExpmDev& e = E[blockIdx.y];
+  if (!e.active) return;
+  const int N = e.N;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)N * N) return;
+  if (op == 0) {
+    e.A[idx] = e.alpha * e.Ht[idx];
+  } else {
+    const int r = (int)(idx % N), c = (int)(idx / N);
+    e.P[idx] = c_taylor[16] * e.A4[idx] + c_taylor[15] * e.A3[idx] + c_taylor[14] * e.A2[idx] +
+               c_taylor[13] * e.A[idx] + (r == c ? c_taylor[12] : 0.0);
+  }
+}
+
+void launch_elementwise(ExpmDev* e, int op, int nprob, int64_t maxNN, hipStream_t st) {
+  dim3 grid((unsigned)((maxNN + 255) / 256), (unsigned)nprob);
+  hipLaunchKernelGGL(k_elementwise, grid, dim3(256), 0, st, e, op);
+}
+
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+// C = A B (+ Taylor epilogue), 32 x 32 tile per workgroup, 4 waves of 16 x 16 MFMA f64.
+//   op 0: A2 = A A      op 1: A3 = A2 A      op 2: A4 = A2 A2
+//   op 3: T = P A4 + c11 A3 + c10 A2 + c9 A + c8 I
+//   op 4: P = T A4 + c7 A3 + c6 A2 + c5 A + c4 I
+//   op 5: T = P A4 + c3 A3 + c2 A2 + c1 A + c0 I
+//   op 6: squaring number k: (k even) P = T T, (k odd) T = P P; skipped when k >= nsq
+__global__ __launch_bounds__(256) void k_gemm(ExpmDev* E, int op, int k) {
+  const ExpmDev& e = E[blockIdx.y];
+  if (!e.active) return;
+  if (op == 6 && k >= e.nsq) return;
+  const int N = e.N;
+  const int nt = (N + 31) / 32;
+  const int tile = blockIdx.x;
+  if (tile >= nt * nt) return;
+  const int i0 = 32 * (tile % nt), j0 = 32 * (tile / nt);
+  const double *A, *B;
+  double* C;
+  int ep = -1;  // epilogue base index (c[ep+3] A3 + c[ep+2] A2 + c[ep+1] A + c[ep] I)
+  switch (op) {
+    case 0: A = e.A; B = e.A; C = e.A2; break;
+    case 1: A = e.A2; B = e.A; C = e.A3; break;
+    case 2: A = e.A2; B = e.A2; C = e.A4; break;
+    case 3: A = e.P; B = e.A4; C = e.T; ep = 8; break;
+    case 4: A = e.T; B = e.A4; C = e.P; ep = 4; break;
+    case 5: A = e.P; B = e.A4; C = e.T; ep = 0; break;
+    default:
+      if (k & 1) { A = e.P; B = e.P; C = e.T; }
+      else { A = e.T; B = e.T; C = e.P; }
+      break;
+  }
+  __shared__ double As[16][33];
+  __shared__ double Bs[32][17];
+  const int t = threadIdx.x;
+  const int lane = t & 63, w = t >> 6;
+  const int wi = w & 1, wj = w >> 1;
+  dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+  for (int kk = 0; kk < N; kk += 16) {
+    for (int h = 0; h < 2; ++h) {
+      const int q = t + 256 * h;
+      {
+        const int kq = q / 32, iq = q % 32;
+        const int gi = i0 + iq, gk = kk + kq;
+        As[kq][iq] = (gi < N && gk < N) ? A[(int64_t)gi + (int64_t)N * gk] : 0.0;
+      }
+      {
+        const int jq = q / 16, kq = q % 16;
+        const int gj = j0 + jq, gk = kk + kq;
+        Bs[jq][kq] = (gj < N && gk < N) ? B[(int64_t)gk + (int64_t)N * gj] : 0.0;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k4 = 0; k4 < 16; k4 += 4) {
+      const double a = As[k4 + (lane >> 4)][wi * 16 + (lane & 15)];
+      const double b = Bs[wj * 16 + (lane & 15)][k4 + (lane >> 4)];
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    // accumulator layout of the f64 16x16x4 MFMA: row = lane/16 + 4 v, column = lane % 16
+    const int i = i0 + wi * 16 + (lane >> 4) + 4 * v;
+    const int j = j0 + wj * 16 + (lane & 15);
+    if (i < N && j < N) {
+      const int64_t o = (int64_t)i + (int64_t)N * j;
+      double val = acc[v];
+      if (ep >= 0)
+        val += c_taylor[ep + 3] * e.A3[o] + c_taylor[ep + 2] * e.A2[o] + c_taylor[ep + 1] * e.A[o] +
+               (i == j ? c_taylor[ep] : 0.0);
+      C[o] = val;
+    }
+  }
+}
+
+void launch_gemm(ExpmDev* e, int op, int k, int nprob, int tiles_max, hipStream_t st) {
+  dim3 grid((unsigned)tiles_max, (unsigned)nprob);
+  hipLaunchKernelGGL(k_gemm, grid, dim3(256), 0, st, e, op, k);
+}
+
+// y = E b with E = T (nsq even) or P (nsq odd); out[0] = |H_{l+1,l} y_last|, out[1] = |y[0:lbw]|
+__global__ __launch_bounds__(256) void k_expm_apply(ExpmDev* E) {
+  const ExpmDev& e = E[blockIdx.x];
+  if (!e.active) return;
+  extern __shared__ double sm[];
+  double* bs = sm;              // N
+  double* red = sm + e.N;       // 16
+  const int N = e.N;
+  const double* M = (e.nsq & 1) ? e.P : e.T;
+  for (int c = threadIdx.x; c < N; c += blockDim.x) bs[c] = e.b[c];
+  __syncthreads();
+  double yn = 0.0;
+  for (int r = threadIdx.x; r < N; r += blockDim.x) {
+    double acc = 0.0;
+    for (int c = 0; c < N; ++c) acc += M[(int64_t)r + (int64_t)N * c] * bs[c];
+    e.y[r] = acc;
+    if (r < e.lbw) yn += acc * acc;
+  }
+  yn = block_sum(yn, red);
+  __threadfence_block();
+  __syncthreads();
+  // residual of the Arnoldi relation at tau = delta: H_{l+1,l} y[(l-1)bw : l bw]
+  double rr = 0.0;
+  const int bw = e.bw, l = e.l;
+  if ((int)threadIdx.x < bw) {
+    const int a = threadIdx.x;
+    double s = 0.0;
+    for (int c = 0; c < bw; ++c)
+      s += e.H[(int64_t)(l * bw + a) + e.ldH * (int64_t)((l - 1) * bw + c)] * e.y[(l - 1) * bw + c];
+    rr = s * s;
+  }
+  rr = block_sum(rr, red);
+  if (threadIdx.x == 0) {
+    e.out[0] = sqrt(rr);
+    e.out[1] = sqrt(yn);
+  }
+}
+
+void launch_expm_apply(ExpmDev* e, int nprob, int maxN, hipStream_t st) {
+  size_t smem = sizeof(double) * ((size_t)maxN + 16);
+  hipLaunchKernelGGL(k_expm_apply, dim3((unsigned)nprob), dim3(256), smem, st, e);
+}
+
+// ------------------------------------------------------------------------------------
+// S7: x = V_{0..l-1} y[0:l*bw]  (and the output column)
+// ------------------------------------------------------------------------------------
+template <typename TS>
+__global__ __launch_bounds__(256) void k_project(ProbDev* probs, ExpmDev* E) {
+  const ProbDev& p = probs[blockIdx.y];
+  if (!p.active || !p.proj) return;
+  const ExpmDev& e = E[blockIdx.y];
+  extern __shared__ double ys[];
+  const int lbw = p.l * p.bw;
+  for (int c = threadIdx.x; c < lbw; c += blockDim.x) ys[c] = e.y[c];
+  __syncthreads();
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= p.n) return;
+  const int bw = p.bw;
+  const TS* V = basis_ptr<TS>(p);
+  const int64_t blk = p.n * bw;
+  double acc = 0.0;
+  for (int i = 0; i < p.l; ++i) {
+    const TS* row = V + (int64_t)i * blk + r * bw;
+    for (int c = 0; c < bw; ++c) acc += (double)row[c] * ys[i * bw + c];
+  }
+  p.xstate[r] = acc;
+  if (p.outcol) p.outcol[r] = acc;
+}
+
+void launch_project(ProbDev* d, ExpmDev* e, int nprob, int64_t maxn, int max_lbw, int mixed, hipStream_t st) {
+  dim3 grid((unsigned)((maxn + 255) / 256), (unsigned)nprob);
+  size_t smem = sizeof(double) * (size_t)max_lbw + 16;
+  if (mixed)
+    hipLaunchKernelGGL(k_project<float>, grid, dim3(256), smem, st, d, e);
+  else
+    hipLaunchKernelGGL(k_project<double>, grid, dim3(256), smem, st, d, e);
+}
+
+// ------------------------------------------------------------------------------------
+// Compression (S3, S4): singular values of the QR factor R of the samples, left vectors,
+// truncation is decided on the host, then U = Q W_m and the Chebyshev fit of C.
+// ------------------------------------------------------------------------------------
+__global__ void k_row_norms(const double* R, int64_t ldR, int rows, int cols, double* rn) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= rows) return;
+  double s = 0.0;
+  for (int c = 0; c < cols; ++c) {
+    const double v = R[(int64_t)i + ldR * c];
+    s += v * v;
+  }
+  rn[i] = sqrt(s);
+}
+
+void launch_row_norms(const double* R, int64_t ldR, int rows, int cols, double* rn, hipStream_t st) {
+  hipLaunchKernelGGL(k_row_norms, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, st, R, ldR, rows, cols, rn);
+}
+
+// One-sided (Hestenes) Jacobi on A = R[sel, 0:s]^T (s x r): A J has orthogonal columns.
+// Singular values are the column norms; J (r x r, column-major) holds the left singular
+// vectors of R[sel, :].  Round-robin ordering, one wave per pair, one workgroup.
+__global__ __launch_bounds__(256) void k_jacobi_svd(const double* R, int64_t ldR, const int* sel, int s, int r,
+                                                    double* A, double* J, double* sig, int* perm, int* info) {
+  __shared__ double red[16];
+  __shared__ double wmax[4];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  for (int64_t e = t; e < (int64_t)s * r; e += blockDim.x) {
+    const int k = (int)(e % s), i = (int)(e / s);
+    A[e] = R[(int64_t)sel[i] + ldR * k];
+  }
+  for (int64_t e = t; e < (int64_t)r * r; e += blockDim.x) J[e] = ((e % r) == (e / r)) ? 1.0 : 0.0;
+  __syncthreads();
+  const int r2 = r + (r & 1);
+  int sweep = 0;
+  for (; sweep < 60 && r > 1; ++sweep) {
+    double off = 0.0;
+    for (int round = 0; round < r2 - 1; ++round) {
+      for (int pi = w; pi < r2 / 2; pi += 4) {
+        int pp, qq;
+        if (pi == 0) {
+          pp = 0;
+          qq = (round % (r2 - 1)) + 1;
+        } else {
+          pp = ((round + pi) % (r2 - 1)) + 1;
+          qq = ((round - pi + r2 - 1) % (r2 - 1)) + 1;
+        }
+        if (pp >= r || qq >= r) continue;
+        double* ap = A + (int64_t)pp * s;
+        double* aq = A + (int64_t)qq * s;
+        double al = 0.0, be = 0.0, ga = 0.0;
+        for (int k = lane; k < s; k += 64) {
+          al += ap[k] * ap[k];
+          be += aq[k] * aq[k];
+          ga += ap[k] * aq[k];
+        }
+        al = wave_sum(al);
+        be = wave_sum(be);
+        ga = wave_sum(ga);
+        if (ga == 0.0 || al == 0.0 || be == 0.0) continue;
+        const double rel = fabs(ga) / sqrt(al * be);
+        off = fmax(off, rel);
+        if (rel < 1e-16) continue;
+        const double zeta = (be - al) / (2.0 * ga);
+        const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+        const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
+        for (int k = lane; k < s; k += 64) {
+          const double x = ap[k], y = aq[k];
+          ap[k] = cs * x - sn * y;
+          aq[k] = sn * x + cs * y;
+        }
+        double* jp = J + (int64_t)pp * r;
+        double* jq = J + (int64_t)qq * r;
+        for (int k = lane; k < r; k += 64) {
+          const double x = jp[k], y = jq[k];
+          jp[k] = cs * x - sn * y;
+          jq[k] = sn * x + cs * y;
+        }
+      }
+      __threadfence_block();
+      __syncthreads();
+    }
+    if (lane == 0) wmax[w] = off;
+    __syncthreads();
+    const double o = fmax(fmax(wmax[0], wmax[1]), fmax(wmax[2], wmax[3]));
+    __syncthreads();
+    if (o < 1e-15) {
+      ++sweep;
+      break;
+    }
+  }
+  for (int i = w; i < r; i += 4) {
+    double q = 0.0;
+    for (int k = lane; k < s; k += 64) q += A[(int64_t)i * s + k] * A[(int64_t)i * s + k];
+    q = wave_sum(q);
+    if (lane == 0) sig[i] = sqrt(q);
+  }
+  __threadfence_block();
+  __syncthreads();
+  if (t == 0) {
+    for (int i = 0; i < r; ++i) perm[i] = i;
+    for (int i = 0; i < r; ++i) {  // selection sort, descending
+      int b = i;
+      for (int k = i + 1; k < r; ++k)
+        if (sig[perm[k]] > sig[perm[b]]) b = k;
+      const int tmp = perm[i];
+      perm[i] = perm[b];
+      perm[b] = tmp;
+    }
+    info[0] = sweep;
+  }
+  (void)red;
+}
+
+void launch_jacobi_svd(const double* R, int64_t ldR, const int* sel, int s, int r, double* A, double* J,
+                       double* sig, int* perm, int* info, hipStream_t st) {
+  hipLaunchKernelGGL(k_jacobi_svd, dim3(1), dim3(256), 0, st, R, ldR, sel, s, r, A, J, sig, perm, info);
+}
+
+// U[:, k] = sum_i Q[:, sel_i] J[i, perm_k], Q stored as blocks of n x bwc (row-major)
+__global__ void k_form_u(const double* Q, int bwc, int64_t n, const int* sel, int r, const double* J,
+                         const int* perm, int m, double* U, int64_t ldU) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n) return;
+  for (int k = 0; k < m; ++k) {
+    const double* jc = J + (int64_t)perm[k] * r;
+    double acc = 0.0;
+    for (int i = 0; i < r; ++i) {
+      const int col = sel[i];
+      acc += Q[(int64_t)(col / bwc) * n * bwc + g * bwc + (col % bwc)] * jc[i];
+    }
+    U[g + ldU * k] = acc;
+  }
+}
+
+void launch_form_u(const double* Q, int bwc, int64_t n, const int* sel, int r, const double* J, const int* perm,
+                   int m, double* U, int64_t ldU, hipStream_t st) {
+  hipLaunchKernelGGL(k_form_u, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, Q, bwc, n, sel, r, J, perm, m,
+                     U, ldU);
+}
+
+// Least-squares Chebyshev fit of the rows of C = (A J)[:, perm[0:m]]^T over the samples:
+// smallest q with relative residual <= fit_tol (q <= qcap); Pi (m x q, column-major).
+// work: qcap*s + qcap*qcap + m*qcap + m*s doubles.  info: [q, residual, capped].
+__global__ __launch_bounds__(256) void k_fit(const double* A, int s, const int* perm, int m, const double* ts,
+                                             double t0, double t1, int qcap, double fit_tol, double* Pi, int ldPi,
+                                             double* work, double* info) {
+  __shared__ double red[16];
+  __shared__ int qsel_s;
+  __shared__ double res_s;
+  const int t = threadIdx.x;
+  double* Tq = work;                              // s x qcap row-major
+  double* Rt = Tq + (int64_t)s * qcap;            // qcap x qcap
+  double* Ch = Rt + (int64_t)qcap * qcap;         // m x qcap
+  double* Em = Ch + (int64_t)m * qcap;            // m x s
+  double cn = 0.0;
+  for (int64_t e = t; e < (int64_t)m * s; e += blockDim.x) {
+    const int a = (int)(e / s), i = (int)(e % s);
+    const double v = A[(int64_t)perm[a] * s + i];
+    Em[e] = v;
+    cn += v * v;
+  }
+  cn = sqrt(block_sum(cn, red));
+  for (int i = t; i < s; i += blockDim.x) {
+    const double x = (2.0 * ts[i] - t0 - t1) / (t1 - t0);
+    double a = 1.0, b = x;
+    for (int k = 0; k < qcap; ++k) {
+      double v;
+      if (k == 0) v = 1.0;
+      else if (k == 1) v = x;
+      else {
+        v = 2.0 * x * b - a;
+        a = b;
+        b = v;
+      }
+      Tq[(int64_t)i * qcap + k] = v;
+    }
+  }
+  for (int e = t; e < qcap * qcap; e += blockDim.x) Rt[e] = 0.0;
+  __threadfence_block();
+  __syncthreads();
+  mgs2_qr<true>(Tq, s, qcap, qcap, Rt, 0x2545F491ull, red, nullptr, 0);
+  __threadfence_block();
+  __syncthreads();
+  for (int e = t; e < m * qcap; e += blockDim.x) {
+    const int a = e / qcap, k = e % qcap;
+    double acc = 0.0;
+    for (int i = 0; i < s; ++i) acc += Em[(int64_t)a * s + i] * Tq[(int64_t)i * qcap + k];
+    Ch[e] = acc;
+  }
+  __threadfence_block();
+  __syncthreads();
+  int qsel = qcap;
+  double res = 0.0;
+  for (int q = 1; q <= qcap; ++q) {
+    double ss = 0.0;
+    for (int64_t e = t; e < (int64_t)m * s; e += blockDim.x) {
+      const int a = (int)(e / s), i = (int)(e % s);
+      const double v = Em[e] - Ch[a * qcap + q - 1] * Tq[(int64_t)i * qcap + q - 1];
+      Em[e] = v;
+      ss += v * v;
+    }
+    res = cn > 0.0 ? sqrt(block_sum(ss, red)) / cn : 0.0;
+    if (res <= fit_tol) {
+      qsel = q;
+      break;
+    }
+  }
+  if (t == 0) {
+    qsel_s = qsel;
+    res_s = res;
+  }
+  __syncthreads();
+  qsel = qsel_s;
+  for (int a = t; a < m; a += blockDim.x) {
+    for (int k = qsel - 1; k >= 0; --k) {
+      double v = Ch[a * qcap + k];
+      for (int kk = k + 1; kk < qsel; ++kk) v -= Rt[k * qcap + kk] * Pi[a + (int64_t)ldPi * kk];
+      const double d = Rt[k * qcap + k];
+      Pi[a + (int64_t)ldPi * k] = d != 0.0 ? v / d : 0.0;
+    }
+  }
+  if (t == 0) {
+    info[0] = (double)qsel;
+    info[1] = res_s;
+    info[2] = (res_s > fit_tol) ? 1.0 : 0.0;
+  }
+}
+
+void launch_fit(const double* A, int s, const int* perm, int m, const double* ts, double t0, double t1, int qcap,
+                double fit_tol, double* Pi, int ldPi, double* work, double* info, hipStream_t st) {
+  hipLaunchKernelGGL(k_fit, dim3(1), dim3(256), 0, st, A, s, perm, m, ts, t0, t1, qcap, fit_tol, Pi, ldPi, work,
+                     info);
+}
+
+// ------------------------------------------------------------------------------------
+// S8 and utilities
+// ------------------------------------------------------------------------------------
+struct PtrList {
+  const double* v[64];
+};
+
+__global__ void k_superpose(const double* u0, PtrList vl, int P, int64_t n, int64_t ldv, double* u, int64_t ldu,
+                            int accumulate) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int k = blockIdx.y;
+  if (r >= n) return;
+  double acc = accumulate ? u[r + ldu * k] : u0[r];
+  for (int j = 0; j < P; ++j) acc += vl.v[j][r + ldv * k];
+  u[r + ldu * k] = acc;
+}
+
+void launch_superpose(const double* u0, const double* const* v, int P, int64_t n, int n_out, int64_t ldv, double* u,
+                      int64_t ldu, hipStream_t st) {
+  dim3 grid((unsigned)((n + 255) / 256), (unsigned)n_out);
+  for (int j0 = 0; j0 < P; j0 += 64) {
+    PtrList pl;
+    const int cnt = (P - j0) < 64 ? (P - j0) : 64;
+    for (int i = 0; i < cnt; ++i) pl.v[i] = v[j0 + i];
+    hipLaunchKernelGGL(k_superpose, grid, dim3(256), 0, st, u0, pl, cnt, n, ldv, u, ldu, j0 > 0 ? 1 : 0);
+  }
+}
+
+__global__ void k_check_finite(const double* x, int64_t n, int64_t ld, int* flag) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = blockIdx.y;
+  if (r >= n) return;
+  const double v = x[r + ld * c];
+  if (!isfinite(v)) atomicOr(flag, 1);
+}
+
+void launch_check_finite(const double* x, int64_t n, int cols, int64_t ld, int* flag, hipStream_t st) {
+  if (n <= 0 || cols <= 0) return;
+  dim3 grid((unsigned)((n + 255) / 256), (unsigned)cols);
+  hipLaunchKernelGGL(k_check_finite, grid, dim3(256), 0, st, x, n, ld, flag);
+}
+
+__global__ void k_fill(double* x, int64_t n, int64_t ld, double v) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = blockIdx.y;
+  if (r < n) x[r + ld * c] = v;
+}
+
+void launch_fill(double* x, int64_t n, int cols, int64_t ld, double v, hipStream_t st) {
+  if (n <= 0 || cols <= 0) return;
+  dim3 grid((unsigned)((n + 255) / 256), (unsigned)cols);
+  hipLaunchKernelGGL(k_fill, grid, dim3(256), 0, st, x, n, ld, v);
+}
+
+__global__ void k_copy(const double* a, double* b, int64_t n) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < n) b[r] = a[r];
+}
+
+void launch_copy(const double* a, double* b, int64_t n, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_copy, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a, b, n);
+}
+
+}  // namespace pe

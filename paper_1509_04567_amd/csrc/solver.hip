@@ -1,0 +1,1006 @@
+// Host orchestration and C ABI of the gfx950 Paraexp library.
+//
+// pe_solve_batch runs, for every window subproblem (paper Sec. 2.2, Fig. 2.1):
+//   S1  shifted samples G^ = G + (L u0) 1^T                          (eq. 2.6)
+//   S2-S3  block CGS2+TSQR factorisation G^ = Q R, one-sided Jacobi SVD of R,
+//          truncation to m columns: G^ ~= U C                          (eqs. 2.2-2.3)
+//   S4  least-squares Chebyshev fit of C in time: p(t) = Pi T(x(t))
+//   S5-S7  restarted block Arnoldi on the Krylov space of [U | x] (eq. 2.4), one
+//          restart cycle per time sub-step: the exponential of the projected matrix
+//          augmented with the polynomial source gives the state at the end of the
+//          sub-step; cycle ends are placed at output times and at the window end.
+// All problems of a batch advance together: every kernel launch serves the whole
+// batch, and the step-size decision of each problem is taken on the host from one
+// small read-back per trial.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/paraexp.h"
+#include "kernels.h"
+
+struct pe_ctx {
+  int device = 0;
+  std::string err;
+  char* arena = nullptr;
+  size_t arena_cap = 0;
+  char* pinned = nullptr;
+  size_t pinned_cap = 0;
+};
+
+static pe_status pe_fail(pe_ctx* ctx, pe_status st, const std::string& msg, hipError_t e = hipSuccess) {
+  if (ctx) {
+    ctx->err = msg;
+    if (e != hipSuccess) ctx->err += std::string(": ") + hipGetErrorString(e);
+  }
+  return st;
+}
+
+#define HCK(expr)                                                                     \
+  do {                                                                                \
+    hipError_t _e = (expr);                                                           \
+    if (_e != hipSuccess) return pe_fail(ctx, PE_ERR_DEVICE, #expr, _e);             \
+  } while (0)
+
+namespace {
+
+constexpr double kTaylorTheta = 0.78;  // ||A||_1 bound for the degree-16 Taylor polynomial
+constexpr int kMaxTrials = 6;
+constexpr double kSigmaFloor = 1e-12;  // relative singular values treated as zero
+constexpr int kRowsU = 64;
+
+// PARAEXP_TRACE=1 prints one line per restart trial to stderr;
+// PARAEXP_MAX_CYCLES=k stops a march after k cycles (outputs left unwritten, flagged).
+int env_int(const char* name, int dflt) {
+  const char* v = std::getenv(name);
+  return v ? std::atoi(v) : dflt;
+}
+
+// ---- workspace carving ----------------------------------------------------------
+struct Carver {
+  size_t off = 0;
+  template <typename T>
+  size_t take(size_t count) {
+    off = (off + 255) & ~(size_t)255;
+    size_t o = off;
+    off += count * sizeof(T);
+    return o;
+  }
+};
+
+pe_status ensure_arena(pe_ctx* ctx, size_t bytes) {
+  if (bytes <= ctx->arena_cap) return PE_OK;
+  if (ctx->arena) {
+    hipDeviceSynchronize();
+    hipFree(ctx->arena);
+    ctx->arena = nullptr;
+    ctx->arena_cap = 0;
+  }
+  size_t cap = bytes + bytes / 4 + (1 << 20);
+  hipError_t e = hipMalloc((void**)&ctx->arena, cap);
+  if (e != hipSuccess) return pe_fail(ctx, PE_ERR_OOM, "device workspace allocation failed", e);
+  ctx->arena_cap = cap;
+  return PE_OK;
+}
+
+pe_status ensure_pinned(pe_ctx* ctx, size_t bytes) {
+  if (bytes <= ctx->pinned_cap) return PE_OK;
+  if (ctx->pinned) hipHostFree(ctx->pinned);
+  ctx->pinned = nullptr;
+  ctx->pinned_cap = 0;
+  size_t cap = bytes + 4096;
+  hipError_t e = hipHostMalloc((void**)&ctx->pinned, cap);
+  if (e != hipSuccess) return pe_fail(ctx, PE_ERR_OOM, "pinned host allocation failed", e);
+  ctx->pinned_cap = cap;
+  return PE_OK;
+}
+
+// ---- geometry of the block kernels ------------------------------------------------
+int rows_p_for(int bw) { return bw <= 8 ? 256 : (bw <= 16 ? 128 : 64); }
+
+int rows_u_for(int64_t n, int bw) {
+  int ru = kRowsU;
+  while (true) {
+    const int64_t cu = std::max<int64_t>(1, n / ru);
+    const size_t comb = (size_t)cu * bw * (bw + 1) * 8;
+    const size_t xs = (size_t)2 * ru * (bw + 1) * 8;
+    if ((comb + 2048 <= (size_t)pe::kUpdateLdsMax - 4096 && xs + 2048 <= (size_t)pe::kUpdateLdsMax - 4096) ||
+        ru >= 4096)
+      return ru;
+    ru *= 2;
+  }
+}
+
+void set_geometry(ProbDev& d, int64_t n, int bw) {
+  d.bw = bw;
+  d.rows_u = rows_u_for(n, bw);
+  d.Cu = (int)std::max<int64_t>(1, n / d.rows_u);
+  d.rows_p = rows_p_for(bw);
+  d.Cp = (int)((n + d.rows_p - 1) / d.rows_p);
+}
+
+size_t proj_smem(int rows_p, int bw) {
+  const size_t ld = bw + 1;
+  return sizeof(double) * ((size_t)rows_p * ld + (size_t)(rows_p + 2) * ld + 256) + 64;
+}
+
+size_t update_smem(const ProbDev& d) {
+  const size_t ld = d.bw + 1;
+  const size_t xs = std::max((size_t)2 * d.rows_u * ld, (size_t)d.Cu * d.bw * ld);
+  return sizeof(double) * (xs + 2 * (size_t)d.bw * d.bw + (size_t)d.bw) + 64;
+}
+
+// capacities of the per-problem block workspace for block widths up to bwmax
+struct BlockCaps {
+  int64_t n;
+  int bwmax, nbmax;
+  size_t basis, qloc, rloc, rf, part, S, H, cnt;
+  int64_t ldH_rows, H_cols;
+};
+
+BlockCaps block_caps(int64_t n, int bwmax, int nbmax, int64_t H_rows, int64_t H_cols) {
+  BlockCaps c;
+  c.n = n;
+  c.bwmax = bwmax;
+  c.nbmax = nbmax;
+  size_t cu_bw2 = 0, cp_bw2 = 0;
+  for (int bw = 1; bw <= bwmax; ++bw) {
+    ProbDev d{};
+    set_geometry(d, n, bw);
+    cu_bw2 = std::max(cu_bw2, (size_t)d.Cu * bw * bw);
+    cp_bw2 = std::max(cp_bw2, (size_t)d.Cp * bw * bw);
+  }
+  c.basis = (size_t)nbmax * n * bwmax;
+  c.qloc = (size_t)n * bwmax;
+  c.rloc = cu_bw2;
+  c.rf = 3 * (size_t)bwmax * bwmax;
+  c.part = 2 * (size_t)nbmax * cp_bw2;
+  c.S = 2 * (size_t)nbmax * bwmax * bwmax;
+  c.H = (size_t)H_rows * H_cols;
+  c.cnt = 2 * (size_t)nbmax + 1;
+  c.ldH_rows = H_rows;
+  c.H_cols = H_cols;
+  return c;
+}
+
+struct BlockOffsets {
+  size_t V, Qloc1, Qloc2, Rloc, Cn, Qs1, Qs2, Rf, Part, S, H, cnt;
+};
+
+BlockOffsets carve_block(Carver& cv, const BlockCaps& c, bool mixed) {
+  BlockOffsets o;
+  o.V = mixed ? cv.take<float>(c.basis) : cv.take<double>(c.basis);
+  o.Qloc1 = cv.take<double>(c.qloc);
+  o.Qloc2 = cv.take<double>(c.qloc);
+  o.Rloc = cv.take<double>(c.rloc);
+  o.Cn = cv.take<double>(c.rloc);
+  o.Qs1 = cv.take<double>(c.rloc);
+  o.Qs2 = cv.take<double>(c.rloc);
+  o.Rf = cv.take<double>(c.rf);
+  o.Part = cv.take<double>(c.part);
+  o.S = cv.take<double>(c.S);
+  o.H = cv.take<double>(c.H);
+  o.cnt = cv.take<unsigned>(c.cnt);
+  return o;
+}
+
+void bind_block(ProbDev& d, char* base, const BlockOffsets& o, bool mixed, int nbmax) {
+  d.V = mixed ? nullptr : (double*)(base + o.V);
+  d.V32 = mixed ? (float*)(base + o.V) : nullptr;
+  d.mixed = mixed ? 1 : 0;
+  d.Qloc1 = (double*)(base + o.Qloc1);
+  d.Qloc2 = (double*)(base + o.Qloc2);
+  d.Rloc = (double*)(base + o.Rloc);
+  d.Cn = (double*)(base + o.Cn);
+  d.Qs1 = (double*)(base + o.Qs1);
+  d.Qs2 = (double*)(base + o.Qs2);
+  d.Rf = (double*)(base + o.Rf);
+  d.Part = (double*)(base + o.Part);
+  d.S = (double*)(base + o.S);
+  d.H = (double*)(base + o.H);
+  d.cnt = (unsigned*)(base + o.cnt);
+  d.nbmax = nbmax;
+}
+
+// host check that a cycle's geometry fits the carved capacities
+bool geometry_fits(const ProbDev& d, const BlockCaps& c, int nb_needed) {
+  const size_t bw2 = (size_t)d.bw * d.bw;
+  if (d.bw < 1 || d.bw > c.bwmax) return false;
+  if (nb_needed > c.nbmax) return false;
+  if ((size_t)d.Cu * bw2 > c.rloc) return false;
+  if (2 * (size_t)d.Cp * c.nbmax * bw2 > c.part) return false;
+  if ((size_t)(d.Cu) * d.rows_u > (size_t)c.n + (size_t)d.rows_u) return false;
+  if (c.n < d.bw) return false;
+  if (update_smem(d) > (size_t)pe::kUpdateLdsMax) return false;
+  return true;
+}
+
+// Chebyshev derivative matrix: T_k' = sum_j D[k][j] T_j, j < k, k - j odd, weight 2k
+// (k for j = 0)
+std::vector<double> chebyshev_derivative(int qmax) {
+  std::vector<double> D((size_t)qmax * qmax, 0.0);
+  for (int k = 1; k < qmax; ++k)
+    for (int j = k - 1; j >= 0; j -= 2) D[(size_t)k * qmax + j] = (j == 0) ? k : 2.0 * k;
+  return D;
+}
+
+void chebyshev_values(double x, int q, double* w) {
+  double a = 1.0, b = x;
+  for (int k = 0; k < q; ++k) {
+    if (k == 0) w[k] = 1.0;
+    else if (k == 1) w[k] = x;
+    else {
+      const double v = 2.0 * x * b - a;
+      a = b;
+      b = v;
+      w[k] = v;
+    }
+  }
+}
+
+pe_status validate_problem(pe_ctx* ctx, const pe_problem& p, bool need_samples) {
+  if (p.op.n < 4) return pe_fail(ctx, PE_ERR_ARG, "n must be >= 4");
+  if (!p.op.coeffs) return pe_fail(ctx, PE_ERR_ARG, "stencil coefficients are null");
+  if (!p.u0) return pe_fail(ctx, PE_ERR_ARG, "u0 is null");
+  if (!(p.t1 > p.t0)) return pe_fail(ctx, PE_ERR_ARG, "window needs t1 > t0");
+  if (p.n_out < 0 || (p.n_out > 0 && (!p.t_out || !p.out))) return pe_fail(ctx, PE_ERR_ARG, "bad outputs");
+  if (p.ldOut < p.op.n) return pe_fail(ctx, PE_ERR_ARG, "ldOut < n");
+  for (int k = 0; k < p.n_out; ++k) {
+    if (!std::isfinite(p.t_out[k])) return pe_fail(ctx, PE_ERR_ARG, "non-finite output time");
+    if (k > 0 && p.t_out[k] < p.t_out[k - 1]) return pe_fail(ctx, PE_ERR_ARG, "t_out must be non-decreasing");
+    if (!p.shift && p.t_out[k] < p.t0) return pe_fail(ctx, PE_ERR_ARG, "unshifted problem needs t_out >= t0");
+  }
+  if (p.krylov_steps < 1 || p.krylov_steps > 512) return pe_fail(ctx, PE_ERR_ARG, "krylov_steps out of range");
+  if (p.rank_max < 0 || p.rank_max > 31) return pe_fail(ctx, PE_ERR_UNSUPPORTED, "rank_max must be in [0, 31]");
+  if (p.q_max < 1 || p.q_max > 64) return pe_fail(ctx, PE_ERR_ARG, "q_max must be in [1, 64]");
+  if (!(p.tol > 0.0)) return pe_fail(ctx, PE_ERR_ARG, "tol must be positive");
+  if (p.prec != PE_FP64 && p.prec != PE_MIXED) return pe_fail(ctx, PE_ERR_ARG, "unknown precision");
+  if (need_samples) {
+    if (p.s < 1 || !p.t_samples || !p.G) return pe_fail(ctx, PE_ERR_ARG, "missing source samples");
+    if (p.ldG < p.op.n) return pe_fail(ctx, PE_ERR_ARG, "ldG < n");
+    for (int i = 0; i < p.s; ++i) {
+      if (!std::isfinite(p.t_samples[i])) return pe_fail(ctx, PE_ERR_ARG, "non-finite sample time");
+      if (i > 0 && !(p.t_samples[i] > p.t_samples[i - 1]))
+        return pe_fail(ctx, PE_ERR_ARG, "t_samples must be strictly increasing");
+    }
+    if (p.s > 1 && (p.t_samples[0] != p.t0 || p.t_samples[p.s - 1] != p.t1))
+      return pe_fail(ctx, PE_ERR_ARG, "t_samples must start at t0 and end at t1");
+    if (!(p.svd_tol >= 0.0) || !(p.fit_tol >= 0.0)) return pe_fail(ctx, PE_ERR_ARG, "negative tolerance");
+  }
+  if (!p.op.per_point)
+    for (int i = 0; i < 3; ++i)
+      if (!std::isfinite(p.op.coeffs[i])) return pe_fail(ctx, PE_ERR_NONFINITE, "non-finite stencil coefficient");
+  return PE_OK;
+}
+
+// ---- device finiteness check of caller arrays -------------------------------------
+pe_status check_finite_dev(pe_ctx* ctx, const double* x, int64_t n, int cols, int64_t ld, int* dflag, int* hflag,
+                           hipStream_t st, const char* what) {
+  HCK(hipMemsetAsync(dflag, 0, sizeof(int), st));
+  pe::launch_check_finite(x, n, cols, ld, dflag, st);
+  HCK(hipMemcpyAsync(hflag, dflag, sizeof(int), hipMemcpyDeviceToHost, st));
+  HCK(hipStreamSynchronize(st));
+  if (*hflag) return pe_fail(ctx, PE_ERR_NONFINITE, std::string("NaN or Inf in ") + what);
+  return PE_OK;
+}
+
+// ---- block orthogonalisation driver -------------------------------------------------
+void run_block_step(ProbDev* dd, int nprob, int gx_proj, size_t smem_p, int gx_upd, size_t smem_u, int j, int nb,
+                    int mode, int mixed, hipStream_t st) {
+  for (int pass = 0; pass < 2; ++pass) {
+    pe::launch_block_proj(dd, nprob, gx_proj, smem_p, j, nb, pass, mode, mixed, st);
+    pe::launch_block_update(dd, nprob, gx_upd, smem_u, j, nb, pass, mode, mixed, st);
+  }
+}
+
+// ---------------------------------------------------------------------------------
+// compression of one problem: S1-S4
+// ---------------------------------------------------------------------------------
+struct CompressOut {
+  int m = 0, q = 0, flags = 0;
+  double fit_resid = 0.0, svd_tail = 0.0, sigma1 = 0.0;
+  std::vector<double> sigma;
+};
+
+pe_status compress_one(pe_ctx* ctx, const pe_problem& p, double* U, int64_t ldU, double* Pi, int ldPi,
+                       CompressOut& res, hipStream_t st) {
+  const int64_t n = p.op.n;
+  const int s = p.s;
+  const int bwc = std::min(8, s);
+  const int nblk = (s + bwc - 1) / bwc;
+  const int S_ = nblk * bwc;
+  const int qcap = std::min(p.q_max, s);
+  BlockCaps caps = block_caps(n, bwc, nblk, S_, S_);
+  Carver cv;
+  const size_t o_coef = cv.take<double>(p.op.per_point ? 3 * (size_t)n : 3);
+  const size_t o_lu0 = cv.take<double>(n);
+  const size_t o_gh = cv.take<double>((size_t)n * s);
+  BlockOffsets bo = carve_block(cv, caps, false);
+  const size_t o_desc = cv.take<ProbDev>(1);
+  const size_t o_rn = cv.take<double>(S_);
+  const size_t o_sel = cv.take<int>(S_);
+  const size_t o_A = cv.take<double>((size_t)s * S_);
+  const size_t o_J = cv.take<double>((size_t)S_ * S_);
+  const size_t o_sig = cv.take<double>(S_);
+  const size_t o_perm = cv.take<int>(S_);
+  const size_t o_info = cv.take<int>(4);
+  const size_t o_ts = cv.take<double>(s);
+  const size_t o_fw = cv.take<double>((size_t)s * qcap + (size_t)qcap * qcap + (size_t)32 * qcap + (size_t)32 * s);
+  const size_t o_fi = cv.take<double>(4);
+  const size_t o_flag = cv.take<int>(4);
+  pe_status stt = ensure_arena(ctx, cv.off);
+  if (stt != PE_OK) return stt;
+  stt = ensure_pinned(ctx, sizeof(double) * (4 * (size_t)S_ + 64));
+  if (stt != PE_OK) return stt;
+  char* base = ctx->arena;
+  double* hp = (double*)ctx->pinned;
+
+  // non-finite inputs
+  stt = check_finite_dev(ctx, p.u0, n, 1, n, (int*)(base + o_flag), (int*)hp, st, "u0");
+  if (stt != PE_OK) return stt;
+  stt = check_finite_dev(ctx, p.G, n, s, p.ldG, (int*)(base + o_flag), (int*)hp, st, "G");
+  if (stt != PE_OK) return stt;
+  if (p.op.per_point) {
+    stt = check_finite_dev(ctx, p.op.coeffs, 3 * n, 1, 3 * n, (int*)(base + o_flag), (int*)hp, st, "stencil");
+    if (stt != PE_OK) return stt;
+  }
+  // S1: G^ = G + L u0
+  double* Gh = (double*)(base + o_gh);
+  double* Lu0 = (double*)(base + o_lu0);
+  if (p.shift) {
+    pe::launch_stencil_cols(n, p.op.per_point, p.op.coeffs, p.op.coeffs, p.u0, n, Lu0, n, 1, st);
+    pe::launch_add_column(n, s, p.G, p.ldG, Lu0, Gh, n, st);
+  } else {
+    pe::launch_add_column(n, s, p.G, p.ldG, nullptr, Gh, n, st);
+  }
+  // S2-S3: G^ = Q R by block CGS2 + TSQR in blocks of bwc columns
+  ProbDev d{};
+  d.n = n;
+  d.per_point = p.op.per_point;
+  if (!p.op.per_point) std::memcpy(d.c3, p.op.coeffs, 3 * sizeof(double));
+  d.coef = p.op.per_point ? p.op.coeffs : nullptr;
+  bind_block(d, base, bo, false, nblk);
+  d.Xg = Gh;
+  d.ldXg = n;
+  d.m = s;
+  d.l = nblk;
+  d.active = 1;
+  d.ldH = S_;
+  set_geometry(d, n, bwc);
+  if (!geometry_fits(d, caps, nblk)) return pe_fail(ctx, PE_ERR_UNSUPPORTED, "compression geometry exceeds workspace");
+  ProbDev* dd = (ProbDev*)(base + o_desc);
+  HCK(hipMemsetAsync(d.cnt, 0, caps.cnt * sizeof(unsigned), st));
+  HCK(hipMemsetAsync(d.H, 0, caps.H * sizeof(double), st));
+  HCK(hipMemcpyAsync(dd, &d, sizeof(ProbDev), hipMemcpyHostToDevice, st));
+  const size_t smem_p = proj_smem(d.rows_p, bwc), smem_u = update_smem(d);
+  for (int j = 0; j < nblk; ++j) {
+    run_block_step(dd, 1, j * d.Cp, smem_p, d.Cu, smem_u, j, j, pe::MODE_GIVEN, 0, st);
+    pe::launch_block_commit(dd, 1, (int)((n * bwc + 255) / 256), j, 0, st);
+  }
+  // significant rows of R
+  double* R = d.H;
+  if (const char* dump = std::getenv("PARAEXP_DUMP")) {  // debugging aid: R and Q as raw doubles
+    HCK(hipStreamSynchronize(st));
+    std::vector<double> hR((size_t)S_ * S_), hQ((size_t)nblk * n * bwc);
+    HCK(hipMemcpy(hR.data(), R, sizeof(double) * hR.size(), hipMemcpyDeviceToHost));
+    HCK(hipMemcpy(hQ.data(), d.V, sizeof(double) * hQ.size(), hipMemcpyDeviceToHost));
+    std::string base_path(dump);
+    if (FILE* f = std::fopen((base_path + "_R.bin").c_str(), "wb")) {
+      std::fwrite(hR.data(), sizeof(double), hR.size(), f);
+      std::fclose(f);
+    }
+    if (FILE* f = std::fopen((base_path + "_Q.bin").c_str(), "wb")) {
+      std::fwrite(hQ.data(), sizeof(double), hQ.size(), f);
+      std::fclose(f);
+    }
+  }
+  pe::launch_row_norms(R, S_, S_, s, (double*)(base + o_rn), st);
+  HCK(hipMemcpyAsync(hp, base + o_rn, sizeof(double) * S_, hipMemcpyDeviceToHost, st));
+  HCK(hipStreamSynchronize(st));
+  double fro2 = 0.0;
+  for (int i = 0; i < S_; ++i) fro2 += hp[i] * hp[i];
+  const double fro = std::sqrt(fro2);
+  std::vector<int> sel;
+  for (int i = 0; i < S_; ++i)
+    if (hp[i] > 1e-15 * fro) sel.push_back(i);
+  res.sigma.assign(s, 0.0);
+  res.m = 0;
+  if (fro == 0.0 || sel.empty() || p.rank_max == 0) {
+    res.sigma1 = 0.0;
+    res.svd_tail = fro == 0.0 ? 0.0 : 1.0;
+    if (fro > 0.0 && p.rank_max == 0) res.flags |= PE_FLAG_RANK_CAPPED;
+    return PE_OK;
+  }
+  const int r = (int)sel.size();
+  HCK(hipMemcpyAsync(base + o_sel, sel.data(), sizeof(int) * r, hipMemcpyHostToDevice, st));
+  double* A = (double*)(base + o_A);
+  double* J = (double*)(base + o_J);
+  pe::launch_jacobi_svd(R, S_, (int*)(base + o_sel), s, r, A, J, (double*)(base + o_sig), (int*)(base + o_perm),
+                        (int*)(base + o_info), st);
+  std::vector<int> perm(r);
+  HCK(hipMemcpyAsync(hp, base + o_sig, sizeof(double) * r, hipMemcpyDeviceToHost, st));
+  HCK(hipMemcpyAsync(perm.data(), base + o_perm, sizeof(int) * r, hipMemcpyDeviceToHost, st));
+  HCK(hipStreamSynchronize(st));
+  std::vector<double> sig(r);
+  for (int i = 0; i < r; ++i) sig[i] = hp[perm[i]];
+  // truncation: smallest m with dropped energy <= svd_tol |G^|_F, never keeping
+  // sigma <= kSigmaFloor sigma_1 (the resolution of the block QR, whose dependence test
+  // drops chunk remainders below 1e-12 of a column), keeping clusters whole, capped at
+  // rank_max
+  double sfro2 = 0.0;
+  for (double v : sig) sfro2 += v * v;
+  const double gfro = std::sqrt(sfro2);
+  std::vector<double> tail(r + 1, 0.0);
+  for (int i = r - 1; i >= 0; --i) tail[i] = std::sqrt(tail[i + 1] * tail[i + 1] + sig[i] * sig[i]);
+  int m = r;
+  for (int i = 0; i <= r; ++i)
+    if (tail[i] <= p.svd_tol * gfro) {
+      m = i;
+      break;
+    }
+  while (m > 0 && sig[m - 1] <= kSigmaFloor * sig[0]) --m;
+  while (m > 0 && m < r && std::fabs(sig[m - 1] - sig[m]) <= 1e-12 * sig[0] && sig[m] > kSigmaFloor * sig[0]) ++m;
+  if (m > p.rank_max) {
+    m = p.rank_max;
+    res.flags |= PE_FLAG_RANK_CAPPED;
+  }
+  res.m = m;
+  res.sigma1 = sig[0];
+  res.svd_tail = gfro > 0.0 ? tail[m] / gfro : 0.0;
+  for (int i = 0; i < std::min(r, s); ++i) res.sigma[i] = sig[i];
+  if (m == 0) return PE_OK;
+  // U = Q J[:, perm[0:m]]
+  pe::launch_form_u(d.V, bwc, n, (int*)(base + o_sel), r, J, (int*)(base + o_perm), m, U, ldU, st);
+  // S4: Chebyshev fit of C = Sigma Z^T rows over the samples
+  HCK(hipMemcpyAsync(base + o_ts, p.t_samples, sizeof(double) * s, hipMemcpyHostToDevice, st));
+  pe::launch_fit(A, s, (int*)(base + o_perm), m, (double*)(base + o_ts), p.t0, p.t1, qcap, p.fit_tol, Pi, ldPi,
+                 (double*)(base + o_fw), (double*)(base + o_fi), st);
+  HCK(hipMemcpyAsync(hp, base + o_fi, sizeof(double) * 3, hipMemcpyDeviceToHost, st));
+  HCK(hipStreamSynchronize(st));
+  res.q = (int)hp[0];
+  res.fit_resid = hp[1];
+  if (hp[2] != 0.0) res.flags |= PE_FLAG_FIT_CAPPED;
+  return PE_OK;
+}
+
+// ---------------------------------------------------------------------------------
+// the march: S5-S7 for a batch of problems of one precision
+// ---------------------------------------------------------------------------------
+struct HostState {
+  double tau = 0.0, dlast = 0.0, Tspan = 1.0, ref = 1.0;
+  int k = 0;
+  bool xzero = true, done = false;
+  int cycles = 0, rejected = 0, steps = 0, flags = 0;
+  double resid = 0.0;
+  // per-cycle
+  bool src = false;
+  double target = 0.0, dtry = 0.0, nrm = 0.0;
+  int bw = 1, N = 0;
+  bool pending = false, accepted = false;
+};
+
+pe_status march_batch(pe_ctx* ctx, const pe_problem* probs, const int* idx, int nb_prob, const double* const* Ul,
+                      const double* const* Pil, const int* ldPil, const int* ml, const int* ql, pe_report* reports,
+                      hipStream_t st) {
+  if (nb_prob == 0) return PE_OK;
+  const bool mixed = probs[idx[0]].prec == PE_MIXED;
+  int qmax_all = 1;
+  for (int ii = 0; ii < nb_prob; ++ii) qmax_all = std::max(qmax_all, ql[ii]);
+  // carve
+  Carver cv;
+  std::vector<BlockCaps> caps(nb_prob);
+  std::vector<BlockOffsets> bo(nb_prob);
+  std::vector<size_t> o_x(nb_prob), o_e(nb_prob), o_w(nb_prob), o_coef(nb_prob);
+  std::vector<int> Nmax(nb_prob);
+  int64_t maxn = 0;
+  int maxNall = 1, max_lbw = 1;
+  for (int ii = 0; ii < nb_prob; ++ii) {
+    const pe_problem& p = probs[idx[ii]];
+    const int bwmax = ml[ii] + 1;
+    const int l = p.krylov_steps;
+    caps[ii] = block_caps(p.op.n, bwmax, l + 1, (int64_t)(l + 1) * bwmax, (int64_t)l * bwmax);
+    bo[ii] = carve_block(cv, caps[ii], mixed);
+    o_x[ii] = cv.take<double>(p.op.n);
+    Nmax[ii] = l * bwmax + ql[ii];
+    o_e[ii] = cv.take<double>(7 * (size_t)Nmax[ii] * Nmax[ii] + 2 * (size_t)Nmax[ii] + 2);
+    o_w[ii] = cv.take<double>(std::max(1, ql[ii]));
+    maxn = std::max<int64_t>(maxn, p.op.n);
+    maxNall = std::max(maxNall, Nmax[ii]);
+    max_lbw = std::max(max_lbw, l * bwmax);
+  }
+  const size_t o_pd = cv.take<ProbDev>(nb_prob);
+  const size_t o_ed = cv.take<ExpmDev>(nb_prob);
+  const size_t o_Dm = cv.take<double>((size_t)qmax_all * qmax_all);
+  const size_t o_nrm = cv.take<double>(nb_prob);
+  pe_status stt = ensure_arena(ctx, cv.off);
+  if (stt != PE_OK) return stt;
+  stt = ensure_pinned(ctx, sizeof(double) * (4 * (size_t)nb_prob + 64));
+  if (stt != PE_OK) return stt;
+  char* base = ctx->arena;
+  double* hp = (double*)ctx->pinned;
+  ProbDev* dd = (ProbDev*)(base + o_pd);
+  ExpmDev* ed = (ExpmDev*)(base + o_ed);
+  {
+    std::vector<double> D = chebyshev_derivative(qmax_all);
+    HCK(hipMemcpyAsync(base + o_Dm, D.data(), sizeof(double) * D.size(), hipMemcpyHostToDevice, st));
+    HCK(hipStreamSynchronize(st));
+  }
+  std::vector<ProbDev> hd(nb_prob);
+  std::vector<ExpmDev> he(nb_prob);
+  std::vector<HostState> hs(nb_prob);
+  std::vector<double> u0n(nb_prob, 0.0);
+  // norms of u0 (reference scale of the error control)
+  {
+    double* tmp = (double*)(base + o_nrm);
+    for (int ii = 0; ii < nb_prob; ++ii) {
+      const pe_problem& p = probs[idx[ii]];
+      pe::launch_row_norms(p.u0, 1, 1, (int)p.op.n, tmp + ii, st);
+    }
+    HCK(hipMemcpyAsync(hp, tmp, sizeof(double) * nb_prob, hipMemcpyDeviceToHost, st));
+    HCK(hipStreamSynchronize(st));
+    for (int ii = 0; ii < nb_prob; ++ii) u0n[ii] = hp[ii];
+  }
+  for (int ii = 0; ii < nb_prob; ++ii) {
+    const pe_problem& p = probs[idx[ii]];
+    ProbDev& d = hd[ii];
+    d = ProbDev{};
+    d.n = p.op.n;
+    d.per_point = p.op.per_point;
+    if (!p.op.per_point) std::memcpy(d.c3, p.op.coeffs, 3 * sizeof(double));
+    d.coef = p.op.per_point ? p.op.coeffs : nullptr;
+    bind_block(d, base, bo[ii], mixed, p.krylov_steps + 1);
+    d.U = Ul[ii];
+    d.xstate = (double*)(base + o_x[ii]);
+    d.x = d.xstate;
+    HostState& h = hs[ii];
+    h.tau = p.t0;
+    h.k = 0;
+    const double tlast = p.n_out > 0 ? p.t_out[p.n_out - 1] : p.t0;
+    h.Tspan = std::max(tlast - p.t0, 1e-300);
+    h.ref = std::max(u0n[ii], 1e-300);
+    h.dlast = h.Tspan;
+    h.xzero = p.shift != 0;
+    if (p.shift) pe::launch_fill(d.xstate, p.op.n, 1, p.op.n, 0.0, st);
+    else pe::launch_copy(p.u0, d.xstate, p.op.n, st);
+    // outputs at or before the start
+    while (h.k < p.n_out && p.t_out[h.k] <= p.t0) {
+      double* col = p.out + (int64_t)h.k * p.ldOut;
+      if (p.t_out[h.k] < p.t0 || p.shift) pe::launch_fill(col, p.op.n, 1, p.op.n, 0.0, st);
+      else pe::launch_copy(p.u0, col, p.op.n, st);
+      ++h.k;
+    }
+    h.done = h.k >= p.n_out;
+    HCK(hipMemsetAsync(d.cnt, 0, caps[ii].cnt * sizeof(unsigned), st));
+    ExpmDev& e = he[ii];
+    e = ExpmDev{};
+    double* eb = (double*)(base + o_e[ii]);
+    const size_t NN = (size_t)Nmax[ii] * Nmax[ii];
+    e.Ht = eb;
+    e.A = eb + NN;
+    e.A2 = eb + 2 * NN;
+    e.A3 = eb + 3 * NN;
+    e.A4 = eb + 4 * NN;
+    e.P = eb + 5 * NN;
+    e.T = eb + 6 * NN;
+    e.b = eb + 7 * NN;
+    e.y = e.b + Nmax[ii];
+    e.out = e.y + Nmax[ii];
+    e.H = d.H;
+    e.R0 = d.Rf + 0;  // set per cycle (depends on bw)
+    e.Pi = Pil[ii];
+    e.ldPi = ldPil[ii];
+    e.w = (double*)(base + o_w[ii]);
+    e.Dm = (double*)(base + o_Dm);
+    e.qmax = qmax_all;
+    e.kscale = 2.0 / (p.t1 - p.t0);
+  }
+  std::vector<std::vector<double>> wv(nb_prob, std::vector<double>(qmax_all + 1));
+  int guard = 0;
+  const int trace = env_int("PARAEXP_TRACE", 0);
+  const int max_cycles = env_int("PARAEXP_MAX_CYCLES", 0);
+  while (true) {
+    // ---- plan the cycle
+    int nact = 0, lmax = 0, gx_p = 0, gx_u = 0, mb_N = 1;
+    size_t smem_p = 0, smem_u = 0;
+    int64_t maxNN = 1;
+    for (int ii = 0; ii < nb_prob; ++ii) {
+      const pe_problem& p = probs[idx[ii]];
+      HostState& h = hs[ii];
+      ProbDev& d = hd[ii];
+      d.active = 0;
+      d.proj = 0;
+      he[ii].active = 0;
+      if (h.done) continue;
+      const int m = ml[ii];
+      h.src = (m > 0) && (h.tau < p.t1);
+      if (!h.src && h.xzero) {  // the shifted state stays zero: remaining outputs are zero
+        for (; h.k < p.n_out; ++h.k) pe::launch_fill(p.out + (int64_t)h.k * p.ldOut, p.op.n, 1, p.op.n, 0.0, st);
+        h.done = true;
+        continue;
+      }
+      h.target = h.src ? std::min(p.t_out[h.k], p.t1) : p.t_out[h.k];
+      const double rem = h.target - h.tau;
+      h.dtry = std::min(rem, 2.0 * h.dlast);
+      h.bw = h.src ? (h.xzero ? m : m + 1) : 1;
+      d.m = h.src ? m : 0;
+      d.with_x = h.xzero ? 0 : 1;
+      d.l = p.krylov_steps;
+      d.ldH = (int64_t)(d.l + 1) * h.bw;
+      set_geometry(d, p.op.n, h.bw);
+      if (!geometry_fits(d, caps[ii], d.l + 1))
+        return pe_fail(ctx, PE_ERR_UNSUPPORTED, "cycle geometry exceeds the workspace");
+      d.active = 1;
+      ++nact;
+      lmax = std::max(lmax, d.l);
+      gx_p = std::max(gx_p, (d.l + 1) * d.Cp);
+      gx_u = std::max(gx_u, d.Cu);
+      smem_p = std::max(smem_p, proj_smem(d.rows_p, d.bw));
+      smem_u = std::max(smem_u, update_smem(d));
+      h.N = d.l * h.bw + (h.src ? ql[ii] : 0);
+      mb_N = std::max(mb_N, h.N);
+      maxNN = std::max<int64_t>(maxNN, (int64_t)h.N * h.N);
+      ExpmDev& e = he[ii];
+      e.N = h.N;
+      e.l = d.l;
+      e.bw = h.bw;
+      e.m = d.m;
+      e.q = h.src ? ql[ii] : 0;
+      e.with_x = d.with_x;
+      e.lbw = d.l * h.bw;
+      e.ldH = d.ldH;
+      e.R0 = d.Rf + 2 * (size_t)h.bw * h.bw;
+      if (h.src && ql[ii] > 0) {
+        chebyshev_values((2.0 * h.tau - p.t0 - p.t1) / (p.t1 - p.t0), ql[ii], wv[ii].data());
+        HCK(hipMemcpyAsync((void*)e.w, wv[ii].data(), sizeof(double) * ql[ii], hipMemcpyHostToDevice, st));
+      }
+    }
+    if (nact == 0) break;
+    if (++guard > 10000000) return pe_fail(ctx, PE_ERR_DEVICE, "march did not terminate");
+    if (max_cycles > 0 && guard > max_cycles) {
+      for (int ii = 0; ii < nb_prob; ++ii) hs[ii].flags |= PE_FLAG_NOT_CONVERGED;
+      break;
+    }
+    HCK(hipMemcpyAsync(dd, hd.data(), sizeof(ProbDev) * nb_prob, hipMemcpyHostToDevice, st));
+    // ---- S5: initial block and block Arnoldi
+    pe::launch_block_update(dd, nb_prob, gx_u, smem_u, 0, 0, 1, pe::MODE_INIT, mixed, st);
+    for (int j = 0; j < lmax; ++j) {
+      const int gxp = std::min(gx_p, (j + 1) * 4096);
+      run_block_step(dd, nb_prob, gxp, smem_p, gx_u, smem_u, j, j + 1, pe::MODE_ARNOLDI, mixed, st);
+    }
+    // ---- S6: projected exponential with step-size trials
+    for (int ii = 0; ii < nb_prob; ++ii) he[ii].active = hd[ii].active;
+    HCK(hipMemcpyAsync(ed, he.data(), sizeof(ExpmDev) * nb_prob, hipMemcpyHostToDevice, st));
+    pe::launch_build_aug(ed, nb_prob, maxNN, st);
+    pe::launch_norm1(ed, (double*)(base + o_nrm), nb_prob, st);
+    HCK(hipMemcpyAsync(hp, base + o_nrm, sizeof(double) * nb_prob, hipMemcpyDeviceToHost, st));
+    HCK(hipStreamSynchronize(st));
+    for (int ii = 0; ii < nb_prob; ++ii) {
+      hs[ii].nrm = hp[ii];
+      hs[ii].pending = hd[ii].active != 0;
+      hs[ii].accepted = false;
+    }
+    const int tiles = (mb_N + 31) / 32;
+    for (int trial = 0; trial < kMaxTrials; ++trial) {
+      int maxsq = 0, npend = 0;
+      for (int ii = 0; ii < nb_prob; ++ii) {
+        ExpmDev& e = he[ii];
+        HostState& h = hs[ii];
+        e.active = h.pending ? 1 : 0;
+        if (!h.pending) continue;
+        ++npend;
+        const double nn = h.dtry * h.nrm;
+        int s = 0;
+        if (nn > kTaylorTheta) s = (int)std::ceil(std::log2(nn / kTaylorTheta));
+        s = std::max(0, std::min(s, 60));
+        e.nsq = s;
+        e.alpha = std::ldexp(h.dtry, -s);
+        maxsq = std::max(maxsq, s);
+      }
+      if (npend == 0) break;
+      HCK(hipMemcpyAsync(ed, he.data(), sizeof(ExpmDev) * nb_prob, hipMemcpyHostToDevice, st));
+      pe::launch_elementwise(ed, 0, nb_prob, maxNN, st);
+      pe::launch_gemm(ed, 0, 0, nb_prob, tiles * tiles, st);
+      pe::launch_gemm(ed, 1, 0, nb_prob, tiles * tiles, st);
+      pe::launch_gemm(ed, 2, 0, nb_prob, tiles * tiles, st);
+      pe::launch_elementwise(ed, 1, nb_prob, maxNN, st);
+      pe::launch_gemm(ed, 3, 0, nb_prob, tiles * tiles, st);
+      pe::launch_gemm(ed, 4, 0, nb_prob, tiles * tiles, st);
+      pe::launch_gemm(ed, 5, 0, nb_prob, tiles * tiles, st);
+      for (int k = 0; k < maxsq; ++k) pe::launch_gemm(ed, 6, k, nb_prob, tiles * tiles, st);
+      pe::launch_expm_apply(ed, nb_prob, mb_N, st);
+      for (int ii = 0; ii < nb_prob; ++ii)
+        if (hs[ii].pending) HCK(hipMemcpyAsync(hp + 2 * ii, he[ii].out, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+      HCK(hipStreamSynchronize(st));
+      for (int ii = 0; ii < nb_prob; ++ii) {
+        HostState& h = hs[ii];
+        if (!h.pending) continue;
+        const pe_problem& p = probs[idx[ii]];
+        const double err = hp[2 * ii], yn = hp[2 * ii + 1];
+        const double lim = p.tol * std::max(h.ref, yn) / h.Tspan;
+        const double dmin = 1e-13 * h.Tspan;
+        if (trace)
+          fprintf(stderr, "[paraexp] prob %d cycle %d trial %d tau %.6e dtry %.3e N %d bw %d |H|1 %.3e nsq %d err %.3e lim %.3e |y| %.3e\n",
+                  idx[ii], guard, trial, h.tau, h.dtry, h.N, h.bw, h.nrm, he[ii].nsq, err, lim, yn);
+        if (std::isfinite(err) && (err <= lim || h.dtry <= dmin)) {
+          h.accepted = true;
+          h.pending = false;
+          if (err > lim) h.flags |= PE_FLAG_NOT_CONVERGED;
+          h.resid = std::max(h.resid, err * h.dtry);
+        } else {
+          ++h.rejected;
+          const double rho = std::isfinite(err) ? err / lim : 1e30;
+          const double ex = 1.0 / std::max(2.0, probs[idx[ii]].krylov_steps / 3.0);
+          h.dtry *= std::min(0.7, std::max(0.1, 0.9 * std::pow(rho, -ex)));
+        }
+      }
+    }
+    // ---- S7: project the accepted problems
+    int nproj = 0;
+    for (int ii = 0; ii < nb_prob; ++ii) {
+      HostState& h = hs[ii];
+      ProbDev& d = hd[ii];
+      const pe_problem& p = probs[idx[ii]];
+      d.proj = 0;
+      d.outcol = nullptr;
+      if (!d.active) continue;
+      h.steps += d.l;
+      if (!h.accepted) {
+        h.dlast = h.dtry;  // retry the cycle with the reduced step
+        continue;
+      }
+      const double rem = h.target - h.tau;
+      const bool landed = h.dtry >= rem;
+      d.proj = 1;
+      if (landed && h.target == p.t_out[h.k]) d.outcol = p.out + (int64_t)h.k * p.ldOut;
+      ++nproj;
+    }
+    if (nproj) {
+      HCK(hipMemcpyAsync(dd, hd.data(), sizeof(ProbDev) * nb_prob, hipMemcpyHostToDevice, st));
+      pe::launch_project(dd, ed, nb_prob, maxn, max_lbw, mixed, st);
+    }
+    for (int ii = 0; ii < nb_prob; ++ii) {
+      HostState& h = hs[ii];
+      ProbDev& d = hd[ii];
+      const pe_problem& p = probs[idx[ii]];
+      if (!d.active || !h.accepted) continue;
+      const double rem = h.target - h.tau;
+      const bool landed = h.dtry >= rem;
+      h.tau = landed ? h.target : h.tau + h.dtry;
+      h.dlast = h.dtry;
+      h.xzero = false;
+      ++h.cycles;
+      if (d.outcol) {
+        const double tk = p.t_out[h.k];
+        ++h.k;
+        while (h.k < p.n_out && p.t_out[h.k] == tk) {
+          pe::launch_copy(d.outcol, p.out + (int64_t)h.k * p.ldOut, p.op.n, st);
+          ++h.k;
+        }
+      }
+      if (h.k >= p.n_out) h.done = true;
+    }
+    // host descriptors are rewritten next cycle: drain the queued uploads first
+    HCK(hipStreamSynchronize(st));
+  }
+  HCK(hipStreamSynchronize(st));
+  for (int ii = 0; ii < nb_prob; ++ii) {
+    pe_report& r = reports[idx[ii]];
+    r.cycles = hs[ii].cycles;
+    r.rejected = hs[ii].rejected;
+    r.block_steps = hs[ii].steps;
+    r.flags |= hs[ii].flags;
+    r.resid_est = hs[ii].resid;
+  }
+  return PE_OK;
+}
+
+pe_status march_all(pe_ctx* ctx, const pe_problem* probs, int nprob, const double* const* Ul,
+                    const double* const* Pil, const int* ldPil, const int* ml, const int* ql, pe_report* reports,
+                    hipStream_t st) {
+  for (int prec = 0; prec < 2; ++prec) {
+    std::vector<int> idx;
+    std::vector<const double*> U, Pi;
+    std::vector<int> ld, m, q;
+    for (int i = 0; i < nprob; ++i)
+      if ((int)probs[i].prec == prec) {
+        idx.push_back(i);
+        U.push_back(Ul[i]);
+        Pi.push_back(Pil[i]);
+        ld.push_back(ldPil[i]);
+        m.push_back(ml[i]);
+        q.push_back(ql[i]);
+      }
+    if (idx.empty()) continue;
+    pe_status s = march_batch(ctx, probs, idx.data(), (int)idx.size(), U.data(), Pi.data(), ld.data(), m.data(),
+                              q.data(), reports, st);
+    if (s != PE_OK) return s;
+  }
+  return PE_OK;
+}
+
+}  // namespace
+
+// =====================================================================================
+// C ABI
+// =====================================================================================
+extern "C" {
+
+const char* pe_version(void) { return "paraexp-gfx950 0.1"; }
+
+pe_status pe_create(pe_ctx** ctx_out, int device) {
+  if (!ctx_out) return PE_ERR_ARG;
+  *ctx_out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) return PE_ERR_DEVICE;
+  if (device < 0 || device >= count) return PE_ERR_ARG;
+  if (hipSetDevice(device) != hipSuccess) return PE_ERR_DEVICE;
+  pe_ctx* ctx = new pe_ctx();
+  ctx->device = device;
+  *ctx_out = ctx;
+  return PE_OK;
+}
+
+pe_status pe_destroy(pe_ctx* ctx) {
+  if (!ctx) return PE_ERR_ARG;
+  hipSetDevice(ctx->device);
+  hipDeviceSynchronize();
+  if (ctx->arena) hipFree(ctx->arena);
+  if (ctx->pinned) hipHostFree(ctx->pinned);
+  delete ctx;
+  return PE_OK;
+}
+
+const char* pe_last_error(const pe_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+pe_status pe_stencil_apply(pe_ctx* ctx, const pe_stencil* op, const double* X, int64_t ldx, double* Y, int64_t ldy,
+                           int32_t ncols, void* stream) {
+  if (!ctx) return PE_ERR_ARG;
+  if (!op || !op->coeffs || !X || !Y || op->n < 1 || ldx < op->n || ldy < op->n || ncols < 0)
+    return pe_fail(ctx, PE_ERR_ARG, "pe_stencil_apply: bad arguments");
+  HCK(hipSetDevice(ctx->device));
+  hipStream_t st = (hipStream_t)stream;
+  pe::launch_stencil_cols(op->n, op->per_point, op->coeffs, op->coeffs, X, ldx, Y, ldy, ncols, st);
+  HCK(hipGetLastError());
+  HCK(hipStreamSynchronize(st));
+  return PE_OK;
+}
+
+pe_status pe_compress(pe_ctx* ctx, const pe_problem* prob, double* U, double* Pi, int32_t* m, int32_t* q,
+                      double* sigma, pe_report* report, void* stream) {
+  if (!ctx) return PE_ERR_ARG;
+  if (!prob || !U || !Pi || !m || !q) return pe_fail(ctx, PE_ERR_ARG, "pe_compress: null argument");
+  pe_status s = validate_problem(ctx, *prob, true);
+  if (s != PE_OK) return s;
+  HCK(hipSetDevice(ctx->device));
+  hipStream_t st = (hipStream_t)stream;
+  CompressOut co;
+  s = compress_one(ctx, *prob, U, prob->op.n, Pi, std::max(1, prob->rank_max), co, st);
+  if (s != PE_OK) return s;
+  HCK(hipGetLastError());
+  HCK(hipStreamSynchronize(st));
+  *m = co.m;
+  *q = co.q;
+  if (sigma)
+    for (int i = 0; i < prob->s; ++i) sigma[i] = co.sigma[i];
+  if (report) {
+    std::memset(report, 0, sizeof(pe_report));
+    report->rank = co.m;
+    report->q = co.q;
+    report->flags = co.flags;
+    report->fit_resid = co.fit_resid;
+    report->svd_tail = co.svd_tail;
+    report->sigma1 = co.sigma1;
+  }
+  return PE_OK;
+}
+
+pe_status pe_expaction_batch(pe_ctx* ctx, const pe_problem* probs, const double* const* U, const double* const* Pi,
+                             const int32_t* m, const int32_t* q, int32_t nprob, pe_report* reports, void* stream) {
+  if (!ctx) return PE_ERR_ARG;
+  if (nprob < 0 || (nprob > 0 && (!probs || !m || !q || !reports || !U || !Pi)))
+    return pe_fail(ctx, PE_ERR_ARG, "pe_expaction_batch: bad arguments");
+  for (int i = 0; i < nprob; ++i) {
+    pe_status s = validate_problem(ctx, probs[i], false);
+    if (s != PE_OK) return s;
+    if (m[i] < 0 || m[i] > 31 || q[i] < 0 || q[i] > 64 || (m[i] > 0 && (q[i] < 1 || !U[i] || !Pi[i])))
+      return pe_fail(ctx, PE_ERR_ARG, "pe_expaction_batch: bad m/q/U/Pi");
+    if (probs[i].op.n < m[i] + 1) return pe_fail(ctx, PE_ERR_ARG, "n too small for the block width");
+  }
+  HCK(hipSetDevice(ctx->device));
+  hipStream_t st = (hipStream_t)stream;
+  std::vector<int> ld(nprob), mm(nprob), qq(nprob);
+  for (int i = 0; i < nprob; ++i) {
+    ld[i] = std::max(1, m[i]);
+    mm[i] = m[i];
+    qq[i] = m[i] > 0 ? q[i] : 0;
+    std::memset(&reports[i], 0, sizeof(pe_report));
+    reports[i].rank = m[i];
+    reports[i].q = qq[i];
+  }
+  pe_status s = march_all(ctx, probs, nprob, U, Pi, ld.data(), mm.data(), qq.data(), reports, st);
+  if (s != PE_OK) return s;
+  HCK(hipGetLastError());
+  HCK(hipStreamSynchronize(st));
+  return PE_OK;
+}
+
+pe_status pe_solve_batch(pe_ctx* ctx, const pe_problem* probs, int32_t nprob, pe_report* reports, void* stream) {
+  if (!ctx) return PE_ERR_ARG;
+  if (nprob < 0 || (nprob > 0 && (!probs || !reports))) return pe_fail(ctx, PE_ERR_ARG, "pe_solve_batch: bad arguments");
+  for (int i = 0; i < nprob; ++i) {
+    pe_status s = validate_problem(ctx, probs[i], true);
+    if (s != PE_OK) return s;
+    if (probs[i].op.n < probs[i].rank_max + 1) return pe_fail(ctx, PE_ERR_ARG, "n too small for rank_max");
+  }
+  HCK(hipSetDevice(ctx->device));
+  hipStream_t st = (hipStream_t)stream;
+  // compressed sources live in their own device allocation so the march can reuse the arena
+  size_t tot = 0;
+  std::vector<size_t> offU(nprob), offPi(nprob);
+  for (int i = 0; i < nprob; ++i) {
+    tot = (tot + 255) & ~(size_t)255;
+    offU[i] = tot;
+    tot += sizeof(double) * (size_t)probs[i].op.n * std::max(1, probs[i].rank_max);
+    tot = (tot + 255) & ~(size_t)255;
+    offPi[i] = tot;
+    tot += sizeof(double) * (size_t)std::max(1, probs[i].rank_max) * probs[i].q_max;
+  }
+  char* src = nullptr;
+  HCK(hipMalloc((void**)&src, std::max<size_t>(tot, 256)));
+  std::vector<const double*> Ul(nprob), Pil(nprob);
+  std::vector<int> ld(nprob), mm(nprob), qq(nprob);
+  pe_status s = PE_OK;
+  for (int i = 0; i < nprob && s == PE_OK; ++i) {
+    std::memset(&reports[i], 0, sizeof(pe_report));
+    CompressOut co;
+    double* U = (double*)(src + offU[i]);
+    double* Pi = (double*)(src + offPi[i]);
+    s = compress_one(ctx, probs[i], U, probs[i].op.n, Pi, std::max(1, probs[i].rank_max), co, st);
+    if (s != PE_OK) break;
+    Ul[i] = U;
+    Pil[i] = Pi;
+    ld[i] = std::max(1, probs[i].rank_max);
+    mm[i] = co.m;
+    qq[i] = co.m > 0 ? co.q : 0;
+    reports[i].rank = co.m;
+    reports[i].q = qq[i];
+    reports[i].flags = co.flags;
+    reports[i].fit_resid = co.fit_resid;
+    reports[i].svd_tail = co.svd_tail;
+    reports[i].sigma1 = co.sigma1;
+  }
+  if (s == PE_OK) s = march_all(ctx, probs, nprob, Ul.data(), Pil.data(), ld.data(), mm.data(), qq.data(), reports, st);
+  hipStreamSynchronize(st);
+  hipFree(src);
+  if (s != PE_OK) return s;
+  HCK(hipGetLastError());
+  return PE_OK;
+}
+
+pe_status pe_superpose(pe_ctx* ctx, const double* u0, const double* const* v, int32_t P, int64_t n, int32_t n_out,
+                       int64_t ldv, double* u, int64_t ldu, void* stream) {
+  if (!ctx) return PE_ERR_ARG;
+  if (!u0 || !u || P < 0 || n < 1 || n_out < 0 || ldv < n || ldu < n || (P > 0 && !v))
+    return pe_fail(ctx, PE_ERR_ARG, "pe_superpose: bad arguments");
+  for (int j = 0; j < P; ++j)
+    if (!v[j]) return pe_fail(ctx, PE_ERR_ARG, "pe_superpose: null window pointer");
+  HCK(hipSetDevice(ctx->device));
+  hipStream_t st = (hipStream_t)stream;
+  if (n_out == 0) return PE_OK;
+  if (P == 0) {
+    for (int k = 0; k < n_out; ++k) pe::launch_copy(u0, u + (int64_t)k * ldu, n, st);
+  } else {
+    pe::launch_superpose(u0, v, P, n, n_out, ldv, u, ldu, st);
+  }
+  HCK(hipGetLastError());
+  HCK(hipStreamSynchronize(st));
+  return PE_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,75 @@
+"""The C ABI library loads, exports every symbol declared in include/paraexp.h, and its
+structs have the same layout in C and in the ctypes binding.  CPU only: no compute calls."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "paraexp.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^(?:pe_status|const char\*)\s+(pe_[a-z_]+)\s*\(", text, re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_1509_04567_amd as pe
+    lib = pe.load_library()
+    names = declared_functions()
+    assert len(names) >= 9
+    for name in names:
+        assert hasattr(lib, name), name
+    assert sorted(pe.EXPORTED) == names
+    assert lib.pe_version().startswith(b"paraexp-gfx950")
+
+
+def test_struct_layout_matches_c(tmp_path):
+    import paper_1509_04567_amd.binding as b
+    fields = {"pe_problem": (b.PeProblem, ["op", "u0", "t0", "t1", "t_samples", "s", "G", "ldG", "shift",
+                                           "t_out", "n_out", "out", "ldOut", "krylov_steps", "rank_max", "q_max",
+                                           "tol", "svd_tol", "fit_tol", "prec"]),
+              "pe_report": (b.PeReport, [f for f, _ in b.PeReport._fields_]),
+              "pe_stencil": (b.PeStencil, ["n", "per_point", "coeffs"])}
+    src = ['#include "%s"' % HEADER, "#include <stdio.h>", "#include <stddef.h>", "int main(void){"]
+    for cname, (_, names) in fields.items():
+        src.append('printf("%%zu\\n", sizeof(%s));' % cname)
+        for f in names:
+            src.append('printf("%%zu\\n", offsetof(%s, %s));' % (cname, f))
+    src.append("return 0;}")
+    c = tmp_path / "layout.c"
+    c.write_text("\n".join(src))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", str(c), "-o", str(exe)], check=True)
+    out = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
+    i = 0
+    for cname, (cls, names) in fields.items():
+        assert out[i] == ctypes.sizeof(cls), cname
+        i += 1
+        for f in names:
+            assert out[i] == getattr(cls, f).offset, (cname, f)
+            i += 1
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    import paper_1509_04567_amd.binding as b
+    with pytest.raises(ImportError):
+        b._LIB_saved = b._LIB
+        b._LIB = None
+        try:
+            b.load_library(str(tmp_path / "nope.so"))
+        finally:
+            b._LIB = b._LIB_saved
+
+
+def test_no_oracle_import_in_product():
+    pkg = os.path.join(ROOT, "paper_1509_04567_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in text and "from oracle" not in text, f
+                assert "synth" not in text, f

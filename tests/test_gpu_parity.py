@@ -1,0 +1,173 @@
+"""Parity of the HIP path (through the C ABI) against the CPU oracle, on seeded inputs.
+
+Bars: the float64 path must match the oracle within 1e-10 relative L2 over all outputs
+(the stated FP64 target); the fp32-basis path within 1e-7.  The compressed source
+(U, p) is unique only up to a rotation of U, so compression is compared through
+rotation-invariant quantities: singular values, rank, polynomial terms, and the fitted
+source matrix B = U Pi (the source is B w(t))."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-10
+MIXED_TOL = 1e-7
+
+
+def rel(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1509_04567_amd as pe
+    c = pe.Context(0)
+    yield c
+    c.close()
+
+
+def gpu_out(t):
+    return t.detach().cpu().numpy().T          # (n, n_out)
+
+
+# ------------------------------------------------------------------ S0
+@pytest.mark.parametrize("n", [7, 256, 1000, 8192])
+@pytest.mark.parametrize("per_point", [False, True])
+def test_stencil_apply(ctx, n, per_point):
+    rng = np.random.default_rng(n)
+    X = rng.standard_normal((n, 5))
+    coeffs = synth.ade_coeffs(n, 1.0, 1e-3)
+    if per_point:
+        coeffs = coeffs[:, None] * (1.0 + 0.1 * rng.standard_normal((3, n)))
+    Y = ctx.stencil_apply(coeffs, X.T).cpu().numpy().T
+    ref = oracle.apply_stencil(coeffs, X)
+    assert rel(Y, ref) < 1e-14
+
+
+# ------------------------------------------------------------------ S1-S4
+@pytest.mark.parametrize("name", ["c1", "c2_1024", "rand_ragged"])
+def test_compress_matches_oracle(ctx, name):
+    if name == "c1":
+        p = synth.config_c1()
+    elif name == "c2_1024":
+        p = synth.config_c2(n=1024, s=64)
+    else:
+        p = synth.random_ade_problem(5, 333, modes=3, deg=4, s=30)
+    res = ctx.compress(p)
+    mdl = oracle.window_model(p)
+    assert res["m"] == mdl["m"]
+    assert res["q"] == mdl["q"]
+    m = mdl["m"]
+    assert np.allclose(res["sigma"][:m], mdl["sigma"][:m], rtol=1e-11, atol=0)
+    U = res["U"].cpu().numpy().T
+    assert np.max(np.abs(U.T @ U - np.eye(m))) < 1e-12
+    B = U @ res["Pi"].cpu().numpy()
+    assert rel(B, mdl["B"]) < 1e-10
+
+
+# ------------------------------------------------------------------ S5-S7 with the oracle's compressed source
+@pytest.mark.parametrize("name", ["c1", "rand_shift", "rand_noshift", "rand_perpoint"])
+def test_expaction_stage_parity(ctx, name):
+    if name == "c1":
+        p = synth.config_c1()
+    elif name == "rand_shift":
+        p = synth.random_ade_problem(11, 200, n_out=6)
+    elif name == "rand_noshift":
+        p = synth.random_ade_problem(12, 157, n_out=4, shift=False)
+    else:
+        p = synth.random_ade_problem(13, 190, per_point=True, n_out=4)
+    mdl = oracle.window_model(p)
+    ref, _ = oracle.solve_window(p, "dense", model=mdl)
+    outs, reps = ctx.expaction_batch([p], [mdl["U"].T], [mdl["Pi"]])
+    got = gpu_out(outs[0])
+    assert rel(got, ref) < FP64_TOL, reps[0]
+    assert reps[0]["cycles"] >= 1
+
+
+# ------------------------------------------------------------------ S1-S8 end to end
+def test_solve_c1_end_to_end(ctx):
+    p = synth.config_c1()
+    ref, mdl = oracle.solve_window(p, "dense")
+    outs, reps = ctx.solve_batch([p])
+    got = gpu_out(outs[0])
+    assert reps[0]["rank"] == 2 and reps[0]["q"] == mdl["q"]
+    assert rel(got, ref) < FP64_TOL, reps[0]
+    # worst single output time as well
+    per_t = np.linalg.norm(got - ref, axis=0) / np.linalg.norm(ref, axis=0)
+    assert per_t.max() < 10 * FP64_TOL
+
+
+def test_solve_batch_ragged_instances(ctx):
+    probs = synth.config_c4_subset(count=6)
+    outs, reps = ctx.solve_batch(probs)
+    for p, o, r in zip(probs, outs, reps):
+        ref, mdl = oracle.solve_window(p, "dense")
+        assert r["rank"] == mdl["m"]
+        assert rel(gpu_out(o), ref) < FP64_TOL, (p.name, p.n, r)
+
+
+def test_paraexp_windows_superposition(ctx):
+    rng = np.random.default_rng(21)
+    n = 180
+    u0, g_at = synth.smooth_field(rng, n, 3, 5)
+    t_out = np.array([0.1, 0.3, 0.5, 0.75, 1.0])
+    wins = synth.ade_windows(n, synth.ade_coeffs(n, 1.0, 5e-3), u0, g_at, 1.0, 4, 16, t_out, krylov_steps=16,
+                             rank_max=8, q_max=16, tol=1e-12, svd_tol=1e-13, fit_tol=1e-13)
+    outs, reps = ctx.solve_batch(wins)
+    u = ctx.superpose(u0, outs)
+    ref = oracle.solve_sequential(wins, "dense")
+    assert rel(gpu_out(u), ref) < FP64_TOL
+
+
+def test_happy_breakdown_fourier_pair(ctx):
+    n, k = 128, 3
+    x = synth.grid(n)
+    ts = synth.chebyshev_lobatto(0.0, 0.5, 12)
+    G = np.outer(np.cos(2 * np.pi * k * x), 1.0 + ts) + np.outer(np.sin(2 * np.pi * k * x), ts**2)
+    p = synth.Problem(n=n, coeffs=synth.ade_coeffs(n, 1.0, 1e-2), u0=np.cos(2 * np.pi * k * x), t0=0.0, t1=0.5,
+                      t_samples=ts, G=G, t_out=np.array([0.25, 0.5, 0.8]), shift=False, krylov_steps=6,
+                      rank_max=4, q_max=8, tol=1e-12)
+    ref, mdl = oracle.solve_window(p, "dense")
+    outs, reps = ctx.solve_batch([p])
+    assert rel(gpu_out(outs[0]), ref) < 1e-12
+
+
+def test_zero_source_and_times_before_window(ctx):
+    n = 64
+    x = synth.grid(n)
+    ts = synth.chebyshev_lobatto(0.5, 1.0, 6)
+    p = synth.Problem(n=n, coeffs=synth.ade_coeffs(n, 1.0, 1e-2), u0=np.exp(-((x - 0.5) / 0.1) ** 2), t0=0.5,
+                      t1=1.0, t_samples=ts, G=np.zeros((n, 6)), t_out=np.array([0.2, 0.5, 0.7, 1.3]), shift=True,
+                      krylov_steps=8, rank_max=4, q_max=6, tol=1e-12)
+    ref, mdl = oracle.solve_window(p, "dense")
+    outs, _ = ctx.solve_batch([p])
+    got = gpu_out(outs[0])
+    assert np.all(got[:, 0] == 0.0)
+    assert rel(got, ref) < FP64_TOL
+
+
+def test_nonfinite_input_is_an_error(ctx):
+    import paper_1509_04567_amd as pe
+    p = synth.random_ade_problem(3, 64)
+    p.u0 = p.u0.copy()
+    p.u0[5] = np.nan
+    with pytest.raises(pe.PeError) as ei:
+        ctx.solve_batch([p])
+    assert ei.value.status == -2
+
+
+# ------------------------------------------------------------------ the 8192-point workload
+def test_c2_full_size_fp64(ctx):
+    p = synth.config_c2()
+    ref, mdl = oracle.solve_window(p, "spectral")
+    outs, reps = ctx.solve_batch([p])
+    assert reps[0]["rank"] == 7 and reps[0]["q"] == 7
+    assert rel(gpu_out(outs[0]), ref) < FP64_TOL, reps[0]
