@@ -292,6 +292,18 @@ class Context:
         self._check(self.lib.pe_solve_batch(self.h, arr, len(dps), reps, _stream_ptr()))
         return [d.out for d in dps], [r.as_dict() for r in reps]
 
+    def prepare(self, problems: Sequence, precision: int = PE_FP64):
+        """Stage a batch on the device once (for repeated solves, e.g. benchmarking)."""
+        dps = [make_problem(p, self.device, precision) for p in problems]
+        arr = (PeProblem * len(dps))(*[d.struct for d in dps])
+        return dict(dps=dps, arr=arr, reps=(PeReport * len(dps))())
+
+    def solve_prepared(self, staged, stream=None):
+        """pe_solve_batch on a staged batch; outputs land in staged['dps'][i].out."""
+        self._check(self.lib.pe_solve_batch(self.h, staged["arr"], len(staged["dps"]), staged["reps"],
+                                            _stream_ptr(stream)))
+        return [d.out for d in staged["dps"]], [r.as_dict() for r in staged["reps"]]
+
     # -- S5-S8 with a given compressed source
     def expaction_batch(self, problems: Sequence, Us: Sequence, Pis: Sequence, precision: int = PE_FP64):
         """Us[i]: torch (m, n) rows = columns of U; Pis[i]: (m, q) numpy/torch Chebyshev coefficients."""

@@ -46,6 +46,7 @@ struct ProbDev {
   int64_t ldXg;
 
   double* xstate;          // writable state (same buffer as x)
+  const double* yacc;      // accepted projected solution y (l*bw entries used)
   double* outcol;          // output column to receive the new state, or null
   int32_t proj;            // 1: project the state with this cycle's accepted y
 
@@ -58,6 +59,9 @@ struct ProbDev {
   int32_t rows_p;          // rows per projection chunk
   int32_t Cp;              // number of projection chunks
 };
+
+// squaring levels whose exponential actions are evaluated in one trial
+#define PE_MAX_LEVELS 40
 
 struct ExpmDev {
   int32_t N;               // dimension of the augmented projected matrix (l*bw + q)
@@ -76,8 +80,8 @@ struct ExpmDev {
   double* P;
   double* T;
   double* b;               // N: initial projected vector
-  double* y;               // N: exp(delta Ht) b
-  double* out;             // 2 doubles: error estimate, |y[0:lbw]|
+  double* y;               // (kMaxLevels+1) x N: exp(alpha 2^k Ht) b for squaring level k
+  double* out;             // 2 (kMaxLevels+1): per level error estimate, |y[0:lbw]|
   const double* H;         // Arnoldi Hessenberg, column-major, ldH
   int64_t ldH;
   const double* R0;        // bw x bw row-major: [U | x] = V_0 R0

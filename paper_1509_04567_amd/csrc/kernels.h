@@ -9,7 +9,9 @@ namespace pe {
 enum BlockMode : int { MODE_ARNOLDI = 0, MODE_GIVEN = 1, MODE_INIT = 2 };
 
 // dynamic LDS requested by the update kernel at most (bytes)
-constexpr int kUpdateLdsMax = 64 * 1024;
+constexpr int kUpdateLdsMax = 150 * 1024;
+// slot group handled by one projection workgroup
+constexpr int kSlotGroup = 2;
 
 // Y[:, c] = L X[:, c]
 void launch_stencil_cols(int64_t n, int per_point, const double* c3, const double* coef, const double* X,
@@ -27,10 +29,10 @@ void launch_block_commit(ProbDev* d, int nprob, int grid_x, int j, int mixed, hi
 
 // exponential of the projected augmented matrix
 void launch_build_aug(ExpmDev* e, int nprob, int64_t maxNN, hipStream_t st);
-void launch_norm1(ExpmDev* e, double* out, int nprob, hipStream_t st);
+void launch_norm1(ExpmDev* e, double* out, int nprob, int maxN, hipStream_t st);
 void launch_elementwise(ExpmDev* e, int op, int nprob, int64_t maxNN, hipStream_t st);
 void launch_gemm(ExpmDev* e, int op, int k, int nprob, int tiles_max, hipStream_t st);
-void launch_expm_apply(ExpmDev* e, int nprob, int maxN, hipStream_t st);
+void launch_expm_apply(ExpmDev* e, int level, int nprob, int maxN, hipStream_t st);
 
 // x = V y (+ output column)
 void launch_project(ProbDev* d, ExpmDev* e, int nprob, int64_t maxn, int max_lbw, int mixed, hipStream_t st);

@@ -23,10 +23,27 @@ namespace pe {
 // ------------------------------------------------------------------------------------
 // reductions and helpers
 // ------------------------------------------------------------------------------------
+// DPP data movement of a double (both 32-bit halves); rows outside row_mask receive 0
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_move(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROW_MASK, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROW_MASK, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum over the 64 lanes of a wave, returned to every lane.  Within each row of 16 lanes:
+// quad_perm [1,0,3,2], quad_perm [2,3,0,1], row_ror 4, row_ror 8; then row_bcast 15 into
+// rows 1 and 3 and row_bcast 31 into rows 2 and 3, which leaves the total in lane 63.
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+  v += dpp_move<0xB1, 0xF>(v);
+  v += dpp_move<0x4E, 0xF>(v);
+  v += dpp_move<0x124, 0xF>(v);
+  v += dpp_move<0x128, 0xF>(v);
+  v += dpp_move<0x142, 0xA>(v);
+  v += dpp_move<0x143, 0xC>(v);
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+  return __hiloint2double(hi, lo);
 }
 
 // sum over a workgroup whose size is a multiple of 64; `red` holds >= 16 doubles of LDS
@@ -113,7 +130,7 @@ __device__ __forceinline__ double tsqr_entry(const ProbDev& p, const double* Qlo
 // replacement directions of the chunk factors in a TSQR combine.
 #define PE_DEP_TOL 1e-12
 template <bool BLOCK, typename Ptr>
-__device__ void mgs2_qr(Ptr X, int rows, int ld, int bw, double* R, uint64_t seed, double* red, const double* ref,
+__device__ __forceinline__ void mgs2_qr(Ptr X, int rows, int ld, int bw, double* R, uint64_t seed, double* red, const double* ref,
                         int stack) {
   const int T = BLOCK ? (int)blockDim.x : 64;
   const int t = BLOCK ? (int)threadIdx.x : (int)(threadIdx.x & 63);
@@ -173,6 +190,214 @@ __device__ void mgs2_qr(Ptr X, int rows, int ld, int bw, double* R, uint64_t see
   }
 }
 
+// Classical Gram-Schmidt applied twice, column by column, by one wave (TSQR chunk and
+// combine QR).  All dot products of a column with the previous columns are reduced
+// together, so a column costs three dependent wave reductions instead of 2b+1.
+// Dependence test and replacement as in mgs2_qr (bw <= 32).
+__device__ __forceinline__ void cgs2_qr_wave(double* X, int rows, int ld, int bw, double* R, uint64_t seed, const double* ref,
+                             int stack) {
+  const int t = threadIdx.x & 63;
+  for (int b = 0; b < bw; ++b) {
+    const double n0 = ref[b];
+    const int npass = 2;
+    for (int pass = 0; pass < npass; ++pass) {
+      double sd[32];
+#pragma unroll
+      for (int a = 0; a < 32; ++a) sd[a] = 0.0;
+      for (int r = t; r < rows; r += 64) {
+        const double xb = X[r * ld + b];
+#pragma unroll
+        for (int a = 0; a < 32; ++a)
+          if (a < b) sd[a] += X[r * ld + a] * xb;
+      }
+#pragma unroll
+      for (int a = 0; a < 32; ++a)
+        if (a < b) sd[a] = wave_sum(sd[a]);
+      for (int r = t; r < rows; r += 64) {
+        double acc = X[r * ld + b];
+#pragma unroll
+        for (int a = 0; a < 32; ++a)
+          if (a < b) acc -= sd[a] * X[r * ld + a];
+        X[r * ld + b] = acc;
+      }
+      if (t == 0) {
+#pragma unroll
+        for (int a = 0; a < 32; ++a)
+          if (a < b) R[a * bw + b] += sd[a];
+      }
+    }
+    double s1 = 0.0;
+    for (int r = t; r < rows; r += 64) s1 += X[r * ld + b] * X[r * ld + b];
+    const double nr = sqrt(wave_sum(s1));
+    if (nr > PE_DEP_TOL * n0 && nr > 1e-300) {
+      const double inv = 1.0 / nr;
+      for (int r = t; r < rows; r += 64) X[r * ld + b] *= inv;
+      if (t == 0) R[b * bw + b] = nr;
+    } else {
+      if (t == 0) R[b * bw + b] = 0.0;
+      for (int r = t; r < rows; r += 64)
+        X[r * ld + b] = (stack > 0 && (r % stack) != b) ? 0.0 : hash_unit(seed + (uint64_t)r, (uint64_t)b);
+      for (int pass = 0; pass < 3; ++pass) {
+        double sd[32];
+#pragma unroll
+        for (int a = 0; a < 32; ++a) sd[a] = 0.0;
+        for (int r = t; r < rows; r += 64) {
+          const double xb = X[r * ld + b];
+#pragma unroll
+          for (int a = 0; a < 32; ++a)
+            if (a < b) sd[a] += X[r * ld + a] * xb;
+        }
+#pragma unroll
+        for (int a = 0; a < 32; ++a)
+          if (a < b) sd[a] = wave_sum(sd[a]);
+        for (int r = t; r < rows; r += 64) {
+          double acc = X[r * ld + b];
+#pragma unroll
+          for (int a = 0; a < 32; ++a)
+            if (a < b) acc -= sd[a] * X[r * ld + a];
+          X[r * ld + b] = acc;
+        }
+      }
+      double s2 = 0.0;
+      for (int r = t; r < rows; r += 64) s2 += X[r * ld + b] * X[r * ld + b];
+      const double n2 = sqrt(wave_sum(s2));
+      const double inv = n2 > 0.0 ? 1.0 / n2 : 0.0;
+      for (int r = t; r < rows; r += 64) X[r * ld + b] *= inv;
+    }
+  }
+}
+
+// Register-resident CGS2 QR of a rows x bw array (LDS, leading dimension ld) by a team
+// of NW waves (NW = 1: no barriers; NW > 1: the whole workgroup, barriers inside).
+// Thread t of the team keeps rows t + 64 NW q, q < RPL, in registers; column loops are
+// unrolled to BWM >= bw so register indices are compile-time constants.  Dependence
+// test and replacement as in mgs2_qr.  `red` is LDS scratch of NW * BWM doubles.
+template <int BWM, int RPL, int NW>
+__device__ __forceinline__ void cgs2_team(double* X, int rows, int ld, int bw, double* R, uint64_t seed,
+                                          const double* ref, int stack, double* red) {
+  const int t = (NW == 1) ? (int)(threadIdx.x & 63) : (int)threadIdx.x;
+  const int w = t >> 6;
+  constexpr int T = 64 * NW;
+  double xr[RPL][BWM];
+#pragma unroll
+  for (int q = 0; q < RPL; ++q) {
+    const int r = t + T * q;
+#pragma unroll
+    for (int a = 0; a < BWM; ++a) xr[q][a] = (a < bw && r < rows) ? X[r * ld + a] : 0.0;
+  }
+  // sum over the team of NA values (NA known at compile time); result in sd[]
+  auto team_sums = [&](double* sd, int NA) {
+#pragma unroll
+    for (int a = 0; a < BWM; ++a)
+      if (a < NA) sd[a] = wave_sum(sd[a]);
+    if (NW > 1) {
+      __syncthreads();
+      if ((t & 63) == 0)
+#pragma unroll
+        for (int a = 0; a < BWM; ++a)
+          if (a < NA) red[w * BWM + a] = sd[a];
+      __syncthreads();
+#pragma unroll
+      for (int a = 0; a < BWM; ++a)
+        if (a < NA) {
+          double v = 0.0;
+          for (int ww = 0; ww < NW; ++ww) v += red[ww * BWM + a];
+          sd[a] = v;
+        }
+    }
+  };
+#pragma unroll
+  for (int b = 0; b < BWM; ++b) {
+    if (b < bw) {
+      const double n0 = ref[b];
+#pragma unroll
+      for (int pass = 0; pass < 2; ++pass) {
+        double sd[BWM];
+#pragma unroll
+        for (int a = 0; a < BWM; ++a) sd[a] = 0.0;
+#pragma unroll
+        for (int q = 0; q < RPL; ++q)
+#pragma unroll
+          for (int a = 0; a < b; ++a) sd[a] += xr[q][a] * xr[q][b];
+        team_sums(sd, b);
+#pragma unroll
+        for (int q = 0; q < RPL; ++q)
+#pragma unroll
+          for (int a = 0; a < b; ++a) xr[q][b] -= sd[a] * xr[q][a];
+        if (t == 0)
+#pragma unroll
+          for (int a = 0; a < b; ++a) R[a * bw + b] += sd[a];
+      }
+      double nn[BWM];
+      nn[0] = 0.0;
+#pragma unroll
+      for (int q = 0; q < RPL; ++q) nn[0] += xr[q][b] * xr[q][b];
+      team_sums(nn, 1);
+      const double nr = sqrt(nn[0]);
+      if (nr > PE_DEP_TOL * n0 && nr > 1e-300) {
+        const double inv = 1.0 / nr;
+#pragma unroll
+        for (int q = 0; q < RPL; ++q) xr[q][b] *= inv;
+        if (t == 0) R[b * bw + b] = nr;
+      } else {
+        if (t == 0) R[b * bw + b] = 0.0;
+#pragma unroll
+        for (int q = 0; q < RPL; ++q) {
+          const int r = t + T * q;
+          xr[q][b] = (r >= rows || (stack > 0 && (r % stack) != b)) ? 0.0 : hash_unit(seed + (uint64_t)r, (uint64_t)b);
+        }
+#pragma unroll
+        for (int pass = 0; pass < 3; ++pass) {
+          double sd[BWM];
+#pragma unroll
+          for (int a = 0; a < BWM; ++a) sd[a] = 0.0;
+#pragma unroll
+          for (int q = 0; q < RPL; ++q)
+#pragma unroll
+            for (int a = 0; a < b; ++a) sd[a] += xr[q][a] * xr[q][b];
+          team_sums(sd, b);
+#pragma unroll
+          for (int q = 0; q < RPL; ++q)
+#pragma unroll
+            for (int a = 0; a < b; ++a) xr[q][b] -= sd[a] * xr[q][a];
+        }
+        double m2[BWM];
+        m2[0] = 0.0;
+#pragma unroll
+        for (int q = 0; q < RPL; ++q) m2[0] += xr[q][b] * xr[q][b];
+        team_sums(m2, 1);
+        const double inv = m2[0] > 0.0 ? 1.0 / sqrt(m2[0]) : 0.0;
+#pragma unroll
+        for (int q = 0; q < RPL; ++q) xr[q][b] *= inv;
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < RPL; ++q) {
+    const int r = t + T * q;
+    if (r < rows)
+#pragma unroll
+      for (int a = 0; a < BWM; ++a)
+        if (a < bw) X[r * ld + a] = xr[q][a];
+  }
+}
+
+// dispatch of the register-resident QR over block-width buckets and rows per thread
+template <int NW>
+__device__ __forceinline__ bool cgs2_dispatch(double* X, int rows, int ld, int bw, double* R, uint64_t seed,
+                                              const double* ref, int stack, double* red) {
+  const int rpl = (rows + 64 * NW - 1) / (64 * NW);
+  if (bw <= 8) {
+    if (rpl <= 1) { cgs2_team<8, 1, NW>(X, rows, ld, bw, R, seed, ref, stack, red); return true; }
+    if (rpl <= 2) { cgs2_team<8, 2, NW>(X, rows, ld, bw, R, seed, ref, stack, red); return true; }
+    if (rpl <= 4) { cgs2_team<8, 4, NW>(X, rows, ld, bw, R, seed, ref, stack, red); return true; }
+  } else if (bw <= 16) {
+    if (rpl <= 1) { cgs2_team<16, 1, NW>(X, rows, ld, bw, R, seed, ref, stack, red); return true; }
+    if (rpl <= 2) { cgs2_team<16, 2, NW>(X, rows, ld, bw, R, seed, ref, stack, red); return true; }
+  }
+  return false;  // wider blocks use the LDS-resident cgs2_qr_wave
+}
+
 // ------------------------------------------------------------------------------------
 // S0: Y = L X, column-major blocks
 // ------------------------------------------------------------------------------------
@@ -216,242 +441,282 @@ void launch_add_column(int64_t n, int s, const double* G, int64_t ldG, const dou
 }
 
 // ------------------------------------------------------------------------------------
-// Block orthogonalisation: projection partials  S_i = V_i^T X  (i < nb)
-//   pass 0, MODE_ARNOLDI: X = L V_j with V_j = TSQR(pass-2 buffers) formed on the fly;
-//                         slot-0 workgroups commit V_j to the basis
-//   pass 0, MODE_GIVEN:   X = columns [j*bw, j*bw+bw) of the given matrix
-//   pass 1:               X = Q1 of the pass-0 TSQR, formed on the fly
-// Grid: x = nb*Cp (slot, chunk), y = problem.  The last workgroup of a slot reduces the
-// Cp partials into S[pass][slot].
+// Block orthogonalisation.  Per block step and pass:
+//   k_block_proj:   S_i = V_i^T X over row chunks, for a group of GS slots per workgroup;
+//                   the last workgroup of a group reduces the chunk partials into S.
+//   k_block_update: X -= sum_i V_i S_i on one row chunk, wave-level MGS2 of the chunk,
+//                   and the TSQR combine by the last workgroup.
+// The input block X of a pass is
+//   pass 0, MODE_ARNOLDI: W = L V_j, V_j given by the previous TSQR (Qloc2, Qs2);
+//                         the projection kernel commits V_j to the basis
+//   pass 0, MODE_GIVEN:   columns [j*bw, j*bw + bw) of the given matrix
+//   pass 0, MODE_INIT:    [U | x]
+//   pass 1:               Q1 of the pass-0 TSQR (Qloc1, Qs1)
 // ------------------------------------------------------------------------------------
+
+
+// Stage the Qs blocks that rows [g_lo, g_hi] (inclusive, no wrap) need into LDS.
+__device__ __forceinline__ int stage_qs(const ProbDev& p, const double* Qs, int64_t g_lo, int64_t g_hi, double* Qsl) {
+  const int bw2 = p.bw * p.bw;
+  const int u_lo = chunk_of(p, g_lo), u_hi = chunk_of(p, g_hi);
+  const int cnt = (u_hi - u_lo + 1) * bw2;
+  for (int e = threadIdx.x; e < cnt; e += blockDim.x) Qsl[e] = Qs[(int64_t)u_lo * bw2 + e];
+  return u_lo;
+}
+
+// X (rows x bw, leading dimension ld, LDS) for rows [r0, r0 + rows) of the current pass.
+// In MODE_ARNOLDI pass 0 with from_tsqr, V_j rows r0-1 .. r0+rows are formed into Vh
+// (rows + 2 rows, LDS) and, when commit, written to basis block j.
+template <typename TS>
+__device__ __forceinline__ void form_block(const ProbDev& p, int mode, int pass, int j, int64_t r0, int rows, double* X, int ld,
+                           double* Vh, double* Qsl, bool from_tsqr, bool commit) {
+  const int bw = p.bw, bw2 = bw * bw;
+  const int t = threadIdx.x, T = blockDim.x;
+  const int64_t n = p.n;
+  TS* V = basis_ptr<TS>(p);
+  const int64_t blk = n * bw;
+  if (mode == MODE_INIT) {
+    for (int e = t; e < rows * bw; e += T) {
+      const int rr = e / bw, col = e % bw;
+      const int64_t g = r0 + rr;
+      X[rr * ld + col] = col < p.m ? p.U[(int64_t)col * n + g] : p.x[g];
+    }
+  } else if (pass == 0 && mode == MODE_GIVEN) {
+    for (int e = t; e < rows * bw; e += T) {
+      const int rr = e / bw, col = e % bw;
+      const int gc = j * bw + col;
+      X[rr * ld + col] = gc < p.m ? p.Xg[(int64_t)gc * p.ldXg + r0 + rr] : 0.0;
+    }
+  } else if (pass == 0) {  // MODE_ARNOLDI: W = L V_j
+    if (from_tsqr) {
+      const int u_lo = stage_qs(p, p.Qs2, r0, r0 + rows - 1, Qsl);
+      __syncthreads();
+      for (int e = t; e < (rows + 2) * bw; e += T) {
+        const int rr = e / bw, col = e % bw;
+        int64_t g = r0 - 1 + rr;
+        double v;
+        if (rr >= 1 && rr <= rows) {
+          const double* q = p.Qloc2 + g * bw;
+          const double* sq = Qsl + (int64_t)(chunk_of(p, g) - u_lo) * bw2 + col;
+          v = 0.0;
+          for (int k = 0; k < bw; ++k) v += q[k] * sq[k * bw];
+        } else {
+          if (g < 0) g += n;
+          if (g >= n) g -= n;
+          v = tsqr_entry(p, p.Qloc2, p.Qs2, g, col);
+        }
+        const TS vs = (TS)v;
+        Vh[rr * ld + col] = (double)vs;
+        if (commit && rr >= 1 && rr <= rows) V[(int64_t)j * blk + g * bw + col] = vs;
+      }
+      __syncthreads();
+      for (int e = t; e < rows * bw; e += T) {
+        const int rr = e / bw, col = e % bw;
+        double cm, cz, cp;
+        stencil_coefs(p, r0 + rr, cm, cz, cp);
+        X[rr * ld + col] = cm * Vh[rr * ld + col] + cz * Vh[(rr + 1) * ld + col] + cp * Vh[(rr + 2) * ld + col];
+      }
+    } else {
+      const TS* vj = V + (int64_t)j * blk;
+      for (int e = t; e < rows * bw; e += T) {
+        const int rr = e / bw, col = e % bw;
+        const int64_t g = r0 + rr;
+        const int64_t gm = g == 0 ? n - 1 : g - 1, gp = g == n - 1 ? 0 : g + 1;
+        double cm, cz, cp;
+        stencil_coefs(p, g, cm, cz, cp);
+        X[rr * ld + col] =
+            cm * (double)vj[gm * bw + col] + cz * (double)vj[g * bw + col] + cp * (double)vj[gp * bw + col];
+      }
+    }
+  } else {  // pass 1: X = Q1
+    const int u_lo = stage_qs(p, p.Qs1, r0, r0 + rows - 1, Qsl);
+    __syncthreads();
+    for (int e = t; e < rows * bw; e += T) {
+      const int rr = e / bw, col = e % bw;
+      const int64_t g = r0 + rr;
+      const double* q = p.Qloc1 + g * bw;
+      const double* sq = Qsl + (int64_t)(chunk_of(p, g) - u_lo) * bw2 + col;
+      double v = 0.0;
+      for (int k = 0; k < bw; ++k) v += q[k] * sq[k * bw];
+      X[rr * ld + col] = v;
+    }
+  }
+  __syncthreads();
+}
+
 template <typename TS>
 __global__ __launch_bounds__(256) void k_block_proj(ProbDev* probs, int j, int nb, int pass, int mode) {
   const ProbDev& p = probs[blockIdx.y];
   if (!p.active || j >= p.l) return;
-  const int bw = p.bw;
-  const int slot = blockIdx.x / p.Cp;
+  const int bw = p.bw, nout = bw * bw;
+  const int grp = blockIdx.x / p.Cp;
   const int c = blockIdx.x % p.Cp;
-  if (slot >= nb) return;
+  const int ngroups = (nb + kSlotGroup - 1) / kSlotGroup;
+  if (grp >= ngroups) return;
   const int64_t n = p.n;
   const int64_t r0 = (int64_t)c * p.rows_p;
   if (r0 >= n) return;
-  const int64_t r1 = r0 + p.rows_p < n ? r0 + p.rows_p : n;
-  const int rows = (int)(r1 - r0);
+  const int rows = (int)(r0 + p.rows_p < n ? p.rows_p : n - r0);
   const int ld = bw + 1;
   const int t = threadIdx.x;
   extern __shared__ double smem[];
-  double* Xs = smem;                                // rows_p * ld
-  double* Vh = Xs + (int64_t)p.rows_p * ld;         // (rows_p + 2) * ld : V_j with halo, or V_slot
-  double* red = Vh + (int64_t)(p.rows_p + 2) * ld;  // 256 * ... reduction scratch
+  double* Xs = smem;                                   // rows_p * ld
+  double* Vh = Xs + (int64_t)p.rows_p * ld;            // (rows_p + 2) * ld
+  double* Vs = Vh + (int64_t)(p.rows_p + 2) * ld;      // rows_p * ld
+  double* red = Vs + (int64_t)p.rows_p * ld;           // 256
+  double* Qsl = red + 256;                             // (rows_p / rows_u + 2) * bw^2
   __shared__ int is_last;
-  TS* V = basis_ptr<TS>(p);
+  const TS* V = basis_ptr<TS>(p);
   const int64_t blk = n * bw;
   const bool arn0 = (mode == MODE_ARNOLDI && pass == 0);
+  form_block<TS>(p, mode, pass, j, r0, rows, Xs, ld, Vh, Qsl, true, arn0 && grp == 0);
 
-  if (arn0) {
-    // V_j rows r0-1 .. r1 (periodic), from the TSQR that produced block j
-    const int tot = (rows + 2) * bw;
-    for (int e = t; e < tot; e += blockDim.x) {
-      const int rr = e / bw, col = e % bw;
-      int64_t g = r0 - 1 + rr;
-      if (g < 0) g += n;
-      if (g >= n) g -= n;
-      const double v = tsqr_entry(p, p.Qloc2, p.Qs2, g, col);
-      Vh[rr * ld + col] = v;
-      if (slot == 0 && rr >= 1 && rr <= rows) V[(int64_t)j * blk + (r0 + rr - 1) * bw + col] = (TS)v;
+  double* part = p.Part + (int64_t)pass * p.Cp * p.nbmax * nout;
+  const int i_lo = grp * kSlotGroup, i_hi = min(nb, i_lo + kSlotGroup);
+  for (int i = i_lo; i < i_hi; ++i) {
+    const double* Vi;
+    if (arn0 && i == j) {
+      Vi = Vh + ld;  // rows 1..rows of the halo block
+    } else {
+      const TS* src = V + (int64_t)i * blk + r0 * bw;
+      for (int e = t; e < rows * bw; e += blockDim.x) Vs[(e / bw) * ld + (e % bw)] = (double)src[e];
+      __syncthreads();
+      Vi = Vs;
     }
-    __syncthreads();
-    for (int e = t; e < rows * bw; e += blockDim.x) {
-      const int rr = e / bw, col = e % bw;
-      double cm, cz, cp;
-      stencil_coefs(p, r0 + rr, cm, cz, cp);
-      Xs[rr * ld + col] = cm * Vh[rr * ld + col] + cz * Vh[(rr + 1) * ld + col] + cp * Vh[(rr + 2) * ld + col];
-    }
-  } else if (pass == 0) {  // MODE_GIVEN
-    for (int e = t; e < rows * bw; e += blockDim.x) {
-      const int rr = e / bw, col = e % bw;
-      const int gc = j * bw + col;
-      Xs[rr * ld + col] = gc < p.m ? p.Xg[(int64_t)gc * p.ldXg + r0 + rr] : 0.0;
-    }
-  } else {
-    for (int e = t; e < rows * bw; e += blockDim.x) {
-      const int rr = e / bw, col = e % bw;
-      Xs[rr * ld + col] = tsqr_entry(p, p.Qloc1, p.Qs1, r0 + rr, col);
-    }
-  }
-  // V_slot chunk (rows r0..r1) into Vh rows 1..rows unless it already is there
-  const bool have = arn0 && slot == j;
-  if (!have) {
-    __syncthreads();
-    for (int e = t; e < rows * bw; e += blockDim.x) {
-      const int rr = e / bw, col = e % bw;
-      Vh[(rr + 1) * ld + col] = (double)V[(int64_t)slot * blk + (r0 + rr) * bw + col];
-    }
-  }
-  __syncthreads();
-
-  // partial[a][b] = sum_r V[r][a] X[r][b]
-  const int nout = bw * bw;
-  double* part = p.Part + (int64_t)pass * p.Cp * p.nbmax * nout;  // capacity checked on host
-  double* mine = part + ((int64_t)slot * p.Cp + c) * nout;
-  if (nout <= 256) {
-    const int G = 256 / nout;
-    const int o = t % nout, g = t / nout;
-    double acc = 0.0;
-    if (g < G) {
-      const int a = o / bw, b = o % bw;
-      for (int rr = g; rr < rows; rr += G) acc += Vh[(rr + 1) * ld + a] * Xs[rr * ld + b];
-    }
-    __syncthreads();
-    if (g < G) red[g * nout + o] = acc;
-    __syncthreads();
-    if (t < nout) {
-      double s = 0.0;
-      for (int gg = 0; gg < G; ++gg) s += red[gg * nout + t];
-      mine[t] = s;
-    }
-  } else {
-    for (int o = t; o < nout; o += blockDim.x) {
-      const int a = o / bw, b = o % bw;
+    double* mine = part + ((int64_t)i * p.Cp + c) * nout;
+    if (nout <= 256) {
+      const int G = 256 / nout;
+      const int o = t % nout, g = t / nout;
       double acc = 0.0;
-      for (int rr = 0; rr < rows; ++rr) acc += Vh[(rr + 1) * ld + a] * Xs[rr * ld + b];
-      mine[o] = acc;
+      if (g < G) {
+        const int a = o / bw, b = o % bw;
+        for (int rr = g; rr < rows; rr += G) acc += Vi[rr * ld + a] * Xs[rr * ld + b];
+      }
+      if (g < G) red[g * nout + o] = acc;
+      __syncthreads();
+      if (t < nout) {
+        double sacc = 0.0;
+        for (int gg = 0; gg < G; ++gg) sacc += red[gg * nout + t];
+        mine[t] = sacc;
+      }
+    } else {
+      for (int o = t; o < nout; o += blockDim.x) {
+        const int a = o / bw, b = o % bw;
+        double acc = 0.0;
+        for (int rr = 0; rr < rows; ++rr) acc += Vi[rr * ld + a] * Xs[rr * ld + b];
+        mine[o] = acc;
+      }
     }
+    __syncthreads();
   }
-  // last workgroup of this slot reduces the Cp partials
+  // the last workgroup of this slot group reduces the Cp partials of its slots
   __threadfence();
   __syncthreads();
   if (t == 0) {
-    unsigned* cnt = p.cnt + pass * p.nbmax + slot;
-    const unsigned old = atomicAdd(cnt, 1u);
+    const unsigned old = atomicAdd(p.cnt + pass * p.nbmax + grp, 1u);
     is_last = (old == (unsigned)(p.Cp - 1));
   }
   __syncthreads();
   if (is_last) {
     __threadfence();
-    double* Sout = p.S + (int64_t)pass * p.nbmax * nout + (int64_t)slot * nout;
-    const double* ps = part + (int64_t)slot * p.Cp * nout;
-    for (int o = t; o < nout; o += blockDim.x) {
-      double s = 0.0;
-      for (int cc = 0; cc < p.Cp; ++cc) s += __builtin_nontemporal_load(ps + (int64_t)cc * nout + o);
-      Sout[o] = s;
+    double* Sout = p.S + (int64_t)pass * p.nbmax * nout;
+    for (int e = t; e < (i_hi - i_lo) * nout; e += blockDim.x) {
+      const int i = i_lo + e / nout, o = e % nout;
+      const double* ps = part + (int64_t)i * p.Cp * nout + o;
+      double sacc = 0.0;
+      for (int cc = 0; cc < p.Cp; ++cc) sacc += __builtin_nontemporal_load(ps + (int64_t)cc * nout);
+      Sout[(int64_t)i * nout + o] = sacc;
     }
-    if (t == 0) atomicExch(p.cnt + pass * p.nbmax + slot, 0u);
+    if (t == 0) atomicExch(p.cnt + pass * p.nbmax + grp, 0u);
   }
 }
 
-// ------------------------------------------------------------------------------------
-// Block orthogonalisation: update + local QR + TSQR combine.
-//   X chunk (as in k_block_proj; MODE_INIT: X = [U | x]) minus sum_i V_i S[pass][i],
-//   then MGS2 of the chunk -> Qloc_pass, Rloc[u]; the last workgroup QR-factorises the
-//   stacked Rloc -> Qs_pass, Rf[pass] and (second pass) writes the Hessenberg column.
-// Grid: x = Cu, y = problem.  One wave per workgroup.
-// ------------------------------------------------------------------------------------
+// slots of the projections subtracted per LDS batch in the update kernel
+__host__ __device__ __forceinline__ int update_batch_slots(int bw, int rows_u) {
+  int k = 8192 / (bw * bw + 2 * rows_u * bw);
+  return k < 1 ? 1 : (k > 8 ? 8 : k);
+}
+
 template <typename TS>
-__global__ __launch_bounds__(64) void k_block_update(ProbDev* probs, int j, int nb, int pass, int mode) {
+__global__ __launch_bounds__(256) void k_block_update(ProbDev* probs, int j, int nb, int pass, int mode) {
   const ProbDev& p = probs[blockIdx.y];
   if (!p.active || (mode != MODE_INIT && j >= p.l)) return;
-  const int bw = p.bw;
+  const int bw = p.bw, nout = bw * bw;
   const int u = blockIdx.x;
   if (u >= p.Cu) return;
   const int64_t n = p.n;
   const int64_t r0 = (int64_t)u * p.rows_u;
   const int64_t r1 = (u == p.Cu - 1) ? n : r0 + p.rows_u;
   const int rows = (int)(r1 - r0);
+  const int rmax = 2 * p.rows_u;
   const int ld = bw + 1;
-  const int t = threadIdx.x;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int KS = update_batch_slots(bw, p.rows_u);
   extern __shared__ double smem[];
-  // X region holds the chunk (< 2*rows_u rows) and later the stacked R factors (Cu*bw rows)
-  const int64_t xs_cap = (int64_t)ld * ((int64_t)2 * p.rows_u > (int64_t)p.Cu * bw ? (int64_t)2 * p.rows_u
-                                                                                  : (int64_t)p.Cu * bw);
-  double* X = smem;
-  double* Ss = X + xs_cap;                           // bw*bw
-  double* Rl = Ss + bw * bw;                         // bw*bw
+  const int64_t xs_cap = (int64_t)ld * (rmax > p.Cu * bw ? rmax : p.Cu * bw);
+  double* X = smem;                               // xs_cap
+  double* Sb = X + xs_cap;                        // KS * bw^2
+  double* Vb = Sb + (int64_t)KS * nout;           // KS * rmax * bw
+  double* Rl = Vb + (int64_t)KS * rmax * bw;      // bw^2
+  double* Rn = Rl + nout;                         // bw
+  double* Qsl = Rn + bw;                          // bw^2 (one chunk's combine factor)
   __shared__ int is_last;
-  TS* V = basis_ptr<TS>(p);
+  const TS* V = basis_ptr<TS>(p);
   const int64_t blk = n * bw;
 
-  // 1. X chunk
-  if (mode == MODE_INIT) {
-    for (int e = t; e < rows * bw; e += 64) {
-      const int rr = e / bw, col = e % bw;
-      const int64_t g = r0 + rr;
-      X[rr * ld + col] = col < p.m ? p.U[(int64_t)col * n + g] : p.x[g];
-    }
-  } else if (pass == 0 && mode == MODE_ARNOLDI) {
-    for (int e = t; e < rows * bw; e += 64) {
-      const int rr = e / bw, col = e % bw;
-      const int64_t g = r0 + rr;
-      const int64_t gm = g == 0 ? n - 1 : g - 1, gp = g == n - 1 ? 0 : g + 1;
-      double cm, cz, cp;
-      stencil_coefs(p, g, cm, cz, cp);
-      const TS* vj = V + (int64_t)j * blk;
-      X[rr * ld + col] = cm * (double)vj[gm * bw + col] + cz * (double)vj[g * bw + col] + cp * (double)vj[gp * bw + col];
-    }
-  } else if (pass == 0) {  // MODE_GIVEN
-    for (int e = t; e < rows * bw; e += 64) {
-      const int rr = e / bw, col = e % bw;
-      const int gc = j * bw + col;
-      X[rr * ld + col] = gc < p.m ? p.Xg[(int64_t)gc * p.ldXg + r0 + rr] : 0.0;
-    }
-  } else {
-    for (int e = t; e < rows * bw; e += 64) {
-      const int rr = e / bw, col = e % bw;
-      X[rr * ld + col] = tsqr_entry(p, p.Qloc1, p.Qs1, r0 + rr, col);
-    }
-  }
-  __syncthreads();
-  // reference column norms of the chunk before the block projections
-  double* Rn = Rl + bw * bw;                         // bw: chunk reference norms, then global
-  for (int b = 0; b < bw; ++b) {
+  // 1. input block of this chunk
+  form_block<TS>(p, mode, pass, j, r0, rows, X, ld, nullptr, Qsl, false, false);
+  // reference column norms before the projections
+  for (int b = w; b < bw; b += 4) {
     double s0 = 0.0;
-    for (int rr = t; rr < rows; rr += 64) s0 += X[rr * ld + b] * X[rr * ld + b];
+    for (int rr = lane; rr < rows; rr += 64) s0 += X[rr * ld + b] * X[rr * ld + b];
     s0 = wave_sum(s0);
-    if (t == 0) {
+    if (lane == 0) {
       Rn[b] = sqrt(s0);
       p.Cn[(int64_t)u * bw + b] = s0;
     }
   }
-  __syncthreads();
-  // 2. subtract projections
-  const int nout = bw * bw;
+  // 2. X -= sum_i V_i S_i, KS slots per LDS batch
   if (mode != MODE_INIT) {
     const double* Sp = p.S + (int64_t)pass * p.nbmax * nout;
-    for (int i = 0; i < nb; ++i) {
-      for (int o = t; o < nout; o += 64) Ss[o] = Sp[(int64_t)i * nout + o];
+    for (int i0 = 0; i0 < nb; i0 += KS) {
+      const int k = min(KS, nb - i0);
       __syncthreads();
-      const TS* vi = V + (int64_t)i * blk;
-      for (int rr = t; rr < rows; rr += 64) {
-        const TS* vrow = vi + (r0 + rr) * bw;
-        for (int b = 0; b < bw; ++b) {
-          double acc = X[rr * ld + b];
-          for (int a = 0; a < bw; ++a) acc -= (double)vrow[a] * Ss[a * bw + b];
-          X[rr * ld + b] = acc;
-        }
+      for (int e = t; e < k * nout; e += 256) Sb[e] = Sp[(int64_t)i0 * nout + e];
+      for (int kk = 0; kk < k; ++kk) {
+        const TS* src = V + (int64_t)(i0 + kk) * blk + r0 * bw;
+        for (int e = t; e < rows * bw; e += 256) Vb[(int64_t)kk * rmax * bw + e] = (double)src[e];
       }
       __syncthreads();
+      for (int e = t; e < rows * bw; e += 256) {
+        const int rr = e / bw, b = e % bw;
+        double acc = X[rr * ld + b];
+        for (int kk = 0; kk < k; ++kk) {
+          const double* vr = Vb + (int64_t)kk * rmax * bw + rr * bw;
+          const double* sb = Sb + kk * nout + b;
+          for (int a = 0; a < bw; ++a) acc -= vr[a] * sb[a * bw];
+        }
+        X[rr * ld + b] = acc;
+      }
     }
   }
-  // 3. local QR
-  for (int o = t; o < nout; o += 64) Rl[o] = 0.0;
+  // 3. local QR of the chunk (wave 0)
+  for (int o = t; o < nout; o += 256) Rl[o] = 0.0;
   __syncthreads();
-  // replacement directions must differ between blocks, passes and chunks
   const uint64_t seed = ((uint64_t)(j + 1) * 1000003ull + (uint64_t)pass * 7919ull + (uint64_t)mode * 104729ull) *
                             0x100000001B3ull + (uint64_t)r0;
-  mgs2_qr<false>(X, rows, ld, bw, Rl, seed, nullptr, Rn, 0);
+  if (w == 0) {
+    if (!cgs2_dispatch<1>(X, rows, ld, bw, Rl, seed, Rn, 0, nullptr)) cgs2_qr_wave(X, rows, ld, bw, Rl, seed, Rn, 0);
+  }
   __syncthreads();
   double* Qloc = pass == 0 ? p.Qloc1 : p.Qloc2;
-  for (int e = t; e < rows * bw; e += 64) {
-    const int rr = e / bw, col = e % bw;
-    Qloc[(r0 + rr) * bw + col] = X[rr * ld + col];
-  }
-  for (int o = t; o < nout; o += 64) p.Rloc[(int64_t)u * nout + o] = Rl[o];
-  // 4. combine
+  for (int e = t; e < rows * bw; e += 256) Qloc[(r0 + e / bw) * bw + (e % bw)] = X[(e / bw) * ld + (e % bw)];
+  for (int o = t; o < nout; o += 256) p.Rloc[(int64_t)u * nout + o] = Rl[o];
+  // 4. TSQR combine by the last workgroup
   __threadfence();
   __syncthreads();
   if (t == 0) {
-    unsigned* cnt = p.cnt + 2 * p.nbmax;
-    const unsigned old = atomicAdd(cnt, 1u);
+    const unsigned old = atomicAdd(p.cnt + 2 * p.nbmax, 1u);
     is_last = (old == (unsigned)(p.Cu - 1));
   }
   __syncthreads();
@@ -459,37 +724,32 @@ __global__ __launch_bounds__(64) void k_block_update(ProbDev* probs, int j, int 
   __threadfence();
   double* Qs = pass == 0 ? p.Qs1 : p.Qs2;
   const int srows = p.Cu * bw;
-  for (int e = t; e < srows * bw; e += 64) {
-    const int rr = e / bw, col = e % bw;
-    X[rr * ld + col] = __builtin_nontemporal_load(p.Rloc + e);
-  }
-  for (int o = t; o < nout; o += 64) Rl[o] = 0.0;
-  for (int b = t; b < bw; b += 64) {
+  for (int e = t; e < srows * bw; e += 256) X[(e / bw) * ld + (e % bw)] = __builtin_nontemporal_load(p.Rloc + e);
+  for (int o = t; o < nout; o += 256) Rl[o] = 0.0;
+  for (int b = t; b < bw; b += 256) {
     double s0 = 0.0;
     for (int uu = 0; uu < p.Cu; ++uu) s0 += __builtin_nontemporal_load(p.Cn + (int64_t)uu * bw + b);
     Rn[b] = sqrt(s0);
   }
   __syncthreads();
-  mgs2_qr<false>(X, srows, ld, bw, Rl, seed ^ 0x5bd1e995ull, nullptr, Rn, bw);
-  __syncthreads();
-  for (int e = t; e < srows * bw; e += 64) {
-    const int rr = e / bw, col = e % bw;
-    Qs[e] = X[rr * ld + col];
+  if (!cgs2_dispatch<4>(X, srows, ld, bw, Rl, seed ^ 0x5bd1e995ull, Rn, bw, Qsl)) {
+    if (w == 0) cgs2_qr_wave(X, srows, ld, bw, Rl, seed ^ 0x5bd1e995ull, Rn, bw);
   }
+  __syncthreads();
+  for (int e = t; e < srows * bw; e += 256) Qs[e] = X[(e / bw) * ld + (e % bw)];
   double* Rout = p.Rf + (mode == MODE_INIT ? 2 : pass) * nout;
-  for (int o = t; o < nout; o += 64) Rout[o] = Rl[o];
+  for (int o = t; o < nout; o += 256) Rout[o] = Rl[o];
   if (mode != MODE_INIT && pass == 1) {
-    // W = V (S1 + S2 Rf1) + Q2 (Rf2 Rf1): column block j of H (or of R in MODE_GIVEN)
-    const double* R1 = p.Rf;
-    const double* S1 = p.S;
-    const double* S2 = p.S + (int64_t)p.nbmax * nout;
-    // rows below the new subdiagonal block of this column block are zero
+    // W = V (S1 + S2 Rf1) + Q2 (Rf2 Rf1): column block j of H (of R in MODE_GIVEN)
     const int64_t r_lo = (int64_t)(nb + 1) * bw;
-    for (int64_t e = t; e < (p.ldH - r_lo) * bw; e += 64) {
+    for (int64_t e = t; e < (p.ldH - r_lo) * bw; e += 256) {
       const int64_t rr = r_lo + e / bw, b = e % bw;
       p.H[rr + p.ldH * (int64_t)(j * bw + b)] = 0.0;
     }
-    for (int e = t; e < (nb + 1) * nout; e += 64) {
+    const double* R1 = p.Rf;
+    const double* S1 = p.S;
+    const double* S2 = p.S + (int64_t)p.nbmax * nout;
+    for (int e = t; e < (nb + 1) * nout; e += 256) {
       const int i = e / nout, o = e % nout, a = o / bw, b = o % bw;
       double v = 0.0;
       if (i < nb) {
@@ -520,6 +780,16 @@ __global__ void k_block_commit(ProbDev* probs, int j) {
 void launch_block_proj(ProbDev* d, int nprob, int grid_x, size_t smem, int j, int nb, int pass, int mode,
                        int mixed, hipStream_t st) {
   if (grid_x <= 0 || nprob <= 0 || nb <= 0) return;
+  static bool attr_set = false;
+  if (!attr_set) {
+    if (hipFuncSetAttribute((const void*)k_block_proj<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            kUpdateLdsMax) != hipSuccess)
+      (void)hipGetLastError();
+    if (hipFuncSetAttribute((const void*)k_block_proj<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            kUpdateLdsMax) != hipSuccess)
+      (void)hipGetLastError();
+    attr_set = true;
+  }
   dim3 grid((unsigned)grid_x, (unsigned)nprob);
   if (mixed)
     hipLaunchKernelGGL(k_block_proj<float>, grid, dim3(256), smem, st, d, j, nb, pass, mode);
@@ -544,9 +814,9 @@ void launch_block_update(ProbDev* d, int nprob, int grid_x, size_t smem, int j, 
   }
   dim3 grid((unsigned)grid_x, (unsigned)nprob);
   if (mixed)
-    hipLaunchKernelGGL(k_block_update<float>, grid, dim3(64), smem, st, d, j, nb, pass, mode);
+    hipLaunchKernelGGL(k_block_update<float>, grid, dim3(256), smem, st, d, j, nb, pass, mode);
   else
-    hipLaunchKernelGGL(k_block_update<double>, grid, dim3(64), smem, st, d, j, nb, pass, mode);
+    hipLaunchKernelGGL(k_block_update<double>, grid, dim3(256), smem, st, d, j, nb, pass, mode);
 }
 
 void launch_block_commit(ProbDev* d, int nprob, int grid_x, int j, int mixed, hipStream_t st) {
@@ -598,29 +868,24 @@ void launch_build_aug(ExpmDev* e, int nprob, int64_t maxNN, hipStream_t st) {
   hipLaunchKernelGGL(k_build_aug, grid, dim3(256), 0, st, e);
 }
 
-// out[p] = ||Ht||_1 (largest absolute column sum)
+// out[p] = ||Ht||_1 (largest absolute column sum); one wave per column, grid over column
+// groups; non-negative doubles order like their bit patterns, so the maximum is an
+// integer atomic max (out[] zeroed by the host)
 __global__ __launch_bounds__(256) void k_norm1(ExpmDev* E, double* out) {
-  const ExpmDev& e = E[blockIdx.x];
-  __shared__ double red[16];
-  if (!e.active) {
-    if (threadIdx.x == 0) out[blockIdx.x] = 0.0;
-    return;
-  }
+  const ExpmDev& e = E[blockIdx.y];
+  if (!e.active) return;
   const int N = e.N;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  double mx = 0.0;
-  for (int c = w; c < N; c += 4) {
-    double s = 0.0;
-    for (int r = lane; r < N; r += 64) s += fabs(e.Ht[(int64_t)r + (int64_t)N * c]);
-    s = wave_sum(s);
-    mx = fmax(mx, s);
-  }
-  mx = block_max(mx, red);
-  if (threadIdx.x == 0) out[blockIdx.x] = mx;
+  const int c = blockIdx.x * 4 + w;
+  if (c >= N) return;
+  double s = 0.0;
+  for (int r = lane; r < N; r += 64) s += fabs(e.Ht[(int64_t)r + (int64_t)N * c]);
+  s = wave_sum(s);
+  if (lane == 0) atomicMax((unsigned long long*)(out + blockIdx.y), (unsigned long long)__double_as_longlong(s));
 }
 
-void launch_norm1(ExpmDev* e, double* out, int nprob, hipStream_t st) {
-  hipLaunchKernelGGL(k_norm1, dim3((unsigned)nprob), dim3(256), 0, st, e, out);
+void launch_norm1(ExpmDev* e, double* out, int nprob, int maxN, hipStream_t st) {
+  hipLaunchKernelGGL(k_norm1, dim3((unsigned)((maxN + 3) / 4), (unsigned)nprob), dim3(256), 0, st, e, out);
 }
 
 __device__ __constant__ double c_taylor[17] = {
@@ -731,47 +996,50 @@ void launch_gemm(ExpmDev* e, int op, int k, int nprob, int tiles_max, hipStream_
   hipLaunchKernelGGL(k_gemm, grid, dim3(256), 0, st, e, op, k);
 }
 
-// y = E b with E = T (nsq even) or P (nsq odd); out[0] = |H_{l+1,l} y_last|, out[1] = |y[0:lbw]|
-__global__ __launch_bounds__(256) void k_expm_apply(ExpmDev* E) {
-  const ExpmDev& e = E[blockIdx.x];
-  if (!e.active) return;
-  extern __shared__ double sm[];
-  double* bs = sm;              // N
-  double* red = sm + e.N;       // 16
+// y_k = exp(alpha 2^k Ht) b after k squarings (T for even k, P for odd k); rows spread
+// over workgroups.  Problems with fewer squarings than k skip.
+__global__ __launch_bounds__(256) void k_expm_apply(ExpmDev* E, int level) {
+  const ExpmDev& e = E[blockIdx.y];
+  if (!e.active || level > e.nsq) return;
   const int N = e.N;
-  const double* M = (e.nsq & 1) ? e.P : e.T;
-  for (int c = threadIdx.x; c < N; c += blockDim.x) bs[c] = e.b[c];
-  __syncthreads();
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= N) return;
+  const double* M = (level & 1) ? e.P : e.T;
+  double acc = 0.0;
+  for (int c = 0; c < N; ++c) acc += M[(int64_t)r + (int64_t)N * c] * e.b[c];
+  e.y[(int64_t)level * N + r] = acc;
+}
+
+// out[2k] = |H_{l+1,l} y_k[(l-1)bw : l bw]| (residual of the Arnoldi relation at the end
+// of the step of level k), out[2k+1] = |y_k[0 : l bw]|
+__global__ __launch_bounds__(256) void k_expm_resid(ExpmDev* E, int level) {
+  const ExpmDev& e = E[blockIdx.x];
+  if (!e.active || level > e.nsq) return;
+  __shared__ double red[16];
+  const double* y = e.y + (int64_t)level * e.N;
   double yn = 0.0;
-  for (int r = threadIdx.x; r < N; r += blockDim.x) {
-    double acc = 0.0;
-    for (int c = 0; c < N; ++c) acc += M[(int64_t)r + (int64_t)N * c] * bs[c];
-    e.y[r] = acc;
-    if (r < e.lbw) yn += acc * acc;
-  }
+  for (int r = threadIdx.x; r < e.lbw; r += blockDim.x) yn += y[r] * y[r];
   yn = block_sum(yn, red);
-  __threadfence_block();
-  __syncthreads();
-  // residual of the Arnoldi relation at tau = delta: H_{l+1,l} y[(l-1)bw : l bw]
   double rr = 0.0;
   const int bw = e.bw, l = e.l;
   if ((int)threadIdx.x < bw) {
     const int a = threadIdx.x;
-    double s = 0.0;
+    double sacc = 0.0;
     for (int c = 0; c < bw; ++c)
-      s += e.H[(int64_t)(l * bw + a) + e.ldH * (int64_t)((l - 1) * bw + c)] * e.y[(l - 1) * bw + c];
-    rr = s * s;
+      sacc += e.H[(int64_t)(l * bw + a) + e.ldH * (int64_t)((l - 1) * bw + c)] * y[(l - 1) * bw + c];
+    rr = sacc * sacc;
   }
   rr = block_sum(rr, red);
   if (threadIdx.x == 0) {
-    e.out[0] = sqrt(rr);
-    e.out[1] = sqrt(yn);
+    e.out[2 * level] = sqrt(rr);
+    e.out[2 * level + 1] = sqrt(yn);
   }
 }
 
-void launch_expm_apply(ExpmDev* e, int nprob, int maxN, hipStream_t st) {
-  size_t smem = sizeof(double) * ((size_t)maxN + 16);
-  hipLaunchKernelGGL(k_expm_apply, dim3((unsigned)nprob), dim3(256), smem, st, e);
+void launch_expm_apply(ExpmDev* e, int level, int nprob, int maxN, hipStream_t st) {
+  hipLaunchKernelGGL(k_expm_apply, dim3((unsigned)((maxN + 255) / 256), (unsigned)nprob), dim3(256), 0, st, e,
+                     level);
+  hipLaunchKernelGGL(k_expm_resid, dim3((unsigned)nprob), dim3(256), 0, st, e, level);
 }
 
 // ------------------------------------------------------------------------------------
@@ -781,10 +1049,10 @@ template <typename TS>
 __global__ __launch_bounds__(256) void k_project(ProbDev* probs, ExpmDev* E) {
   const ProbDev& p = probs[blockIdx.y];
   if (!p.active || !p.proj) return;
-  const ExpmDev& e = E[blockIdx.y];
+  (void)E;
   extern __shared__ double ys[];
   const int lbw = p.l * p.bw;
-  for (int c = threadIdx.x; c < lbw; c += blockDim.x) ys[c] = e.y[c];
+  for (int c = threadIdx.x; c < lbw; c += blockDim.x) ys[c] = p.yacc[c];
   __syncthreads();
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= p.n) return;
@@ -844,7 +1112,7 @@ __global__ __launch_bounds__(256) void k_jacobi_svd(const double* R, int64_t ldR
   __syncthreads();
   const int r2 = r + (r & 1);
   int sweep = 0;
-  for (; sweep < 60 && r > 1; ++sweep) {
+  for (; sweep < 30 && r > 1; ++sweep) {
     double off = 0.0;
     for (int round = 0; round < r2 - 1; ++round) {
       for (int pi = w; pi < r2 / 2; pi += 4) {
@@ -871,7 +1139,7 @@ __global__ __launch_bounds__(256) void k_jacobi_svd(const double* R, int64_t ldR
         if (ga == 0.0 || al == 0.0 || be == 0.0) continue;
         const double rel = fabs(ga) / sqrt(al * be);
         off = fmax(off, rel);
-        if (rel < 1e-16) continue;
+        if (rel < 1e-15) continue;
         const double zeta = (be - al) / (2.0 * ga);
         const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
         const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
@@ -895,7 +1163,7 @@ __global__ __launch_bounds__(256) void k_jacobi_svd(const double* R, int64_t ldR
     __syncthreads();
     const double o = fmax(fmax(wmax[0], wmax[1]), fmax(wmax[2], wmax[3]));
     __syncthreads();
-    if (o < 1e-15) {
+    if (o < 1e-14) {
       ++sweep;
       break;
     }

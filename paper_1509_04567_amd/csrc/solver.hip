@@ -102,17 +102,18 @@ pe_status ensure_pinned(pe_ctx* ctx, size_t bytes) {
 }
 
 // ---- geometry of the block kernels ------------------------------------------------
+size_t update_smem(const ProbDev& d);
+size_t proj_smem(const ProbDev& d);
 int rows_p_for(int bw) { return bw <= 8 ? 256 : (bw <= 16 ? 128 : 64); }
 
 int rows_u_for(int64_t n, int bw) {
   int ru = kRowsU;
   while (true) {
-    const int64_t cu = std::max<int64_t>(1, n / ru);
-    const size_t comb = (size_t)cu * bw * (bw + 1) * 8;
-    const size_t xs = (size_t)2 * ru * (bw + 1) * 8;
-    if ((comb + 2048 <= (size_t)pe::kUpdateLdsMax - 4096 && xs + 2048 <= (size_t)pe::kUpdateLdsMax - 4096) ||
-        ru >= 4096)
-      return ru;
+    ProbDev d{};
+    d.bw = bw;
+    d.rows_u = ru;
+    d.Cu = (int)std::max<int64_t>(1, n / ru);
+    if (update_smem(d) <= (size_t)pe::kUpdateLdsMax || ru >= 4096) return ru;
     ru *= 2;
   }
 }
@@ -125,15 +126,24 @@ void set_geometry(ProbDev& d, int64_t n, int bw) {
   d.Cp = (int)((n + d.rows_p - 1) / d.rows_p);
 }
 
-size_t proj_smem(int rows_p, int bw) {
-  const size_t ld = bw + 1;
-  return sizeof(double) * ((size_t)rows_p * ld + (size_t)(rows_p + 2) * ld + 256) + 64;
+size_t proj_smem(const ProbDev& d) {
+  const size_t ld = d.bw + 1;
+  const size_t qsl = (size_t)(d.rows_p / d.rows_u + 3) * d.bw * d.bw;
+  return sizeof(double) * ((size_t)d.rows_p * ld * 2 + (size_t)(d.rows_p + 2) * ld + 256 + qsl) + 64;
+}
+
+int batch_slots(int bw, int rows_u) {
+  int k = 8192 / (bw * bw + 2 * rows_u * bw);
+  return k < 1 ? 1 : (k > 8 ? 8 : k);
 }
 
 size_t update_smem(const ProbDev& d) {
   const size_t ld = d.bw + 1;
-  const size_t xs = std::max((size_t)2 * d.rows_u * ld, (size_t)d.Cu * d.bw * ld);
-  return sizeof(double) * (xs + 2 * (size_t)d.bw * d.bw + (size_t)d.bw) + 64;
+  const size_t rmax = 2 * (size_t)d.rows_u;
+  const size_t xs = std::max(rmax * ld, (size_t)d.Cu * d.bw * ld);
+  const size_t KS = batch_slots(d.bw, d.rows_u);
+  const size_t bw2 = (size_t)d.bw * d.bw;
+  return sizeof(double) * (xs + KS * bw2 + KS * rmax * d.bw + bw2 + d.bw + std::max<size_t>(bw2, 128)) + 64;
 }
 
 // capacities of the per-problem block workspace for block widths up to bwmax
@@ -218,6 +228,7 @@ bool geometry_fits(const ProbDev& d, const BlockCaps& c, int nb_needed) {
   if ((size_t)(d.Cu) * d.rows_u > (size_t)c.n + (size_t)d.rows_u) return false;
   if (c.n < d.bw) return false;
   if (update_smem(d) > (size_t)pe::kUpdateLdsMax) return false;
+  if (proj_smem(d) > (size_t)pe::kUpdateLdsMax) return false;
   return true;
 }
 
@@ -378,9 +389,10 @@ pe_status compress_one(pe_ctx* ctx, const pe_problem& p, double* U, int64_t ldU,
   HCK(hipMemsetAsync(d.cnt, 0, caps.cnt * sizeof(unsigned), st));
   HCK(hipMemsetAsync(d.H, 0, caps.H * sizeof(double), st));
   HCK(hipMemcpyAsync(dd, &d, sizeof(ProbDev), hipMemcpyHostToDevice, st));
-  const size_t smem_p = proj_smem(d.rows_p, bwc), smem_u = update_smem(d);
+  const size_t smem_p = proj_smem(d), smem_u = update_smem(d);
   for (int j = 0; j < nblk; ++j) {
-    run_block_step(dd, 1, j * d.Cp, smem_p, d.Cu, smem_u, j, j, pe::MODE_GIVEN, 0, st);
+    run_block_step(dd, 1, ((j + pe::kSlotGroup - 1) / pe::kSlotGroup) * d.Cp, smem_p, d.Cu, smem_u, j, j,
+                   pe::MODE_GIVEN, 0, st);
     pe::launch_block_commit(dd, 1, (int)((n * bwc + 255) / 256), j, 0, st);
   }
   // significant rows of R
@@ -408,7 +420,7 @@ pe_status compress_one(pe_ctx* ctx, const pe_problem& p, double* U, int64_t ldU,
   const double fro = std::sqrt(fro2);
   std::vector<int> sel;
   for (int i = 0; i < S_; ++i)
-    if (hp[i] > 1e-15 * fro) sel.push_back(i);
+    if (hp[i] > kSigmaFloor * fro) sel.push_back(i);
   res.sigma.assign(s, 0.0);
   res.m = 0;
   if (fro == 0.0 || sel.empty() || p.rank_max == 0) {
@@ -473,7 +485,7 @@ pe_status compress_one(pe_ctx* ctx, const pe_problem& p, double* U, int64_t ldU,
 // the march: S5-S7 for a batch of problems of one precision
 // ---------------------------------------------------------------------------------
 struct HostState {
-  double tau = 0.0, dlast = 0.0, Tspan = 1.0, ref = 1.0;
+  double tau = 0.0, dlast = 0.0, Tspan = 1.0, ref = 1.0, dgrow = 2.0;
   int k = 0;
   bool xzero = true, done = false;
   int cycles = 0, rejected = 0, steps = 0, flags = 0;
@@ -483,6 +495,8 @@ struct HostState {
   double target = 0.0, dtry = 0.0, nrm = 0.0;
   int bw = 1, N = 0;
   bool pending = false, accepted = false;
+  int level = 0;
+  double rho = 1.0;
 };
 
 pe_status march_batch(pe_ctx* ctx, const pe_problem* probs, const int* idx, int nb_prob, const double* const* Ul,
@@ -508,7 +522,8 @@ pe_status march_batch(pe_ctx* ctx, const pe_problem* probs, const int* idx, int 
     bo[ii] = carve_block(cv, caps[ii], mixed);
     o_x[ii] = cv.take<double>(p.op.n);
     Nmax[ii] = l * bwmax + ql[ii];
-    o_e[ii] = cv.take<double>(7 * (size_t)Nmax[ii] * Nmax[ii] + 2 * (size_t)Nmax[ii] + 2);
+    o_e[ii] = cv.take<double>(7 * (size_t)Nmax[ii] * Nmax[ii] + (PE_MAX_LEVELS + 2) * (size_t)Nmax[ii] +
+                              2 * (PE_MAX_LEVELS + 1));
     o_w[ii] = cv.take<double>(std::max(1, ql[ii]));
     maxn = std::max<int64_t>(maxn, p.op.n);
     maxNall = std::max(maxNall, Nmax[ii]);
@@ -520,7 +535,7 @@ pe_status march_batch(pe_ctx* ctx, const pe_problem* probs, const int* idx, int 
   const size_t o_nrm = cv.take<double>(nb_prob);
   pe_status stt = ensure_arena(ctx, cv.off);
   if (stt != PE_OK) return stt;
-  stt = ensure_pinned(ctx, sizeof(double) * (4 * (size_t)nb_prob + 64));
+  stt = ensure_pinned(ctx, sizeof(double) * (2 * (PE_MAX_LEVELS + 1) * (size_t)nb_prob + 64));
   if (stt != PE_OK) return stt;
   char* base = ctx->arena;
   double* hp = (double*)ctx->pinned;
@@ -590,7 +605,7 @@ pe_status march_batch(pe_ctx* ctx, const pe_problem* probs, const int* idx, int 
     e.T = eb + 6 * NN;
     e.b = eb + 7 * NN;
     e.y = e.b + Nmax[ii];
-    e.out = e.y + Nmax[ii];
+    e.out = e.y + (size_t)(PE_MAX_LEVELS + 1) * Nmax[ii];
     e.H = d.H;
     e.R0 = d.Rf + 0;  // set per cycle (depends on bw)
     e.Pi = Pil[ii];
@@ -626,7 +641,7 @@ pe_status march_batch(pe_ctx* ctx, const pe_problem* probs, const int* idx, int 
       }
       h.target = h.src ? std::min(p.t_out[h.k], p.t1) : p.t_out[h.k];
       const double rem = h.target - h.tau;
-      h.dtry = std::min(rem, 2.0 * h.dlast);
+      h.dtry = std::min(rem, h.dgrow * h.dlast);
       h.bw = h.src ? (h.xzero ? m : m + 1) : 1;
       d.m = h.src ? m : 0;
       d.with_x = h.xzero ? 0 : 1;
@@ -638,9 +653,9 @@ pe_status march_batch(pe_ctx* ctx, const pe_problem* probs, const int* idx, int 
       d.active = 1;
       ++nact;
       lmax = std::max(lmax, d.l);
-      gx_p = std::max(gx_p, (d.l + 1) * d.Cp);
+      gx_p = std::max(gx_p, d.Cp);
       gx_u = std::max(gx_u, d.Cu);
-      smem_p = std::max(smem_p, proj_smem(d.rows_p, d.bw));
+      smem_p = std::max(smem_p, proj_smem(d));
       smem_u = std::max(smem_u, update_smem(d));
       h.N = d.l * h.bw + (h.src ? ql[ii] : 0);
       mb_N = std::max(mb_N, h.N);
@@ -670,14 +685,15 @@ pe_status march_batch(pe_ctx* ctx, const pe_problem* probs, const int* idx, int 
     // ---- S5: initial block and block Arnoldi
     pe::launch_block_update(dd, nb_prob, gx_u, smem_u, 0, 0, 1, pe::MODE_INIT, mixed, st);
     for (int j = 0; j < lmax; ++j) {
-      const int gxp = std::min(gx_p, (j + 1) * 4096);
-      run_block_step(dd, nb_prob, gxp, smem_p, gx_u, smem_u, j, j + 1, pe::MODE_ARNOLDI, mixed, st);
+      const int groups = (j + 1 + pe::kSlotGroup - 1) / pe::kSlotGroup;
+      run_block_step(dd, nb_prob, gx_p * groups, smem_p, gx_u, smem_u, j, j + 1, pe::MODE_ARNOLDI, mixed, st);
     }
     // ---- S6: projected exponential with step-size trials
     for (int ii = 0; ii < nb_prob; ++ii) he[ii].active = hd[ii].active;
     HCK(hipMemcpyAsync(ed, he.data(), sizeof(ExpmDev) * nb_prob, hipMemcpyHostToDevice, st));
     pe::launch_build_aug(ed, nb_prob, maxNN, st);
-    pe::launch_norm1(ed, (double*)(base + o_nrm), nb_prob, st);
+    HCK(hipMemsetAsync(base + o_nrm, 0, sizeof(double) * nb_prob, st));
+    pe::launch_norm1(ed, (double*)(base + o_nrm), nb_prob, mb_N, st);
     HCK(hipMemcpyAsync(hp, base + o_nrm, sizeof(double) * nb_prob, hipMemcpyDeviceToHost, st));
     HCK(hipStreamSynchronize(st));
     for (int ii = 0; ii < nb_prob; ++ii) {
@@ -686,6 +702,9 @@ pe_status march_batch(pe_ctx* ctx, const pe_problem* probs, const int* idx, int 
       hs[ii].accepted = false;
     }
     const int tiles = (mb_N + 31) / 32;
+    // Each trial evaluates the step at every squaring level: after k squarings the
+    // exponential is exp(alpha 2^k Ht) with alpha = dtry / 2^nsq, so the largest level
+    // whose error estimate passes gives the accepted step without recomputation.
     for (int trial = 0; trial < kMaxTrials; ++trial) {
       int maxsq = 0, npend = 0;
       for (int ii = 0; ii < nb_prob; ++ii) {
@@ -697,7 +716,7 @@ pe_status march_batch(pe_ctx* ctx, const pe_problem* probs, const int* idx, int 
         const double nn = h.dtry * h.nrm;
         int s = 0;
         if (nn > kTaylorTheta) s = (int)std::ceil(std::log2(nn / kTaylorTheta));
-        s = std::max(0, std::min(s, 60));
+        s = std::max(0, std::min(s, PE_MAX_LEVELS));
         e.nsq = s;
         e.alpha = std::ldexp(h.dtry, -s);
         maxsq = std::max(maxsq, s);
@@ -712,31 +731,60 @@ pe_status march_batch(pe_ctx* ctx, const pe_problem* probs, const int* idx, int 
       pe::launch_gemm(ed, 3, 0, nb_prob, tiles * tiles, st);
       pe::launch_gemm(ed, 4, 0, nb_prob, tiles * tiles, st);
       pe::launch_gemm(ed, 5, 0, nb_prob, tiles * tiles, st);
-      for (int k = 0; k < maxsq; ++k) pe::launch_gemm(ed, 6, k, nb_prob, tiles * tiles, st);
-      pe::launch_expm_apply(ed, nb_prob, mb_N, st);
+      pe::launch_expm_apply(ed, 0, nb_prob, mb_N, st);
+      for (int k = 0; k < maxsq; ++k) {
+        pe::launch_gemm(ed, 6, k, nb_prob, tiles * tiles, st);
+        pe::launch_expm_apply(ed, k + 1, nb_prob, mb_N, st);
+      }
       for (int ii = 0; ii < nb_prob; ++ii)
-        if (hs[ii].pending) HCK(hipMemcpyAsync(hp + 2 * ii, he[ii].out, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+        if (hs[ii].pending)
+          HCK(hipMemcpyAsync(hp + 2 * (PE_MAX_LEVELS + 1) * ii, he[ii].out,
+                             2 * (he[ii].nsq + 1) * sizeof(double), hipMemcpyDeviceToHost, st));
       HCK(hipStreamSynchronize(st));
       for (int ii = 0; ii < nb_prob; ++ii) {
         HostState& h = hs[ii];
         if (!h.pending) continue;
         const pe_problem& p = probs[idx[ii]];
-        const double err = hp[2 * ii], yn = hp[2 * ii + 1];
-        const double lim = p.tol * std::max(h.ref, yn) / h.Tspan;
+        const double* ho = hp + 2 * (PE_MAX_LEVELS + 1) * ii;
+        const int ns = he[ii].nsq;
         const double dmin = 1e-13 * h.Tspan;
-        if (trace)
-          fprintf(stderr, "[paraexp] prob %d cycle %d trial %d tau %.6e dtry %.3e N %d bw %d |H|1 %.3e nsq %d err %.3e lim %.3e |y| %.3e\n",
-                  idx[ii], guard, trial, h.tau, h.dtry, h.N, h.bw, h.nrm, he[ii].nsq, err, lim, yn);
-        if (std::isfinite(err) && (err <= lim || h.dtry <= dmin)) {
+        int best = -1;
+        double best_err = 0.0, best_lim = 1.0;
+        for (int k = ns; k >= 0; --k) {
+          const double err = ho[2 * k], yn = ho[2 * k + 1];
+          const double lim = p.tol * std::max(h.ref, yn) / h.Tspan;
+          if (trace)
+            fprintf(stderr, "[paraexp] prob %d cycle %d trial %d level %d tau %.6e d %.3e N %d bw %d |H|1 %.3e "
+                    "err %.3e lim %.3e |y| %.3e\n", idx[ii], guard, trial, k, h.tau, std::ldexp(he[ii].alpha, k),
+                    h.N, h.bw, h.nrm, err, lim, yn);
+          if (std::isfinite(err) && err <= lim) {
+            best = k;
+            best_err = err;
+            best_lim = lim;
+            break;
+          }
+        }
+        const double d0 = he[ii].alpha;  // the level-0 step
+        if (best < 0 && d0 <= dmin) {
+          best = 0;
+          best_err = ho[0];
+          h.flags |= PE_FLAG_NOT_CONVERGED;
+        }
+        if (best >= 0) {
           h.accepted = true;
           h.pending = false;
-          if (err > lim) h.flags |= PE_FLAG_NOT_CONVERGED;
-          h.resid = std::max(h.resid, err * h.dtry);
+          h.level = best;
+          h.rho = best_lim > 0 ? best_err / best_lim : 0.0;
+          h.dtry = (best == ns) ? h.dtry : std::ldexp(he[ii].alpha, best);
+          h.resid = std::max(h.resid, best_err * h.dtry);
+          if (best < ns) h.rejected += 1;
         } else {
           ++h.rejected;
+          const double err = ho[0], yn = ho[1];
+          const double lim = p.tol * std::max(h.ref, yn) / h.Tspan;
           const double rho = std::isfinite(err) ? err / lim : 1e30;
           const double ex = 1.0 / std::max(2.0, probs[idx[ii]].krylov_steps / 3.0);
-          h.dtry *= std::min(0.7, std::max(0.1, 0.9 * std::pow(rho, -ex)));
+          h.dtry = d0 * std::min(0.5, std::max(0.05, 0.9 * std::pow(rho, -ex)));
         }
       }
     }
@@ -757,6 +805,7 @@ pe_status march_batch(pe_ctx* ctx, const pe_problem* probs, const int* idx, int 
       const double rem = h.target - h.tau;
       const bool landed = h.dtry >= rem;
       d.proj = 1;
+      d.yacc = he[ii].y + (size_t)h.level * h.N;
       if (landed && h.target == p.t_out[h.k]) d.outcol = p.out + (int64_t)h.k * p.ldOut;
       ++nproj;
     }
@@ -772,7 +821,12 @@ pe_status march_batch(pe_ctx* ctx, const pe_problem* probs, const int* idx, int 
       const double rem = h.target - h.tau;
       const bool landed = h.dtry >= rem;
       h.tau = landed ? h.target : h.tau + h.dtry;
-      h.dlast = h.dtry;
+      // a step clipped at an output time does not limit the next one
+      if (!landed || h.dtry >= h.dlast) h.dlast = h.dtry;
+      {
+        const double ex = 1.0 / std::max(2.0, p.krylov_steps / 3.0);
+        h.dgrow = std::min(4.0, std::max(1.25, 0.9 * std::pow(std::max(h.rho, 1e-30), -ex)));
+      }
       h.xzero = false;
       ++h.cycles;
       if (d.outcol) {
