@@ -170,6 +170,17 @@ pe_status pe_superpose(pe_ctx* ctx, const double* u0, const double* const* v, in
                        int64_t n, int32_t n_out, int64_t ldv, double* u, int64_t ldu,
                        void* stream);
 
+/* Kernel timing for roofline measurements.  Enables HIP-event timing, on the stream of
+ * each call, of every launch of one kernel family: "block_update" (block Gram-Schmidt
+ * update + chunk QR + TSQR combine), "block_proj" (block projections), "stencil"
+ * (pe_stencil_apply), or NULL to switch timing off.  Resets the accumulators.  Timing
+ * adds two event records per launch, so time throughput separately. */
+pe_status pe_profile_enable(pe_ctx* ctx, const char* family);
+/* Read and reset the accumulators: timed launches, their summed duration (ms), and the
+ * algorithmic traffic (bytes, each datum read or written once per launch) and flops of
+ * those launches.  All pointers are host pointers. */
+pe_status pe_profile_read(pe_ctx* ctx, int64_t* launches, double* ms, double* bytes, double* flops);
+
 #ifdef __cplusplus
 }
 #endif

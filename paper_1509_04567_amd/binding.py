@@ -34,7 +34,7 @@ FLAG_RANK_CAPPED = 4
 FLAG_FIT_CAPPED = 8
 
 EXPORTED = ["pe_create", "pe_destroy", "pe_last_error", "pe_version", "pe_stencil_apply", "pe_compress",
-            "pe_expaction_batch", "pe_solve_batch", "pe_superpose"]
+            "pe_expaction_batch", "pe_solve_batch", "pe_superpose", "pe_profile_enable", "pe_profile_read"]
 
 
 class PeStencil(ctypes.Structure):
@@ -120,8 +120,11 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                                        ctypes.POINTER(i32), ctypes.POINTER(i32), i32, ctypes.POINTER(PeReport), vp]
     lib.pe_solve_batch.argtypes = [vp, ctypes.POINTER(PeProblem), i32, ctypes.POINTER(PeReport), vp]
     lib.pe_superpose.argtypes = [vp, vp, ctypes.POINTER(vp), i32, i64, i32, i64, vp, i64, vp]
+    lib.pe_profile_enable.argtypes = [vp, ctypes.c_char_p]
+    lib.pe_profile_read.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double),
+                                    ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
     for name in ["pe_create", "pe_destroy", "pe_stencil_apply", "pe_compress", "pe_expaction_batch",
-                 "pe_solve_batch", "pe_superpose"]:
+                 "pe_solve_batch", "pe_superpose", "pe_profile_enable", "pe_profile_read"]:
         getattr(lib, name).restype = ctypes.c_int
     _LIB = lib
     return lib
@@ -328,6 +331,17 @@ class Context:
         reps = (PeReport * len(dps))()
         self._check(self.lib.pe_expaction_batch(self.h, arr, Uptr, Pptr, ms, qs, len(dps), reps, _stream_ptr()))
         return [d.out for d in dps], [r.as_dict() for r in reps]
+
+    # -- kernel timing
+    def profile_enable(self, family: Optional[str]):
+        self._check(self.lib.pe_profile_enable(self.h, family.encode() if family else None))
+
+    def profile_read(self):
+        n = ctypes.c_int64()
+        ms, by, fl = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        self._check(self.lib.pe_profile_read(self.h, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(by),
+                                             ctypes.byref(fl)))
+        return dict(launches=n.value, ms=ms.value, bytes=by.value, flops=fl.value)
 
     # -- S8
     def superpose(self, u0, vs: Sequence):

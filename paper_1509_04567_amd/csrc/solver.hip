@@ -32,6 +32,17 @@ struct pe_ctx {
   size_t arena_cap = 0;
   char* pinned = nullptr;
   size_t pinned_cap = 0;
+  // kernel timing (pe_profile_enable / pe_profile_read)
+  std::string prof_name;
+  std::vector<hipEvent_t> ev;
+  struct Pending {
+    int e0;
+    double bytes, flops;
+  };
+  std::vector<Pending> pend;
+  size_t ev_used = 0;
+  int64_t prof_launches = 0;
+  double prof_ms = 0.0, prof_bytes = 0.0, prof_flops = 0.0;
 };
 
 static pe_status pe_fail(pe_ctx* ctx, pe_status st, const std::string& msg, hipError_t e = hipSuccess) {
@@ -49,6 +60,41 @@ static pe_status pe_fail(pe_ctx* ctx, pe_status st, const std::string& msg, hipE
   } while (0)
 
 namespace {
+
+// ---- kernel timing with HIP events on the launch stream ----------------------------
+int prof_begin(pe_ctx* ctx, const char* family, hipStream_t st) {
+  if (ctx->prof_name.empty() || ctx->prof_name != family) return -1;
+  while (ctx->ev.size() < ctx->ev_used + 2) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return -1;
+    ctx->ev.push_back(e);
+  }
+  const int i = (int)ctx->ev_used;
+  ctx->ev_used += 2;
+  if (hipEventRecord(ctx->ev[i], st) != hipSuccess) return -1;
+  return i;
+}
+
+void prof_end(pe_ctx* ctx, int i, double bytes, double flops, hipStream_t st) {
+  if (i < 0) return;
+  (void)hipEventRecord(ctx->ev[i + 1], st);
+  ctx->pend.push_back({i, bytes, flops});
+}
+
+// after the stream is synchronised: fold the recorded launches into the totals
+void prof_collect(pe_ctx* ctx) {
+  for (const auto& p : ctx->pend) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, ctx->ev[p.e0], ctx->ev[p.e0 + 1]) == hipSuccess) {
+      ctx->prof_ms += ms;
+      ctx->prof_bytes += p.bytes;
+      ctx->prof_flops += p.flops;
+      ++ctx->prof_launches;
+    }
+  }
+  ctx->pend.clear();
+  ctx->ev_used = 0;
+}
 
 constexpr double kTaylorTheta = 0.78;  // ||A||_1 bound for the degree-16 Taylor polynomial
 constexpr int kMaxTrials = 6;
@@ -302,12 +348,32 @@ pe_status check_finite_dev(pe_ctx* ctx, const double* x, int64_t n, int cols, in
 }
 
 // ---- block orthogonalisation driver -------------------------------------------------
-void run_block_step(ProbDev* dd, int nprob, int gx_proj, size_t smem_p, int gx_upd, size_t smem_u, int j, int nb,
-                    int mode, int mixed, hipStream_t st) {
+// Algorithmic traffic of one block step's pass over all active problems: the
+// projection reads the nb basis blocks and the input block; the update reads them again
+// and writes the chunk Q factor.
+struct StepCost {
+  double proj_bytes = 0.0, upd_bytes = 0.0, flops = 0.0;
+};
+
+void run_block_step(pe_ctx* ctx, ProbDev* dd, int nprob, int gx_proj, size_t smem_p, int gx_upd, size_t smem_u,
+                    int j, int nb, int mode, int mixed, const StepCost& cost, hipStream_t st) {
   for (int pass = 0; pass < 2; ++pass) {
+    int ev = prof_begin(ctx, "block_proj", st);
     pe::launch_block_proj(dd, nprob, gx_proj, smem_p, j, nb, pass, mode, mixed, st);
+    prof_end(ctx, ev, cost.proj_bytes, cost.flops, st);
+    ev = prof_begin(ctx, "block_update", st);
     pe::launch_block_update(dd, nprob, gx_upd, smem_u, j, nb, pass, mode, mixed, st);
+    prof_end(ctx, ev, cost.upd_bytes, cost.flops, st);
   }
+}
+
+StepCost step_cost(int64_t n, int bw, int nb, int beta) {
+  StepCost c;
+  const double blk = (double)n * bw;
+  c.proj_bytes = blk * beta * (nb + 1);
+  c.upd_bytes = blk * beta * (nb + 1) + blk * 8.0;
+  c.flops = 2.0 * nb * blk * bw;
+  return c;
 }
 
 // ---------------------------------------------------------------------------------
@@ -391,8 +457,8 @@ pe_status compress_one(pe_ctx* ctx, const pe_problem& p, double* U, int64_t ldU,
   HCK(hipMemcpyAsync(dd, &d, sizeof(ProbDev), hipMemcpyHostToDevice, st));
   const size_t smem_p = proj_smem(d), smem_u = update_smem(d);
   for (int j = 0; j < nblk; ++j) {
-    run_block_step(dd, 1, ((j + pe::kSlotGroup - 1) / pe::kSlotGroup) * d.Cp, smem_p, d.Cu, smem_u, j, j,
-                   pe::MODE_GIVEN, 0, st);
+    run_block_step(ctx, dd, 1, ((j + pe::kSlotGroup - 1) / pe::kSlotGroup) * d.Cp, smem_p, d.Cu, smem_u, j, j,
+                   pe::MODE_GIVEN, 0, step_cost(n, bwc, j, 8), st);
     pe::launch_block_commit(dd, 1, (int)((n * bwc + 255) / 256), j, 0, st);
   }
   // significant rows of R
@@ -686,7 +752,16 @@ pe_status march_batch(pe_ctx* ctx, const pe_problem* probs, const int* idx, int 
     pe::launch_block_update(dd, nb_prob, gx_u, smem_u, 0, 0, 1, pe::MODE_INIT, mixed, st);
     for (int j = 0; j < lmax; ++j) {
       const int groups = (j + 1 + pe::kSlotGroup - 1) / pe::kSlotGroup;
-      run_block_step(dd, nb_prob, gx_p * groups, smem_p, gx_u, smem_u, j, j + 1, pe::MODE_ARNOLDI, mixed, st);
+      StepCost cost;
+      for (int ii = 0; ii < nb_prob; ++ii)
+        if (hd[ii].active && j < hd[ii].l) {
+          const StepCost c = step_cost(hd[ii].n, hd[ii].bw, j + 1, mixed ? 4 : 8);
+          cost.proj_bytes += c.proj_bytes;
+          cost.upd_bytes += c.upd_bytes;
+          cost.flops += c.flops;
+        }
+      run_block_step(ctx, dd, nb_prob, gx_p * groups, smem_p, gx_u, smem_u, j, j + 1, pe::MODE_ARNOLDI, mixed, cost,
+                     st);
     }
     // ---- S6: projected exponential with step-size trials
     for (int ii = 0; ii < nb_prob; ++ii) he[ii].active = hd[ii].active;
@@ -906,6 +981,7 @@ pe_status pe_destroy(pe_ctx* ctx) {
   hipDeviceSynchronize();
   if (ctx->arena) hipFree(ctx->arena);
   if (ctx->pinned) hipHostFree(ctx->pinned);
+  for (hipEvent_t e : ctx->ev) hipEventDestroy(e);
   delete ctx;
   return PE_OK;
 }
@@ -919,9 +995,12 @@ pe_status pe_stencil_apply(pe_ctx* ctx, const pe_stencil* op, const double* X, i
     return pe_fail(ctx, PE_ERR_ARG, "pe_stencil_apply: bad arguments");
   HCK(hipSetDevice(ctx->device));
   hipStream_t st = (hipStream_t)stream;
+  const int ev = prof_begin(ctx, "stencil", st);
   pe::launch_stencil_cols(op->n, op->per_point, op->coeffs, op->coeffs, X, ldx, Y, ldy, ncols, st);
+  prof_end(ctx, ev, 16.0 * (double)op->n * ncols + (op->per_point ? 24.0 * op->n : 0.0), 5.0 * op->n * ncols, st);
   HCK(hipGetLastError());
   HCK(hipStreamSynchronize(st));
+  prof_collect(ctx);
   return PE_OK;
 }
 
@@ -938,6 +1017,7 @@ pe_status pe_compress(pe_ctx* ctx, const pe_problem* prob, double* U, double* Pi
   if (s != PE_OK) return s;
   HCK(hipGetLastError());
   HCK(hipStreamSynchronize(st));
+  prof_collect(ctx);
   *m = co.m;
   *q = co.q;
   if (sigma)
@@ -981,6 +1061,7 @@ pe_status pe_expaction_batch(pe_ctx* ctx, const pe_problem* probs, const double*
   if (s != PE_OK) return s;
   HCK(hipGetLastError());
   HCK(hipStreamSynchronize(st));
+  prof_collect(ctx);
   return PE_OK;
 }
 
@@ -1031,9 +1112,32 @@ pe_status pe_solve_batch(pe_ctx* ctx, const pe_problem* probs, int32_t nprob, pe
   }
   if (s == PE_OK) s = march_all(ctx, probs, nprob, Ul.data(), Pil.data(), ld.data(), mm.data(), qq.data(), reports, st);
   hipStreamSynchronize(st);
+  prof_collect(ctx);
   hipFree(src);
   if (s != PE_OK) return s;
   HCK(hipGetLastError());
+  return PE_OK;
+}
+
+pe_status pe_profile_enable(pe_ctx* ctx, const char* family) {
+  if (!ctx) return PE_ERR_ARG;
+  if (family && std::strcmp(family, "block_update") && std::strcmp(family, "block_proj") &&
+      std::strcmp(family, "stencil"))
+    return pe_fail(ctx, PE_ERR_ARG, "pe_profile_enable: unknown kernel family");
+  ctx->prof_name = family ? family : "";
+  ctx->prof_launches = 0;
+  ctx->prof_ms = ctx->prof_bytes = ctx->prof_flops = 0.0;
+  return PE_OK;
+}
+
+pe_status pe_profile_read(pe_ctx* ctx, int64_t* launches, double* ms, double* bytes, double* flops) {
+  if (!ctx || !launches || !ms || !bytes || !flops) return PE_ERR_ARG;
+  *launches = ctx->prof_launches;
+  *ms = ctx->prof_ms;
+  *bytes = ctx->prof_bytes;
+  *flops = ctx->prof_flops;
+  ctx->prof_launches = 0;
+  ctx->prof_ms = ctx->prof_bytes = ctx->prof_flops = 0.0;
   return PE_OK;
 }
 
