@@ -11,6 +11,7 @@ import os
 import sys
 import time
 
+HBM_PEAK_GBS = 8000.0  # MI355X published HBM3E bandwidth
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -23,6 +24,7 @@ def main():
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
     ap.add_argument("--n", type=int, default=8192)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--roofline-kernel", default="block_update", choices=["block_update", "block_proj"])
     ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work for the baseline")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -46,6 +48,8 @@ def main():
         ctx.solve_prepared(staged)
         print(f"warmup {i}: {time.perf_counter() - tw:.3f} s", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
+    # per-launch HIP-event timing of the dominant kernel family, on the solve's stream
+    ctx.profile_enable(args.roofline_kernel)
     t0 = time.perf_counter()
     for i in range(args.steps):
         ts = time.perf_counter()
@@ -55,6 +59,17 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     ms = 1e3 * elapsed / max(args.steps, 1)
+    prof = ctx.profile_read()
+    launches, k_ms, k_bytes, k_flops = prof["launches"], prof["ms"], prof["bytes"], prof["flops"]
+    ctx.profile_enable(None)
+    roof = None
+    if launches > 0 and k_ms > 0:
+        achieved = k_bytes / (k_ms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": args.roofline_kernel,
+                "launches": launches, "avg_launch_us": 1e3 * k_ms / launches,
+                "algorithmic_bytes_per_launch": k_bytes / launches,
+                "flops_per_launch": k_flops / launches}
     rep = reps[0]
     got = outs[0].detach().cpu().numpy().T
 
@@ -101,6 +116,7 @@ def main():
                    "precision": args.precision},
         "rel_l2_vs_oracle": err,
         "report": rep,
+        "roofline": roof,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
