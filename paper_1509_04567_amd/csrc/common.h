@@ -55,6 +55,7 @@ struct ProbDev {
   int32_t l;               // block steps this cycle
   int32_t active;          // 1: participates in this cycle's kernels
   int32_t rows_u;          // rows per update chunk (>= bw); last chunk takes the remainder
+  int32_t rows_u_log2;     // rows_u is a power of two
   int32_t Cu;              // number of update chunks
   int32_t rows_p;          // rows per projection chunk
   int32_t Cp;              // number of projection chunks

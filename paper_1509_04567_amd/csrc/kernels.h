@@ -11,7 +11,16 @@ enum BlockMode : int { MODE_ARNOLDI = 0, MODE_GIVEN = 1, MODE_INIT = 2 };
 // dynamic LDS requested by the update kernel at most (bytes)
 constexpr int kUpdateLdsMax = 150 * 1024;
 // slot group handled by one projection workgroup
-constexpr int kSlotGroup = 2;
+constexpr int kSlotGroup = 4;
+// LDS doubles for the projection coefficients staged by the update kernel
+constexpr int kSb = 4096;
+
+// The TSQR combine of Cu stacked bw x bw factors runs register-resident (four waves)
+// when it fits; otherwise from LDS.
+__host__ __device__ inline bool combine_in_registers(int bw, int Cu) {
+  const int rpl = (Cu * bw + 255) / 256;
+  return (bw <= 8 && rpl <= 4) || (bw <= 16 && rpl <= 2);
+}
 
 // Y[:, c] = L X[:, c]
 void launch_stencil_cols(int64_t n, int per_point, const double* c3, const double* coef, const double* X,

@@ -102,7 +102,7 @@ __device__ __forceinline__ void stencil_coefs(const ProbDev& p, int64_t r, doubl
 
 // chunk of a row for the update (TSQR) partition: the last chunk takes the remainder
 __device__ __forceinline__ int chunk_of(const ProbDev& p, int64_t r) {
-  int64_t u = r / p.rows_u;
+  int64_t u = r >> p.rows_u_log2;
   return (int)(u < p.Cu - 1 ? u : p.Cu - 1);
 }
 
@@ -273,8 +273,8 @@ __device__ __forceinline__ void cgs2_qr_wave(double* X, int rows, int ld, int bw
 // unrolled to BWM >= bw so register indices are compile-time constants.  Dependence
 // test and replacement as in mgs2_qr.  `red` is LDS scratch of NW * BWM doubles.
 template <int BWM, int RPL, int NW>
-__device__ __forceinline__ void cgs2_team(double* X, int rows, int ld, int bw, double* R, uint64_t seed,
-                                          const double* ref, int stack, double* red) {
+__device__ __forceinline__ void cgs2_team(const double* Xi, int ldi, double* X, int ld, int rows, int bw, double* R,
+                                          uint64_t seed, const double* ref, int stack, double* red) {
   const int t = (NW == 1) ? (int)(threadIdx.x & 63) : (int)threadIdx.x;
   const int w = t >> 6;
   constexpr int T = 64 * NW;
@@ -283,7 +283,7 @@ __device__ __forceinline__ void cgs2_team(double* X, int rows, int ld, int bw, d
   for (int q = 0; q < RPL; ++q) {
     const int r = t + T * q;
 #pragma unroll
-    for (int a = 0; a < BWM; ++a) xr[q][a] = (a < bw && r < rows) ? X[r * ld + a] : 0.0;
+    for (int a = 0; a < BWM; ++a) xr[q][a] = (a < bw && r < rows) ? Xi[r * ldi + a] : 0.0;
   }
   // sum over the team of NA values (NA known at compile time); result in sd[]
   auto team_sums = [&](double* sd, int NA) {
@@ -382,18 +382,19 @@ __device__ __forceinline__ void cgs2_team(double* X, int rows, int ld, int bw, d
   }
 }
 
-// dispatch of the register-resident QR over block-width buckets and rows per thread
+// dispatch of the register-resident QR over block-width buckets and rows per thread;
+// Xi (ld ldi) is read once, the Q factor written to X (ld ld), which may alias Xi
 template <int NW>
-__device__ __forceinline__ bool cgs2_dispatch(double* X, int rows, int ld, int bw, double* R, uint64_t seed,
-                                              const double* ref, int stack, double* red) {
+__device__ __forceinline__ bool cgs2_dispatch(const double* Xi, int ldi, double* X, int ld, int rows, int bw, double* R,
+                                              uint64_t seed, const double* ref, int stack, double* red) {
   const int rpl = (rows + 64 * NW - 1) / (64 * NW);
   if (bw <= 8) {
-    if (rpl <= 1) { cgs2_team<8, 1, NW>(X, rows, ld, bw, R, seed, ref, stack, red); return true; }
-    if (rpl <= 2) { cgs2_team<8, 2, NW>(X, rows, ld, bw, R, seed, ref, stack, red); return true; }
-    if (rpl <= 4) { cgs2_team<8, 4, NW>(X, rows, ld, bw, R, seed, ref, stack, red); return true; }
+    if (rpl <= 1) { cgs2_team<8, 1, NW>(Xi, ldi, X, ld, rows, bw, R, seed, ref, stack, red); return true; }
+    if (rpl <= 2) { cgs2_team<8, 2, NW>(Xi, ldi, X, ld, rows, bw, R, seed, ref, stack, red); return true; }
+    if (rpl <= 4) { cgs2_team<8, 4, NW>(Xi, ldi, X, ld, rows, bw, R, seed, ref, stack, red); return true; }
   } else if (bw <= 16) {
-    if (rpl <= 1) { cgs2_team<16, 1, NW>(X, rows, ld, bw, R, seed, ref, stack, red); return true; }
-    if (rpl <= 2) { cgs2_team<16, 2, NW>(X, rows, ld, bw, R, seed, ref, stack, red); return true; }
+    if (rpl <= 1) { cgs2_team<16, 1, NW>(Xi, ldi, X, ld, rows, bw, R, seed, ref, stack, red); return true; }
+    if (rpl <= 2) { cgs2_team<16, 2, NW>(Xi, ldi, X, ld, rows, bw, R, seed, ref, stack, red); return true; }
   }
   return false;  // wider blocks use the LDS-resident cgs2_qr_wave
 }
@@ -455,100 +456,172 @@ void launch_add_column(int64_t n, int s, const double* G, int64_t ldG, const dou
 // ------------------------------------------------------------------------------------
 
 
-// Stage the Qs blocks that rows [g_lo, g_hi] (inclusive, no wrap) need into LDS.
-__device__ __forceinline__ int stage_qs(const ProbDev& p, const double* Qs, int64_t g_lo, int64_t g_hi, double* Qsl) {
-  const int bw2 = p.bw * p.bw;
-  const int u_lo = chunk_of(p, g_lo), u_hi = chunk_of(p, g_hi);
-  const int cnt = (u_hi - u_lo + 1) * bw2;
-  for (int e = threadIdx.x; e < cnt; e += blockDim.x) Qsl[e] = Qs[(int64_t)u_lo * bw2 + e];
-  return u_lo;
+// Bulk global -> LDS copy: cnt elements, element e read by src(e) and stored by
+// put(e, v).  Each thread keeps kBulkDepth loads in flight, so a phase costs one or two
+// memory round trips however many elements a thread handles (data written by other
+// workgroups comes from other XCDs with microsecond latency).
+constexpr int kBulkDepth = 8;
+template <typename Src, typename Put>
+__device__ __forceinline__ void bulk_load(int64_t cnt, Src src, Put put) {
+  const int T = blockDim.x;
+  for (int64_t e0 = threadIdx.x; e0 < cnt; e0 += kBulkDepth * (int64_t)T) {
+    double v[kBulkDepth];
+#pragma unroll
+    for (int k = 0; k < kBulkDepth; ++k) {
+      const int64_t e = e0 + (int64_t)k * T;
+      v[k] = e < cnt ? src(e) : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < kBulkDepth; ++k) {
+      const int64_t e = e0 + (int64_t)k * T;
+      if (e < cnt) put(e, v[k]);
+    }
+  }
 }
 
-// X (rows x bw, leading dimension ld, LDS) for rows [r0, r0 + rows) of the current pass.
-// In MODE_ARNOLDI pass 0 with from_tsqr, V_j rows r0-1 .. r0+rows are formed into Vh
-// (rows + 2 rows, LDS) and, when commit, written to basis block j.
+__device__ __forceinline__ int64_t wrap_row(int64_t g, int64_t n) { return g < 0 ? g + n : (g >= n ? g - n : g); }
+
+// Flat multi-segment copy global -> LDS: segment s moves cnt contiguous elements from
+// d (double) or f (float, when non-null) to dst.  Segment lookup is unrolled over NS so
+// no division or dynamic indexing is involved; kBulkDepth loads stay in flight.
+struct CopySeg {
+  const double* d;
+  const float* f;
+  int64_t cnt;
+  double* dst;
+};
+template <int NS>
+__device__ __forceinline__ void bulk_copy(const CopySeg (&sg)[NS]) {
+  const int T = blockDim.x;
+  int64_t total = 0;
+#pragma unroll
+  for (int q = 0; q < NS; ++q) total += sg[q].cnt;
+  for (int64_t e0 = threadIdx.x; e0 < total; e0 += kBulkDepth * (int64_t)T) {
+    double v[kBulkDepth];
+    double* dp[kBulkDepth];
+#pragma unroll
+    for (int k = 0; k < kBulkDepth; ++k) {
+      int64_t off = e0 + (int64_t)k * T;
+      const double* sd = nullptr;
+      const float* sf = nullptr;
+      double* dd = nullptr;
+#pragma unroll
+      for (int q = 0; q < NS; ++q) {
+        if (off >= 0 && off < sg[q].cnt) {
+          sd = sg[q].d + off;
+          sf = sg[q].f ? sg[q].f + off : nullptr;
+          dd = sg[q].dst + off;
+        }
+        off -= sg[q].cnt;
+      }
+      dp[k] = dd;
+      v[k] = dd ? (sf ? (double)*sf : *sd) : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < kBulkDepth; ++k)
+      if (dp[k]) *dp[k] = v[k];
+  }
+}
+
 template <typename TS>
-__device__ __forceinline__ void form_block(const ProbDev& p, int mode, int pass, int j, int64_t r0, int rows, double* X, int ld,
-                           double* Vh, double* Qsl, bool from_tsqr, bool commit) {
+__device__ __forceinline__ CopySeg basis_seg(const TS* src, int64_t cnt, double* dst);
+template <>
+__device__ __forceinline__ CopySeg basis_seg<double>(const double* src, int64_t cnt, double* dst) {
+  return CopySeg{src, nullptr, cnt, dst};
+}
+template <>
+__device__ __forceinline__ CopySeg basis_seg<float>(const float* src, int64_t cnt, double* dst) {
+  return CopySeg{nullptr, src, cnt, dst};
+}
+
+// Input block X (rows x bw, leading dimension ld, LDS) of the update kernel's chunk
+// [r0, r0 + rows) (one TSQR chunk).  Qrow: LDS staging of (rows + 2) x bw doubles, Qsl
+// of one bw x bw combine block.  Row/column walks are per thread (col = t % bw fixed) so
+// no division sits in the loops.
+template <typename TS>
+__device__ __forceinline__ void form_block(const ProbDev& p, int mode, int pass, int j, int64_t r0, int rows, double* X,
+                                           int ld, double* Qrow, double* Qsl) {
   const int bw = p.bw, bw2 = bw * bw;
   const int t = threadIdx.x, T = blockDim.x;
   const int64_t n = p.n;
-  TS* V = basis_ptr<TS>(p);
+  const TS* V = basis_ptr<TS>(p);
   const int64_t blk = n * bw;
-  if (mode == MODE_INIT) {
-    for (int e = t; e < rows * bw; e += T) {
-      const int rr = e / bw, col = e % bw;
-      const int64_t g = r0 + rr;
-      X[rr * ld + col] = col < p.m ? p.U[(int64_t)col * n + g] : p.x[g];
-    }
+  const int col = t % bw, rstep = T / bw, rr0 = t / bw;
+  const bool act = rr0 < rstep;
+  if (mode == MODE_INIT) {  // [U | x], column-major sources: coalesce along rows
+    bulk_load(
+        (int64_t)rows * bw,
+        [&](int64_t e) -> double {
+          const int c = (int)(e / rows);
+          const int64_t g = r0 + e % rows;
+          return c < p.m ? p.U[(int64_t)c * n + g] : p.x[g];
+        },
+        [&](int64_t e, double v) { X[(e % rows) * ld + e / rows] = v; });
   } else if (pass == 0 && mode == MODE_GIVEN) {
-    for (int e = t; e < rows * bw; e += T) {
-      const int rr = e / bw, col = e % bw;
-      const int gc = j * bw + col;
-      X[rr * ld + col] = gc < p.m ? p.Xg[(int64_t)gc * p.ldXg + r0 + rr] : 0.0;
-    }
-  } else if (pass == 0) {  // MODE_ARNOLDI: W = L V_j
-    if (from_tsqr) {
-      const int u_lo = stage_qs(p, p.Qs2, r0, r0 + rows - 1, Qsl);
-      __syncthreads();
-      for (int e = t; e < (rows + 2) * bw; e += T) {
-        const int rr = e / bw, col = e % bw;
-        int64_t g = r0 - 1 + rr;
-        double v;
-        if (rr >= 1 && rr <= rows) {
-          const double* q = p.Qloc2 + g * bw;
-          const double* sq = Qsl + (int64_t)(chunk_of(p, g) - u_lo) * bw2 + col;
-          v = 0.0;
-          for (int k = 0; k < bw; ++k) v += q[k] * sq[k * bw];
-        } else {
-          if (g < 0) g += n;
-          if (g >= n) g -= n;
-          v = tsqr_entry(p, p.Qloc2, p.Qs2, g, col);
-        }
-        const TS vs = (TS)v;
-        Vh[rr * ld + col] = (double)vs;
-        if (commit && rr >= 1 && rr <= rows) V[(int64_t)j * blk + g * bw + col] = vs;
-      }
-      __syncthreads();
-      for (int e = t; e < rows * bw; e += T) {
-        const int rr = e / bw, col = e % bw;
+    bulk_load(
+        (int64_t)rows * bw,
+        [&](int64_t e) -> double {
+          const int gc = j * bw + (int)(e / rows);
+          return gc < p.m ? p.Xg[(int64_t)gc * p.ldXg + r0 + e % rows] : 0.0;
+        },
+        [&](int64_t e, double v) { X[(e % rows) * ld + e / rows] = v; });
+  } else if (pass == 0) {  // MODE_ARNOLDI: W = L V_j, V_j read from the basis
+    const TS* vj = V + (int64_t)j * blk;
+    const int64_t gm = wrap_row(r0 - 1, n), gp = wrap_row(r0 + rows, n);
+    const CopySeg sg[3] = {basis_seg<TS>(vj + gm * bw, bw, Qrow),
+                           basis_seg<TS>(vj + r0 * bw, (int64_t)rows * bw, Qrow + bw),
+                           basis_seg<TS>(vj + gp * bw, bw, Qrow + (int64_t)(rows + 1) * bw)};
+    bulk_copy(sg);
+    __syncthreads();
+    if (act)
+      for (int rr = rr0; rr < rows; rr += rstep) {
         double cm, cz, cp;
         stencil_coefs(p, r0 + rr, cm, cz, cp);
-        X[rr * ld + col] = cm * Vh[rr * ld + col] + cz * Vh[(rr + 1) * ld + col] + cp * Vh[(rr + 2) * ld + col];
+        X[rr * ld + col] = cm * Qrow[rr * bw + col] + cz * Qrow[(rr + 1) * bw + col] + cp * Qrow[(rr + 2) * bw + col];
       }
-    } else {
-      const TS* vj = V + (int64_t)j * blk;
-      for (int e = t; e < rows * bw; e += T) {
-        const int rr = e / bw, col = e % bw;
-        const int64_t g = r0 + rr;
-        const int64_t gm = g == 0 ? n - 1 : g - 1, gp = g == n - 1 ? 0 : g + 1;
-        double cm, cz, cp;
-        stencil_coefs(p, g, cm, cz, cp);
-        X[rr * ld + col] =
-            cm * (double)vj[gm * bw + col] + cz * (double)vj[g * bw + col] + cp * (double)vj[gp * bw + col];
-      }
-    }
-  } else {  // pass 1: X = Q1
-    const int u_lo = stage_qs(p, p.Qs1, r0, r0 + rows - 1, Qsl);
+  } else {  // pass 1: X = Q1 = Qloc1 Qs1 on this chunk
+    const CopySeg sg[2] = {{p.Qloc1 + r0 * bw, nullptr, (int64_t)rows * bw, Qrow},
+                           {p.Qs1 + (int64_t)chunk_of(p, r0) * bw2, nullptr, bw2, Qsl}};
+    bulk_copy(sg);
     __syncthreads();
-    for (int e = t; e < rows * bw; e += T) {
-      const int rr = e / bw, col = e % bw;
-      const int64_t g = r0 + rr;
-      const double* q = p.Qloc1 + g * bw;
-      const double* sq = Qsl + (int64_t)(chunk_of(p, g) - u_lo) * bw2 + col;
-      double v = 0.0;
-      for (int k = 0; k < bw; ++k) v += q[k] * sq[k * bw];
-      X[rr * ld + col] = v;
-    }
+    if (act)
+      for (int rr = rr0; rr < rows; rr += rstep) {
+        double v = 0.0;
+        for (int k = 0; k < bw; ++k) v += Qrow[rr * bw + k] * Qsl[k * bw + col];
+        X[rr * ld + col] = v;
+      }
   }
   __syncthreads();
 }
 
+// Cross-workgroup hand-off inside a kernel: data for the last workgroup is stored
+// write-through at agent scope, every thread waits for its stores, then thread 0 bumps
+// the counter.  The last workgroup invalidates its L2 view (agent-scope acquire) before
+// reading.  No L2 write-back is needed, unlike a full __threadfence per workgroup.
+__device__ __forceinline__ void st_agent(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ bool arrive_last(unsigned* counter, unsigned expected, int* flag) {
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (threadIdx.x == 0) *flag = (atomicAdd(counter, 1u) == expected - 1);
+  __syncthreads();
+  const bool last = *flag != 0;
+  if (last) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  return last;
+}
+
+// Projections S_i = V_i^T X, i in the workgroup's slot group, on one row chunk.  One
+// bulk phase stages everything the chunk needs (TSQR factors of the input block and the
+// basis rows of the group's slots); the input block is formed in LDS (in MODE_ARNOLDI
+// pass 0: V_j = Qloc2 Qs2 with its halo, committed to the basis by slot group 0, then
+// W = L V_j); each thread then owns one output of one slot over all rows of the chunk.
+// The last workgroup of a slot group reduces the Cp chunk partials into S.
 template <typename TS>
 __global__ __launch_bounds__(256) void k_block_proj(ProbDev* probs, int j, int nb, int pass, int mode) {
   const ProbDev& p = probs[blockIdx.y];
   if (!p.active || j >= p.l) return;
-  const int bw = p.bw, nout = bw * bw;
+  const int bw = p.bw, nout = bw * bw, bw2 = nout;
   const int grp = blockIdx.x / p.Cp;
   const int c = blockIdx.x % p.Cp;
   const int ngroups = (nb + kSlotGroup - 1) / kSlotGroup;
@@ -557,84 +630,218 @@ __global__ __launch_bounds__(256) void k_block_proj(ProbDev* probs, int j, int n
   const int64_t r0 = (int64_t)c * p.rows_p;
   if (r0 >= n) return;
   const int rows = (int)(r0 + p.rows_p < n ? p.rows_p : n - r0);
-  const int ld = bw + 1;
   const int t = threadIdx.x;
   extern __shared__ double smem[];
-  double* Xs = smem;                                   // rows_p * ld
-  double* Vh = Xs + (int64_t)p.rows_p * ld;            // (rows_p + 2) * ld
-  double* Vs = Vh + (int64_t)(p.rows_p + 2) * ld;      // rows_p * ld
-  double* red = Vs + (int64_t)p.rows_p * ld;           // 256
-  double* Qsl = red + 256;                             // (rows_p / rows_u + 2) * bw^2
+  // unpadded row-major tiles: every access below is a broadcast or walks consecutive rows
+  double* Xs = smem;                                           // rows_p * bw
+  double* Vh = Xs + (int64_t)p.rows_p * bw;                    // (rows_p + 2) * bw
+  double* Vs = Vh + (int64_t)(p.rows_p + 2) * bw;              // kSlotGroup * rows_p * bw
+  double* red = Vs + (int64_t)kSlotGroup * p.rows_p * bw;      // 256
+  double* Qrow = red + 256;                                    // (rows_p + 2) * bw
+  double* Qsl = Qrow + (int64_t)(p.rows_p + 2) * bw;           // (rows_p / rows_u + 4) * bw^2
   __shared__ int is_last;
-  const TS* V = basis_ptr<TS>(p);
+  TS* V = basis_ptr<TS>(p);
   const int64_t blk = n * bw;
   const bool arn0 = (mode == MODE_ARNOLDI && pass == 0);
-  form_block<TS>(p, mode, pass, j, r0, rows, Xs, ld, Vh, Qsl, true, arn0 && grp == 0);
-
-  double* part = p.Part + (int64_t)pass * p.Cp * p.nbmax * nout;
+  const bool given0 = (mode == MODE_GIVEN && pass == 0);
   const int i_lo = grp * kSlotGroup, i_hi = min(nb, i_lo + kSlotGroup);
-  for (int i = i_lo; i < i_hi; ++i) {
-    const double* Vi;
-    if (arn0 && i == j) {
-      Vi = Vh + ld;  // rows 1..rows of the halo block
-    } else {
-      const TS* src = V + (int64_t)i * blk + r0 * bw;
-      for (int e = t; e < rows * bw; e += blockDim.x) Vs[(e / bw) * ld + (e % bw)] = (double)src[e];
-      __syncthreads();
-      Vi = Vs;
+  const int col = t % bw, rstep = 256 / bw, rr0 = t / bw;
+  const bool act = rr0 < rstep;
+
+  // ---- one bulk phase: input-block factors, then the slot rows
+  const int u_lo = chunk_of(p, r0), u_hi = chunk_of(p, r0 + rows - 1);
+  const int nm = u_hi - u_lo + 1;
+  {
+    CopySeg sg[6 + kSlotGroup];
+#pragma unroll
+    for (int q = 0; q < 6 + kSlotGroup; ++q) sg[q] = CopySeg{nullptr, nullptr, 0, Qrow};
+    if (arn0) {
+      const int64_t gm = wrap_row(r0 - 1, n), gp = wrap_row(r0 + rows, n);
+      sg[0] = CopySeg{p.Qloc2 + gm * bw, nullptr, bw, Qrow};
+      sg[1] = CopySeg{p.Qloc2 + r0 * bw, nullptr, (int64_t)rows * bw, Qrow + bw};
+      sg[2] = CopySeg{p.Qloc2 + gp * bw, nullptr, bw, Qrow + (int64_t)(rows + 1) * bw};
+      sg[3] = CopySeg{p.Qs2 + (int64_t)u_lo * bw2, nullptr, (int64_t)nm * bw2, Qsl};
+      sg[4] = CopySeg{p.Qs2 + (int64_t)chunk_of(p, gm) * bw2, nullptr, bw2, Qsl + (int64_t)nm * bw2};
+      sg[5] = CopySeg{p.Qs2 + (int64_t)chunk_of(p, gp) * bw2, nullptr, bw2, Qsl + (int64_t)(nm + 1) * bw2};
+    } else if (!given0) {
+      sg[1] = CopySeg{p.Qloc1 + r0 * bw, nullptr, (int64_t)rows * bw, Qrow};
+      sg[3] = CopySeg{p.Qs1 + (int64_t)u_lo * bw2, nullptr, (int64_t)nm * bw2, Qsl};
     }
-    double* mine = part + ((int64_t)i * p.Cp + c) * nout;
-    if (nout <= 256) {
-      const int G = 256 / nout;
-      const int o = t % nout, g = t / nout;
-      double acc = 0.0;
-      if (g < G) {
-        const int a = o / bw, b = o % bw;
-        for (int rr = g; rr < rows; rr += G) acc += Vi[rr * ld + a] * Xs[rr * ld + b];
+#pragma unroll
+    for (int kk = 0; kk < kSlotGroup; ++kk) {
+      const int i = i_lo + kk;
+      if (i < i_hi && !(arn0 && i == j))
+        sg[6 + kk] = basis_seg<TS>(V + (int64_t)i * blk + r0 * bw, (int64_t)rows * bw, Vs + (int64_t)kk * p.rows_p * bw);
+    }
+    bulk_copy(sg);
+  }
+  if (given0)
+    bulk_load(
+        (int64_t)rows * bw,
+        [&](int64_t e) -> double {
+          const int gc = j * bw + (int)(e / rows);
+          return gc < p.m ? p.Xg[(int64_t)gc * p.ldXg + r0 + e % rows] : 0.0;
+        },
+        [&](int64_t e, double v) { Xs[(e % rows) * bw + e / rows] = v; });
+  __syncthreads();
+  // ---- form the input block
+  if (arn0) {
+    const bool commit = (grp == 0);
+    if (act)
+      for (int rr = rr0; rr < rows + 2; rr += rstep) {
+        const int slot = rr == 0 ? nm : (rr == rows + 1 ? nm + 1 : chunk_of(p, r0 - 1 + rr) - u_lo);
+        const double* q = Qrow + rr * bw;
+        const double* sq = Qsl + slot * bw2 + col;
+        double v = 0.0;
+        for (int k = 0; k < bw; ++k) v += q[k] * sq[k * bw];
+        const TS vs = (TS)v;
+        Vh[rr * bw + col] = (double)vs;
+        if (commit && rr >= 1 && rr <= rows) V[(int64_t)j * blk + (r0 - 1 + rr) * bw + col] = vs;
       }
-      if (g < G) red[g * nout + o] = acc;
-      __syncthreads();
-      if (t < nout) {
-        double sacc = 0.0;
-        for (int gg = 0; gg < G; ++gg) sacc += red[gg * nout + t];
-        mine[t] = sacc;
+    __syncthreads();
+    if (act)
+      for (int rr = rr0; rr < rows; rr += rstep) {
+        double cm, cz, cp;
+        stencil_coefs(p, r0 + rr, cm, cz, cp);
+        Xs[rr * bw + col] = cm * Vh[rr * bw + col] + cz * Vh[(rr + 1) * bw + col] + cp * Vh[(rr + 2) * bw + col];
       }
-    } else {
-      for (int o = t; o < nout; o += blockDim.x) {
-        const int a = o / bw, b = o % bw;
-        double acc = 0.0;
-        for (int rr = 0; rr < rows; ++rr) acc += Vi[rr * ld + a] * Xs[rr * ld + b];
-        mine[o] = acc;
+    if (j >= i_lo && j < i_hi) {  // slot j is V_j itself
+      double* dst = Vs + (int64_t)(j - i_lo) * p.rows_p * bw;
+      for (int e = t; e < rows * bw; e += 256) dst[e] = Vh[bw + e];
+    }
+  } else if (!given0) {  // pass 1: X = Q1 = Qloc1 Qs1
+    if (act)
+      for (int rr = rr0; rr < rows; rr += rstep) {
+        const double* q = Qrow + rr * bw;
+        const double* sq = Qsl + (int64_t)(chunk_of(p, r0 + rr) - u_lo) * bw2 + col;
+        double v = 0.0;
+        for (int k = 0; k < bw; ++k) v += q[k] * sq[k * bw];
+        Xs[rr * bw + col] = v;
       }
+  }
+  __syncthreads();
+  // ---- chunk partials: one output of one slot per thread, all rows
+  double* part = p.Part + (int64_t)pass * p.Cp * p.nbmax * nout;
+  for (int e = t; e < (i_hi - i_lo) * nout; e += 256) {
+    const int kk = e / nout, o = e - kk * nout, a = o / bw, b = o - a * bw;
+    const double* Vi = Vs + (int64_t)kk * p.rows_p * bw;
+    double acc0 = 0.0, acc1 = 0.0;
+    int rr = 0;
+    for (; rr + 1 < rows; rr += 2) {
+      acc0 += Vi[rr * bw + a] * Xs[rr * bw + b];
+      acc1 += Vi[(rr + 1) * bw + a] * Xs[(rr + 1) * bw + b];
+    }
+    if (rr < rows) acc0 += Vi[rr * bw + a] * Xs[rr * bw + b];
+    st_agent(part + ((int64_t)(i_lo + kk) * p.Cp + c) * nout + o, acc0 + acc1);
+  }
+  // ---- the last workgroup of this slot group reduces the Cp partials of its slots
+  if (!arrive_last(p.cnt + pass * p.nbmax + grp, (unsigned)p.Cp, &is_last)) return;
+  double* Sout = p.S + (int64_t)pass * p.nbmax * nout;
+  // G threads per output, each summing a strided subset of the partials with 32 loads
+  // in flight
+  const int total = (i_hi - i_lo) * nout;
+  const int G = total >= 256 ? 1 : 256 / total;
+  const int per = 256 / G;
+  for (int e0 = 0; e0 < total; e0 += per) {
+    const int e = e0 + t / G, g = t % G;
+    double acc = 0.0;
+    if (t < per * G && e < total) {
+      const double* ps = part + (int64_t)(i_lo + e / nout) * p.Cp * nout + (e % nout);
+      for (int cc = g; cc < p.Cp; cc += 32 * G) {
+        double v[32];
+#pragma unroll
+        for (int k = 0; k < 32; ++k) {
+          const int c2 = cc + k * G;
+          v[k] = c2 < p.Cp ? ps[(int64_t)c2 * nout] : 0.0;
+        }
+#pragma unroll
+        for (int k = 0; k < 32; ++k) acc += v[k];
+      }
+    }
+    red[t] = acc;
+    __syncthreads();
+    if (g == 0 && t < per * G && e < total) {
+      double sacc = 0.0;
+      for (int gg = 0; gg < G; ++gg) sacc += red[t + gg];
+      Sout[(int64_t)(i_lo + e / nout) * nout + (e % nout)] = sacc;
     }
     __syncthreads();
   }
-  // the last workgroup of this slot group reduces the Cp partials of its slots
-  __threadfence();
-  __syncthreads();
-  if (t == 0) {
-    const unsigned old = atomicAdd(p.cnt + pass * p.nbmax + grp, 1u);
-    is_last = (old == (unsigned)(p.Cp - 1));
-  }
-  __syncthreads();
-  if (is_last) {
-    __threadfence();
-    double* Sout = p.S + (int64_t)pass * p.nbmax * nout;
-    for (int e = t; e < (i_hi - i_lo) * nout; e += blockDim.x) {
-      const int i = i_lo + e / nout, o = e % nout;
-      const double* ps = part + (int64_t)i * p.Cp * nout + o;
-      double sacc = 0.0;
-      for (int cc = 0; cc < p.Cp; ++cc) sacc += __builtin_nontemporal_load(ps + (int64_t)cc * nout);
-      Sout[(int64_t)i * nout + o] = sacc;
-    }
-    if (t == 0) atomicExch(p.cnt + pass * p.nbmax + grp, 0u);
-  }
+  if (t == 0) atomicExch(p.cnt + pass * p.nbmax + grp, 0u);
 }
 
-// slots of the projections subtracted per LDS batch in the update kernel
-__host__ __device__ __forceinline__ int update_batch_slots(int bw, int rows_u) {
-  int k = 8192 / (bw * bw + 2 * rows_u * bw);
-  return k < 1 ? 1 : (k > 8 ? 8 : k);
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+// X (rows x bw, LDS, ld) -= sum_{i < nb} V_i[rows] S_i on f64 MFMA (16x16x4): wave w takes
+// 16-row tiles w, w+4, ...; the A operand (-V rows) streams from global memory with PF
+// slots of loads in flight, the B operand (S_i, row-major bw x bw) from LDS, staged in
+// batches of kSb doubles.  Accumulator layout: row = lane/16 + 4v, column = lane%16.
+template <int BWM, typename TS>
+__device__ __forceinline__ void subtract_proj_mfma(const TS* V, int64_t blk, const double* Sp, int nb, int64_t r0,
+                                                   int rows, int bw, double* X, int ld, double* Sb) {
+  constexpr int KT = BWM / 4;                   // k-steps per slot
+  constexpr int NT = (BWM + 15) / 16;           // 16-column tiles
+  constexpr int PF = BWM <= 8 ? 8 : (BWM <= 16 ? 4 : 2);
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int nout = bw * bw;
+  const int ksb = max(1, kSb / nout);
+  const int RT = (rows + 15) / 16;
+  const int li = lane & 15, lk = lane >> 4;
+  for (int i0 = 0; i0 < nb; i0 += ksb) {
+    const int k = min(ksb, nb - i0);
+    __syncthreads();
+    bulk_load(
+        (int64_t)k * nout, [&](int64_t e) -> double { return Sp[(int64_t)i0 * nout + e]; },
+        [&](int64_t e, double v) { Sb[e] = v; });
+    __syncthreads();
+    for (int rt = w; rt < RT; rt += 4) {
+      const int row = rt * 16 + li;  // A-operand row of this lane
+      const bool rok = row < rows;
+      dbl4 acc[NT];
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int rr = rt * 16 + lk + 4 * v, cc = nt * 16 + li;
+          acc[nt][v] = (rr < rows && cc < bw) ? X[rr * ld + cc] : 0.0;
+        }
+      for (int kk0 = 0; kk0 < k; kk0 += PF) {
+        double a[PF][KT];
+#pragma unroll
+        for (int f = 0; f < PF; ++f) {
+          const TS* vr = V + (int64_t)(i0 + kk0 + f) * blk + (r0 + row) * bw;
+#pragma unroll
+          for (int kt = 0; kt < KT; ++kt) {
+            const int ka = kt * 4 + lk;
+            a[f][kt] = (kk0 + f < k && rok && ka < bw) ? -(double)vr[ka] : 0.0;
+          }
+        }
+#pragma unroll
+        for (int f = 0; f < PF; ++f) {
+          if (kk0 + f >= k) break;
+          const double* sb = Sb + (kk0 + f) * nout;
+#pragma unroll
+          for (int kt = 0; kt < KT; ++kt) {
+            const int ka = kt * 4 + lk;
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) {
+              const int cc = nt * 16 + li;
+              const double b = (ka < bw && cc < bw) ? sb[ka * bw + cc] : 0.0;
+              acc[nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[f][kt], b, acc[nt], 0, 0, 0);
+            }
+          }
+        }
+      }
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int rr = rt * 16 + lk + 4 * v, cc = nt * 16 + li;
+          if (rr < rows && cc < bw) X[rr * ld + cc] = acc[nt][v];
+        }
+    }
+  }
+  __syncthreads();
 }
 
 template <typename TS>
@@ -651,21 +858,44 @@ __global__ __launch_bounds__(256) void k_block_update(ProbDev* probs, int j, int
   const int rmax = 2 * p.rows_u;
   const int ld = bw + 1;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  const int KS = update_batch_slots(bw, p.rows_u);
+  const bool reg_comb = combine_in_registers(bw, p.Cu);
   extern __shared__ double smem[];
-  const int64_t xs_cap = (int64_t)ld * (rmax > p.Cu * bw ? rmax : p.Cu * bw);
+  const int64_t xs_cap = (int64_t)ld * (reg_comb || rmax > p.Cu * bw ? rmax : p.Cu * bw);
   double* X = smem;                               // xs_cap
-  double* Sb = X + xs_cap;                        // KS * bw^2
-  double* Vb = Sb + (int64_t)KS * nout;           // KS * rmax * bw
-  double* Rl = Vb + (int64_t)KS * rmax * bw;      // bw^2
+  double* Sb = X + xs_cap;                        // kSb
+  double* Rl = Sb + kSb;                          // bw^2
   double* Rn = Rl + nout;                         // bw
-  double* Qsl = Rn + bw;                          // bw^2 (one chunk's combine factor)
+  double* Qrow = Rn + bw;                         // (rmax + 2) * bw
+  double* Qsl = Qrow + (int64_t)(rmax + 2) * bw;  // max(bw^2, 128)
   __shared__ int is_last;
   const TS* V = basis_ptr<TS>(p);
   const int64_t blk = n * bw;
+  const bool hcol = (mode != MODE_INIT && pass == 1);
 
+  // 0. pass 1: blocks i < nb of column block j of H (of R in MODE_GIVEN), one block per
+  //    workgroup: H_ij = S1_i + S2_i Rf1 (the block nb needs the combine below)
+  if (hcol) {
+    const double* R1 = p.Rf;
+    const double* S1 = p.S;
+    const double* S2 = p.S + (int64_t)p.nbmax * nout;
+    for (int i = u; i < nb; i += p.Cu)
+      for (int o = t; o < nout; o += 256) {
+        const int a = o / bw, b = o % bw;
+        double v = S1[(int64_t)i * nout + o];
+#pragma unroll 8
+        for (int k = 0; k < bw; ++k) v += S2[(int64_t)i * nout + a * bw + k] * R1[k * bw + b];
+        p.H[(int64_t)(i * bw + a) + p.ldH * (int64_t)(j * bw + b)] = v;
+      }
+    // rows below the subdiagonal block stay zero
+    const int64_t r_lo = (int64_t)(nb + 1) * bw;
+    const int64_t zcnt = (p.ldH - r_lo) * bw;
+    for (int64_t e = (int64_t)u * 256 + t; e < zcnt; e += (int64_t)p.Cu * 256) {
+      const int64_t rr = r_lo + e / bw, b = e % bw;
+      p.H[rr + p.ldH * (int64_t)(j * bw + b)] = 0.0;
+    }
+  }
   // 1. input block of this chunk
-  form_block<TS>(p, mode, pass, j, r0, rows, X, ld, nullptr, Qsl, false, false);
+  form_block<TS>(p, mode, pass, j, r0, rows, X, ld, Qrow, Qsl);
   // reference column norms before the projections
   for (int b = w; b < bw; b += 4) {
     double s0 = 0.0;
@@ -673,92 +903,95 @@ __global__ __launch_bounds__(256) void k_block_update(ProbDev* probs, int j, int
     s0 = wave_sum(s0);
     if (lane == 0) {
       Rn[b] = sqrt(s0);
-      p.Cn[(int64_t)u * bw + b] = s0;
+      st_agent(p.Cn + (int64_t)u * bw + b, s0);
     }
   }
-  // 2. X -= sum_i V_i S_i, KS slots per LDS batch
+  // 2. X -= sum_i V_i S_i
   if (mode != MODE_INIT) {
     const double* Sp = p.S + (int64_t)pass * p.nbmax * nout;
-    for (int i0 = 0; i0 < nb; i0 += KS) {
-      const int k = min(KS, nb - i0);
-      __syncthreads();
-      for (int e = t; e < k * nout; e += 256) Sb[e] = Sp[(int64_t)i0 * nout + e];
-      for (int kk = 0; kk < k; ++kk) {
-        const TS* src = V + (int64_t)(i0 + kk) * blk + r0 * bw;
-        for (int e = t; e < rows * bw; e += 256) Vb[(int64_t)kk * rmax * bw + e] = (double)src[e];
-      }
-      __syncthreads();
-      for (int e = t; e < rows * bw; e += 256) {
-        const int rr = e / bw, b = e % bw;
-        double acc = X[rr * ld + b];
-        for (int kk = 0; kk < k; ++kk) {
-          const double* vr = Vb + (int64_t)kk * rmax * bw + rr * bw;
-          const double* sb = Sb + kk * nout + b;
-          for (int a = 0; a < bw; ++a) acc -= vr[a] * sb[a * bw];
-        }
-        X[rr * ld + b] = acc;
-      }
-    }
+    if (bw <= 8)
+      subtract_proj_mfma<8, TS>(V, blk, Sp, nb, r0, rows, bw, X, ld, Sb);
+    else if (bw <= 16)
+      subtract_proj_mfma<16, TS>(V, blk, Sp, nb, r0, rows, bw, X, ld, Sb);
+    else
+      subtract_proj_mfma<32, TS>(V, blk, Sp, nb, r0, rows, bw, X, ld, Sb);
   }
   // 3. local QR of the chunk (wave 0)
   for (int o = t; o < nout; o += 256) Rl[o] = 0.0;
   __syncthreads();
   const uint64_t seed = ((uint64_t)(j + 1) * 1000003ull + (uint64_t)pass * 7919ull + (uint64_t)mode * 104729ull) *
                             0x100000001B3ull + (uint64_t)r0;
+  // Q of the chunk goes straight from registers to Qloc (row-major, ld bw)
+  double* Qloc = (pass == 0 ? p.Qloc1 : p.Qloc2) + r0 * bw;
+  __shared__ int reg_qr;
+  if (t == 0) reg_qr = 1;
+  __syncthreads();
   if (w == 0) {
-    if (!cgs2_dispatch<1>(X, rows, ld, bw, Rl, seed, Rn, 0, nullptr)) cgs2_qr_wave(X, rows, ld, bw, Rl, seed, Rn, 0);
+    if (!cgs2_dispatch<1>(X, ld, Qloc, bw, rows, bw, Rl, seed, Rn, 0, nullptr)) {
+      cgs2_qr_wave(X, rows, ld, bw, Rl, seed, Rn, 0);
+      if (lane == 0) reg_qr = 0;
+    }
   }
   __syncthreads();
-  double* Qloc = pass == 0 ? p.Qloc1 : p.Qloc2;
-  for (int e = t; e < rows * bw; e += 256) Qloc[(r0 + e / bw) * bw + (e % bw)] = X[(e / bw) * ld + (e % bw)];
-  for (int o = t; o < nout; o += 256) p.Rloc[(int64_t)u * nout + o] = Rl[o];
+  if (!reg_qr) {
+    const int col = t % bw, rstep = 256 / bw;
+    if (t / bw < rstep)
+      for (int rr = t / bw; rr < rows; rr += rstep) Qloc[rr * bw + col] = X[rr * ld + col];
+  }
+  for (int o = t; o < nout; o += 256) st_agent(p.Rloc + (int64_t)u * nout + o, Rl[o]);
   // 4. TSQR combine by the last workgroup
-  __threadfence();
-  __syncthreads();
-  if (t == 0) {
-    const unsigned old = atomicAdd(p.cnt + 2 * p.nbmax, 1u);
-    is_last = (old == (unsigned)(p.Cu - 1));
-  }
-  __syncthreads();
-  if (!is_last) return;
-  __threadfence();
+  if (!arrive_last(p.cnt + 2 * p.nbmax, (unsigned)p.Cu, &is_last)) return;
   double* Qs = pass == 0 ? p.Qs1 : p.Qs2;
   const int srows = p.Cu * bw;
-  for (int e = t; e < srows * bw; e += 256) X[(e / bw) * ld + (e % bw)] = __builtin_nontemporal_load(p.Rloc + e);
   for (int o = t; o < nout; o += 256) Rl[o] = 0.0;
+  {
+    // global reference norms: 256 / bw threads per column, eight loads in flight each
+    const int per = 256 / bw, b = t % bw, k = t / bw;
+    double acc = 0.0;
+    if (k < per)
+      for (int uu = k; uu < p.Cu; uu += 8 * per) {
+        double v[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const int u2 = uu + q * per;
+          v[q] = u2 < p.Cu ? p.Cn[(int64_t)u2 * bw + b] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) acc += v[q];
+      }
+    Sb[t] = acc;  // the coefficient buffer is free after the subtraction
+  }
+  __syncthreads();
   for (int b = t; b < bw; b += 256) {
     double s0 = 0.0;
-    for (int uu = 0; uu < p.Cu; ++uu) s0 += __builtin_nontemporal_load(p.Cn + (int64_t)uu * bw + b);
+    for (int k = 0; k < 256 / bw; ++k) s0 += Sb[k * bw + b];
     Rn[b] = sqrt(s0);
   }
   __syncthreads();
-  if (!cgs2_dispatch<4>(X, srows, ld, bw, Rl, seed ^ 0x5bd1e995ull, Rn, bw, Qsl)) {
-    if (w == 0) cgs2_qr_wave(X, srows, ld, bw, Rl, seed ^ 0x5bd1e995ull, Rn, bw);
+  const uint64_t cseed = seed ^ 0x5bd1e995ull;
+  if (reg_comb) {
+    // stacked chunk factors read straight from global memory into registers
+    cgs2_dispatch<4>(p.Rloc, bw, Qs, bw, srows, bw, Rl, cseed, Rn, bw, Qsl);
+    __syncthreads();
+  } else {
+    bulk_load(
+        (int64_t)srows * bw, [&](int64_t e) -> double { return p.Rloc[e]; },
+        [&](int64_t e, double v) { X[(e / bw) * ld + (e % bw)] = v; });
+    __syncthreads();
+    if (w == 0) cgs2_qr_wave(X, srows, ld, bw, Rl, cseed, Rn, bw);
+    __syncthreads();
+    for (int e = t; e < srows * bw; e += 256) Qs[e] = X[(e / bw) * ld + (e % bw)];
   }
-  __syncthreads();
-  for (int e = t; e < srows * bw; e += 256) Qs[e] = X[(e / bw) * ld + (e % bw)];
   double* Rout = p.Rf + (mode == MODE_INIT ? 2 : pass) * nout;
   for (int o = t; o < nout; o += 256) Rout[o] = Rl[o];
-  if (mode != MODE_INIT && pass == 1) {
-    // W = V (S1 + S2 Rf1) + Q2 (Rf2 Rf1): column block j of H (of R in MODE_GIVEN)
-    const int64_t r_lo = (int64_t)(nb + 1) * bw;
-    for (int64_t e = t; e < (p.ldH - r_lo) * bw; e += 256) {
-      const int64_t rr = r_lo + e / bw, b = e % bw;
-      p.H[rr + p.ldH * (int64_t)(j * bw + b)] = 0.0;
-    }
+  if (hcol) {
+    // W = V (S1 + S2 Rf1) + Q2 (Rf2 Rf1): the subdiagonal block of column block j
     const double* R1 = p.Rf;
-    const double* S1 = p.S;
-    const double* S2 = p.S + (int64_t)p.nbmax * nout;
-    for (int e = t; e < (nb + 1) * nout; e += 256) {
-      const int i = e / nout, o = e % nout, a = o / bw, b = o % bw;
+    for (int o = t; o < nout; o += 256) {
+      const int a = o / bw, b = o % bw;
       double v = 0.0;
-      if (i < nb) {
-        v = S1[(int64_t)i * nout + o];
-        for (int k = 0; k < bw; ++k) v += S2[(int64_t)i * nout + a * bw + k] * R1[k * bw + b];
-      } else {
-        for (int k = 0; k < bw; ++k) v += Rl[a * bw + k] * R1[k * bw + b];
-      }
-      p.H[(int64_t)(i * bw + a) + p.ldH * (int64_t)(j * bw + b)] = v;
+      for (int k = 0; k < bw; ++k) v += Rl[a * bw + k] * R1[k * bw + b];
+      p.H[(int64_t)(nb * bw + a) + p.ldH * (int64_t)(j * bw + b)] = v;
     }
   }
   if (t == 0) atomicExch(p.cnt + 2 * p.nbmax, 0u);
@@ -914,7 +1147,6 @@ void launch_elementwise(ExpmDev* e, int op, int nprob, int64_t maxNN, hipStream_
   hipLaunchKernelGGL(k_elementwise, grid, dim3(256), 0, st, e, op);
 }
 
-typedef double dbl4 __attribute__((ext_vector_type(4)));
 
 // C = A B (+ Taylor epilogue), 32 x 32 tile per workgroup, 4 waves of 16 x 16 MFMA f64.
 //   op 0: A2 = A A      op 1: A3 = A2 A      op 2: A4 = A2 A2
@@ -998,16 +1230,40 @@ void launch_gemm(ExpmDev* e, int op, int k, int nprob, int tiles_max, hipStream_
 
 // y_k = exp(alpha 2^k Ht) b after k squarings (T for even k, P for odd k); rows spread
 // over workgroups.  Problems with fewer squarings than k skip.
-__global__ __launch_bounds__(256) void k_expm_apply(ExpmDev* E, int level) {
+// A workgroup takes 64 rows; its 16 column groups (of 64 lanes each, one row per lane)
+// sum strided columns with eight loads in flight and reduce through LDS.
+constexpr int kApplySplit = 16;
+__global__ __launch_bounds__(1024) void k_expm_apply(ExpmDev* E, int level) {
   const ExpmDev& e = E[blockIdx.y];
   if (!e.active || level > e.nsq) return;
   const int N = e.N;
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= N) return;
+  const int lane = threadIdx.x & 63, cs = threadIdx.x >> 6;
+  const int r0 = blockIdx.x * 64;
+  if (r0 >= N) return;
+  const int r = r0 + lane;
+  __shared__ double red[kApplySplit * 64];
   const double* M = (level & 1) ? e.P : e.T;
   double acc = 0.0;
-  for (int c = 0; c < N; ++c) acc += M[(int64_t)r + (int64_t)N * c] * e.b[c];
-  e.y[(int64_t)level * N + r] = acc;
+  if (r < N)
+    for (int c = cs; c < N; c += 8 * kApplySplit) {
+      double v[8], bb[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const int c2 = c + k * kApplySplit;
+        v[k] = c2 < N ? M[(int64_t)r + (int64_t)N * c2] : 0.0;
+        bb[k] = c2 < N ? e.b[c2] : 0.0;
+      }
+#pragma unroll
+      for (int k = 0; k < 8; ++k) acc += v[k] * bb[k];
+    }
+  red[cs * 64 + lane] = acc;
+  __syncthreads();
+  if (cs == 0 && r < N) {
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < kApplySplit; ++k) s += red[k * 64 + lane];
+    e.y[(int64_t)level * N + r] = s;
+  }
 }
 
 // out[2k] = |H_{l+1,l} y_k[(l-1)bw : l bw]| (residual of the Arnoldi relation at the end
@@ -1037,8 +1293,8 @@ __global__ __launch_bounds__(256) void k_expm_resid(ExpmDev* E, int level) {
 }
 
 void launch_expm_apply(ExpmDev* e, int level, int nprob, int maxN, hipStream_t st) {
-  hipLaunchKernelGGL(k_expm_apply, dim3((unsigned)((maxN + 255) / 256), (unsigned)nprob), dim3(256), 0, st, e,
-                     level);
+  hipLaunchKernelGGL(k_expm_apply, dim3((unsigned)((maxN + 63) / 64), (unsigned)nprob), dim3(64 * kApplySplit), 0,
+                     st, e, level);
   hipLaunchKernelGGL(k_expm_resid, dim3((unsigned)nprob), dim3(256), 0, st, e, level);
 }
 

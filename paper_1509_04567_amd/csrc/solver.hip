@@ -150,7 +150,7 @@ pe_status ensure_pinned(pe_ctx* ctx, size_t bytes) {
 // ---- geometry of the block kernels ------------------------------------------------
 size_t update_smem(const ProbDev& d);
 size_t proj_smem(const ProbDev& d);
-int rows_p_for(int bw) { return bw <= 8 ? 256 : (bw <= 16 ? 128 : 64); }
+int rows_p_for(int bw) { return bw <= 8 ? 128 : (bw <= 16 ? 64 : 32); }
 
 int rows_u_for(int64_t n, int bw) {
   int ru = kRowsU;
@@ -167,6 +167,8 @@ int rows_u_for(int64_t n, int bw) {
 void set_geometry(ProbDev& d, int64_t n, int bw) {
   d.bw = bw;
   d.rows_u = rows_u_for(n, bw);
+  d.rows_u_log2 = 0;
+  while ((1 << d.rows_u_log2) < d.rows_u) ++d.rows_u_log2;
   d.Cu = (int)std::max<int64_t>(1, n / d.rows_u);
   d.rows_p = rows_p_for(bw);
   d.Cp = (int)((n + d.rows_p - 1) / d.rows_p);
@@ -174,22 +176,20 @@ void set_geometry(ProbDev& d, int64_t n, int bw) {
 
 size_t proj_smem(const ProbDev& d) {
   const size_t ld = d.bw + 1;
-  const size_t qsl = (size_t)(d.rows_p / d.rows_u + 3) * d.bw * d.bw;
-  return sizeof(double) * ((size_t)d.rows_p * ld * 2 + (size_t)(d.rows_p + 2) * ld + 256 + qsl) + 64;
-}
-
-int batch_slots(int bw, int rows_u) {
-  int k = 8192 / (bw * bw + 2 * rows_u * bw);
-  return k < 1 ? 1 : (k > 8 ? 8 : k);
+  const size_t qsl = (size_t)(d.rows_p / d.rows_u + 4) * d.bw * d.bw;
+  const size_t qrow = (size_t)(d.rows_p + 2) * d.bw;
+  (void)ld;
+  return sizeof(double) * ((size_t)d.rows_p * d.bw * (1 + pe::kSlotGroup) + (size_t)(d.rows_p + 2) * d.bw + 256 +
+                            qrow + qsl) + 64;
 }
 
 size_t update_smem(const ProbDev& d) {
   const size_t ld = d.bw + 1;
   const size_t rmax = 2 * (size_t)d.rows_u;
-  const size_t xs = std::max(rmax * ld, (size_t)d.Cu * d.bw * ld);
-  const size_t KS = batch_slots(d.bw, d.rows_u);
+  const bool reg = pe::combine_in_registers(d.bw, d.Cu);
+  const size_t xs = (reg || rmax > (size_t)d.Cu * d.bw) ? rmax * ld : (size_t)d.Cu * d.bw * ld;
   const size_t bw2 = (size_t)d.bw * d.bw;
-  return sizeof(double) * (xs + KS * bw2 + KS * rmax * d.bw + bw2 + d.bw + std::max<size_t>(bw2, 128)) + 64;
+  return sizeof(double) * (xs + pe::kSb + bw2 + d.bw + (rmax + 2) * d.bw + std::max<size_t>(bw2, 128)) + 64;
 }
 
 // capacities of the per-problem block workspace for block widths up to bwmax
