@@ -170,6 +170,41 @@ pe_status pe_superpose(pe_ctx* ctx, const double* u0, const double* const* v, in
                        int64_t n, int32_t n_out, int64_t ldv, double* u, int64_t ldu,
                        void* stream);
 
+/* Step S10 (Secs. 2.3-2.4, eqs. 2.10-2.20; Sec. 4): waveform relaxation for the viscous
+ * Burgers equation u_t + u u_x = nu u_xx on the periodic unit interval, central
+ * differences with h = 1/n and the advective form N(u)_i = -u_i (u_{i+1} - u_{i-1})/(2h).
+ * [0, T] is split into P windows; window j has s uniform samples
+ *     t_{j,i} = T j / P + i (T / P) / (s - 1),  i = 0..s-1  (end points included).
+ * Iteration k -> k+1 solves every window with the operator L_j = nu D2 + Jbar_j, where
+ * Jbar_j is the trapezoid average over the window's samples of the Jacobian of N at the
+ * iterate u_k (jacobian = 1, eqs. 2.12-2.14) or zero (jacobian = 0: Picard), and the
+ * source samples g = N(u_k) - Jbar_j u_k (eq. 2.10 with the correction of eq. 2.13),
+ * shifted by L_j u0 (eq. 2.16 read with u_k in place of the hatted term).  The window
+ * subsolutions from zero state are superposed with the homogeneous continuation of the
+ * earlier windows through each later window's own operator (eqs. 2.19-2.20):
+ *     u_{k+1}(t) = u0 + sum_j v_j(t).
+ *   u0       device, n
+ *   u_init   device, n x (P s), ld n, window-major columns; NULL = u0 at every sample
+ *   u_final  device, n x (P s), ld n: the iterate after K iterations (may alias u_init)
+ *   the remaining fields are as in pe_problem and apply to every window solve.
+ * reports: host, P entries (the window solves of the last iteration); increments: host,
+ * K entries (|u_{k+1} - u_k| / |u_{k+1}| over all samples), or NULL. */
+typedef struct {
+  int64_t n;
+  double nu, T;
+  int32_t P, s, K, jacobian;
+  const double* u0;
+  const double* u_init;
+  double* u_final;
+  int32_t krylov_steps;
+  int32_t rank_max;
+  int32_t q_max;
+  double tol, svd_tol, fit_tol;
+  pe_precision prec;
+} pe_wr_problem;
+pe_status pe_wr_burgers(pe_ctx* ctx, const pe_wr_problem* wr, pe_report* reports, double* increments,
+                        void* stream);
+
 /* Kernel timing for roofline measurements.  Enables HIP-event timing, on the stream of
  * each call, of every launch of one kernel family: "block_update" (block Gram-Schmidt
  * update + chunk QR + TSQR combine), "block_proj" (block projections), "stencil"

@@ -34,7 +34,8 @@ FLAG_RANK_CAPPED = 4
 FLAG_FIT_CAPPED = 8
 
 EXPORTED = ["pe_create", "pe_destroy", "pe_last_error", "pe_version", "pe_stencil_apply", "pe_compress",
-            "pe_expaction_batch", "pe_solve_batch", "pe_superpose", "pe_profile_enable", "pe_profile_read"]
+            "pe_expaction_batch", "pe_solve_batch", "pe_superpose", "pe_wr_burgers", "pe_profile_enable",
+            "pe_profile_read"]
 
 
 class PeStencil(ctypes.Structure):
@@ -84,6 +85,28 @@ class PeReport(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class PeWrProblem(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int64),
+        ("nu", ctypes.c_double),
+        ("T", ctypes.c_double),
+        ("P", ctypes.c_int32),
+        ("s", ctypes.c_int32),
+        ("K", ctypes.c_int32),
+        ("jacobian", ctypes.c_int32),
+        ("u0", ctypes.c_void_p),
+        ("u_init", ctypes.c_void_p),
+        ("u_final", ctypes.c_void_p),
+        ("krylov_steps", ctypes.c_int32),
+        ("rank_max", ctypes.c_int32),
+        ("q_max", ctypes.c_int32),
+        ("tol", ctypes.c_double),
+        ("svd_tol", ctypes.c_double),
+        ("fit_tol", ctypes.c_double),
+        ("prec", ctypes.c_int32),
+    ]
+
+
 class PeError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"paraexp status {status}: {msg}")
@@ -120,11 +143,13 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                                        ctypes.POINTER(i32), ctypes.POINTER(i32), i32, ctypes.POINTER(PeReport), vp]
     lib.pe_solve_batch.argtypes = [vp, ctypes.POINTER(PeProblem), i32, ctypes.POINTER(PeReport), vp]
     lib.pe_superpose.argtypes = [vp, vp, ctypes.POINTER(vp), i32, i64, i32, i64, vp, i64, vp]
+    lib.pe_wr_burgers.argtypes = [vp, ctypes.POINTER(PeWrProblem), ctypes.POINTER(PeReport),
+                                  ctypes.POINTER(ctypes.c_double), vp]
     lib.pe_profile_enable.argtypes = [vp, ctypes.c_char_p]
     lib.pe_profile_read.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double),
                                     ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
     for name in ["pe_create", "pe_destroy", "pe_stencil_apply", "pe_compress", "pe_expaction_batch",
-                 "pe_solve_batch", "pe_superpose", "pe_profile_enable", "pe_profile_read"]:
+                 "pe_solve_batch", "pe_superpose", "pe_wr_burgers", "pe_profile_enable", "pe_profile_read"]:
         getattr(lib, name).restype = ctypes.c_int
     _LIB = lib
     return lib
@@ -342,6 +367,28 @@ class Context:
         self._check(self.lib.pe_profile_read(self.h, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(by),
                                              ctypes.byref(fl)))
         return dict(launches=n.value, ms=ms.value, bytes=by.value, flops=fl.value)
+
+    # -- S10
+    def wr_burgers(self, bp, precision: int = PE_FP64, u_init=None):
+        """Waveform relaxation for Burgers (fields of a BurgersProblem-like object).
+
+        Returns (U, reports, increments): U is a torch (P*s, n) tensor of the final
+        iterate at every window sample (window-major), reports the P window solves of
+        the last iteration, increments the K relative iterate changes."""
+        torch = _torch()
+        n, P, s, K = int(bp.n), int(bp.P), int(bp.s), int(bp.K)
+        u0 = _dev(bp.u0, self.device)
+        out = torch.empty((P * s, n), dtype=torch.float64, device=self.device)
+        ui = _dev(u_init, self.device) if u_init is not None else None
+        wp = PeWrProblem(n=n, nu=float(bp.nu), T=float(bp.T), P=P, s=s, K=K, jacobian=int(bool(bp.jacobian)),
+                         u0=u0.data_ptr(), u_init=ui.data_ptr() if ui is not None else None,
+                         u_final=out.data_ptr(), krylov_steps=int(bp.krylov_steps), rank_max=int(bp.rank_max),
+                         q_max=int(bp.q_max), tol=float(bp.tol), svd_tol=float(bp.svd_tol),
+                         fit_tol=float(bp.fit_tol), prec=int(precision))
+        reps = (PeReport * P)()
+        inc = (ctypes.c_double * max(K, 1))()
+        self._check(self.lib.pe_wr_burgers(self.h, ctypes.byref(wp), reps, inc, _stream_ptr()))
+        return out, [r.as_dict() for r in reps], list(inc[:K])
 
     # -- S8
     def superpose(self, u0, vs: Sequence):

@@ -55,6 +55,11 @@ void launch_form_u(const double* Q, int bwc, int64_t n, const int* sel, int r, c
 void launch_fit(const double* A, int s, const int* perm, int m, const double* ts, double t0, double t1, int qcap,
                 double fit_tol, double* Pi, int ldPi, double* work, double* info, hipStream_t st);
 
+// waveform relaxation (Burgers): per-point operator and source samples of one window
+void launch_wr_source(int64_t n, int s, double h, double nu, const double* U, int jacobian, double w_end, double w_in,
+                      double* coef, double* G, hipStream_t st);
+void launch_diff_norms(const double* a, const double* b, int64_t cnt, double* part, int blocks, hipStream_t st);
+
 // utilities
 void launch_superpose(const double* u0, const double* const* v, int P, int64_t n, int n_out, int64_t ldv,
                       double* u, int64_t ldu, hipStream_t st);

@@ -1588,12 +1588,80 @@ __global__ void k_superpose(const double* u0, PtrList vl, int P, int64_t n, int6
 void launch_superpose(const double* u0, const double* const* v, int P, int64_t n, int n_out, int64_t ldv, double* u,
                       int64_t ldu, hipStream_t st) {
   dim3 grid((unsigned)((n + 255) / 256), (unsigned)n_out);
+  if (P == 0) {  // u = u0 in every column
+    PtrList pl;
+    hipLaunchKernelGGL(k_superpose, grid, dim3(256), 0, st, u0, pl, 0, n, ldv, u, ldu, 0);
+    return;
+  }
   for (int j0 = 0; j0 < P; j0 += 64) {
     PtrList pl;
     const int cnt = (P - j0) < 64 ? (P - j0) : 64;
     for (int i = 0; i < cnt; ++i) pl.v[i] = v[j0 + i];
     hipLaunchKernelGGL(k_superpose, grid, dim3(256), 0, st, u0, pl, cnt, n, ldv, u, ldu, j0 > 0 ? 1 : 0);
   }
+}
+
+// ------------------------------------------------------------------------------------
+// S10: waveform-relaxation sources for viscous Burgers on one window.
+// For iterate u_k at the window's s samples (n x s, ld n):
+//   Jbar = sum_i w_i dN/du(u_k(t_i)), stencil rows [u/(2h), -(u_{+}-u_{-})/(2h), -u/(2h)]
+//   coef = nu D2 + Jbar (per-point stencil, rows c_minus, c_zero, c_plus)
+//   G[:, i] = N(u_k(t_i)) - Jbar u_k(t_i),  N(u) = -u (u_{+} - u_{-}) / (2h)
+// with trapezoid weights w (end weight w_end, interior w_in).  Without the Jacobian
+// Jbar = 0 (Picard iteration).  One thread per grid point.
+// ------------------------------------------------------------------------------------
+__global__ void k_wr_source(int64_t n, int s, double h, double nu, const double* __restrict__ U, int jacobian,
+                            double w_end, double w_in, double* __restrict__ coef, double* __restrict__ G) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  const int64_t rm = r == 0 ? n - 1 : r - 1, rp = r == n - 1 ? 0 : r + 1;
+  const double i2h = 1.0 / (2.0 * h);
+  double j0 = 0.0, j1 = 0.0, j2 = 0.0;
+  if (jacobian)
+    for (int i = 0; i < s; ++i) {
+      const double* u = U + (int64_t)i * n;
+      const double w = (i == 0 || i == s - 1) ? w_end : w_in;
+      const double ur = u[r];
+      j0 += w * (ur * i2h);
+      j1 += w * (-(u[rp] - u[rm]) * i2h);
+      j2 += w * (-ur * i2h);
+    }
+  const double d2 = nu / (h * h);
+  coef[r] = d2 + j0;
+  coef[n + r] = -2.0 * d2 + j1;
+  coef[2 * n + r] = d2 + j2;
+  for (int i = 0; i < s; ++i) {
+    const double* u = U + (int64_t)i * n;
+    const double um = u[rm], uz = u[r], up = u[rp];
+    G[(int64_t)i * n + r] = -uz * (up - um) * i2h - (j0 * um + j1 * uz + j2 * up);
+  }
+}
+
+void launch_wr_source(int64_t n, int s, double h, double nu, const double* U, int jacobian, double w_end, double w_in,
+                      double* coef, double* G, hipStream_t st) {
+  hipLaunchKernelGGL(k_wr_source, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, s, h, nu, U, jacobian,
+                     w_end, w_in, coef, G);
+}
+
+// per-block partial sums of |a - b|^2 and |a|^2 over cnt contiguous doubles
+__global__ __launch_bounds__(256) void k_diff_norms(const double* a, const double* b, int64_t cnt, double* part) {
+  __shared__ double red[16];
+  double d2 = 0.0, a2 = 0.0;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < cnt; e += (int64_t)gridDim.x * 256) {
+    const double x = a[e], y = b[e];
+    d2 += (x - y) * (x - y);
+    a2 += x * x;
+  }
+  d2 = block_sum(d2, red);
+  a2 = block_sum(a2, red);
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = d2;
+    part[2 * blockIdx.x + 1] = a2;
+  }
+}
+
+void launch_diff_norms(const double* a, const double* b, int64_t cnt, double* part, int blocks, hipStream_t st) {
+  hipLaunchKernelGGL(k_diff_norms, dim3((unsigned)blocks), dim3(256), 0, st, a, b, cnt, part);
 }
 
 __global__ void k_check_finite(const double* x, int64_t n, int64_t ld, int* flag) {

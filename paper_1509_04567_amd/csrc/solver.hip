@@ -1119,6 +1119,170 @@ pe_status pe_solve_batch(pe_ctx* ctx, const pe_problem* probs, int32_t nprob, pe
   return PE_OK;
 }
 
+// ---- S10: waveform relaxation for Burgers ------------------------------------------
+pe_status pe_wr_burgers(pe_ctx* ctx, const pe_wr_problem* wr, pe_report* reports, double* increments, void* stream) {
+  if (!ctx) return PE_ERR_ARG;
+  if (!wr || !reports) return pe_fail(ctx, PE_ERR_ARG, "pe_wr_burgers: null argument");
+  const pe_wr_problem& w = *wr;
+  if (w.n < 4 || w.P < 1 || w.s < 2 || w.K < 0 || !(w.T > 0.0) || !(w.nu >= 0.0) || !w.u0 || !w.u_final)
+    return pe_fail(ctx, PE_ERR_ARG, "pe_wr_burgers: bad sizes or pointers");
+  if (w.n < w.rank_max + 1) return pe_fail(ctx, PE_ERR_ARG, "n too small for rank_max");
+  HCK(hipSetDevice(ctx->device));
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t n = w.n;
+  const int P = w.P, s = w.s, cols = P * s;
+  const double h = 1.0 / (double)n;
+  // sample times, window-major; the product and the sum are separate statements so the
+  // compiler cannot fuse them (the same two roundings as t0 + i * step elsewhere)
+  std::vector<double> times((size_t)cols), tw(P + 1);
+  for (int j = 0; j <= P; ++j) tw[j] = w.T * (double)j / (double)P;
+  for (int j = 0; j < P; ++j) {
+    const double step = (tw[j + 1] - tw[j]) / (double)(s - 1);
+    for (int i = 0; i < s; ++i) {
+      const double a = (double)i * step;
+      times[(size_t)j * s + i] = a + tw[j];
+    }
+    times[(size_t)j * s] = tw[j];
+    times[(size_t)j * s + s - 1] = tw[j + 1];
+  }
+  // trapezoid weights of uniform samples, normalised by the window length
+  const double w_in = 1.0 / (double)(s - 1), w_end = 0.5 / (double)(s - 1);
+  // device buffers: iterate, window solutions, continuations, sources, operators
+  const size_t blkn = (size_t)n * cols;
+  const int nblk = 256;
+  double* base = nullptr;
+  const size_t tot = sizeof(double) * (4 * blkn + 3 * (size_t)n * P + n + 2 * nblk);
+  if (hipMalloc((void**)&base, tot) != hipSuccess) return pe_fail(ctx, PE_ERR_OOM, "pe_wr_burgers: workspace");
+  double* Uk = base;
+  double* Vown = Uk + blkn;
+  double* Cc = Vown + blkn;
+  double* G = Cc + blkn;
+  double* coef = G + blkn;
+  double* z = coef + 3 * (size_t)n * P;
+  double* part = z + n;
+  std::vector<double> hpart(2 * nblk);
+  pe_status res = PE_OK;
+  auto fail = [&](pe_status e) {
+    res = e;
+    return e;
+  };
+  do {
+    if (w.u_init) {
+      if (hipMemcpyAsync(Uk, w.u_init, sizeof(double) * blkn, hipMemcpyDeviceToDevice, st) != hipSuccess) {
+        fail(pe_fail(ctx, PE_ERR_DEVICE, "pe_wr_burgers: copy u_init"));
+        break;
+      }
+    } else {
+      std::vector<const double*> none;
+      pe::launch_superpose(w.u0, none.data(), 0, n, cols, n, Uk, n, st);
+    }
+    for (int k = 0; k < w.K && res == PE_OK; ++k) {
+      // sources and operators of every window from the current iterate
+      for (int j = 0; j < P; ++j)
+        pe::launch_wr_source(n, s, h, w.nu, Uk + (size_t)j * s * n, w.jacobian, w_end, w_in, coef + 3 * (size_t)n * j,
+                             G + (size_t)j * s * n, st);
+      // the P window subproblems, batched: v_j at the window's own samples
+      std::vector<pe_problem> pr((size_t)P);
+      for (int j = 0; j < P; ++j) {
+        pe_problem& q = pr[j];
+        std::memset(&q, 0, sizeof(q));
+        q.op.n = n;
+        q.op.per_point = 1;
+        q.op.coeffs = coef + 3 * (size_t)n * j;
+        q.u0 = w.u0;
+        q.t0 = tw[j];
+        q.t1 = tw[j + 1];
+        q.t_samples = times.data() + (size_t)j * s;
+        q.s = s;
+        q.G = G + (size_t)j * s * n;
+        q.ldG = n;
+        q.shift = 1;
+        q.t_out = times.data() + (size_t)j * s;
+        q.n_out = s;
+        q.out = Vown + (size_t)j * s * n;
+        q.ldOut = n;
+        q.krylov_steps = w.krylov_steps;
+        q.rank_max = w.rank_max;
+        q.q_max = w.q_max;
+        q.tol = w.tol;
+        q.svd_tol = w.svd_tol;
+        q.fit_tol = w.fit_tol;
+        q.prec = w.prec;
+      }
+      {
+        const pe_status sb = pe_solve_batch(ctx, pr.data(), P, reports, stream);
+        if (sb != PE_OK) {
+          res = sb;
+          break;
+        }
+      }
+      // homogeneous continuation of the earlier windows through window i with L_i:
+      // c_i(T_i) = c_{i-1}(T_i) + v_{i-1}(T_i), then c' = L_i c over window i
+      pe::launch_fill(Cc, n, s, n, 0.0, st);
+      for (int i = 1; i < P && res == PE_OK; ++i) {
+        const double* vlast = Vown + ((size_t)i * s - 1) * n;
+        const double* clast = Cc + ((size_t)i * s - 1) * n;
+        pe::launch_superpose(vlast, &clast, 1, n, 1, n, z, n, st);
+        pe_problem q;
+        std::memset(&q, 0, sizeof(q));
+        q.op.n = n;
+        q.op.per_point = 1;
+        q.op.coeffs = coef + 3 * (size_t)n * i;
+        q.u0 = z;
+        q.t0 = tw[i];
+        q.t1 = tw[i + 1];
+        q.shift = 0;
+        q.t_out = times.data() + (size_t)i * s;
+        q.n_out = s;
+        q.out = Cc + (size_t)i * s * n;
+        q.ldOut = n;
+        q.krylov_steps = w.krylov_steps;
+        q.rank_max = w.rank_max;
+        q.q_max = w.q_max;
+        q.tol = w.tol;
+        q.prec = w.prec;
+        const double* nullp = nullptr;
+        const int32_t zero = 0;
+        pe_report rep;
+        const pe_status se = pe_expaction_batch(ctx, &q, &nullp, &nullp, &zero, &zero, 1, &rep, stream);
+        if (se != PE_OK) {
+          res = se;
+          break;
+        }
+        reports[i].cycles += rep.cycles;
+        reports[i].block_steps += rep.block_steps;
+        reports[i].rejected += rep.rejected;
+        reports[i].flags |= rep.flags;
+      }
+      if (res != PE_OK) break;
+      // u_{k+1} = u0 + v + c at every sample; increment against u_k
+      const double* vv[2] = {Vown, Cc};
+      pe::launch_superpose(w.u0, vv, 2, n, cols, n, G, n, st);
+      pe::launch_diff_norms(G, Uk, (int64_t)blkn, part, nblk, st);
+      if (hipMemcpyAsync(hpart.data(), part, sizeof(double) * 2 * nblk, hipMemcpyDeviceToHost, st) != hipSuccess ||
+          hipMemcpyAsync(Uk, G, sizeof(double) * blkn, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+          hipStreamSynchronize(st) != hipSuccess) {
+        fail(pe_fail(ctx, PE_ERR_DEVICE, "pe_wr_burgers: iterate update"));
+        break;
+      }
+      double d2 = 0.0, a2 = 0.0;
+      for (int b = 0; b < nblk; ++b) {
+        d2 += hpart[2 * b];
+        a2 += hpart[2 * b + 1];
+      }
+      if (increments) increments[k] = a2 > 0.0 ? std::sqrt(d2 / a2) : std::sqrt(d2);
+    }
+    if (res == PE_OK &&
+        hipMemcpyAsync(w.u_final, Uk, sizeof(double) * blkn, hipMemcpyDeviceToDevice, st) != hipSuccess)
+      fail(pe_fail(ctx, PE_ERR_DEVICE, "pe_wr_burgers: copy u_final"));
+  } while (false);
+  hipStreamSynchronize(st);
+  hipFree(base);
+  if (res != PE_OK) return res;
+  HCK(hipGetLastError());
+  return PE_OK;
+}
+
 pe_status pe_profile_enable(pe_ctx* ctx, const char* family) {
   if (!ctx) return PE_ERR_ARG;
   if (family && std::strcmp(family, "block_update") && std::strcmp(family, "block_proj") &&

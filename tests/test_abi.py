@@ -33,7 +33,8 @@ def test_struct_layout_matches_c(tmp_path):
                                            "t_out", "n_out", "out", "ldOut", "krylov_steps", "rank_max", "q_max",
                                            "tol", "svd_tol", "fit_tol", "prec"]),
               "pe_report": (b.PeReport, [f for f, _ in b.PeReport._fields_]),
-              "pe_stencil": (b.PeStencil, ["n", "per_point", "coeffs"])}
+              "pe_stencil": (b.PeStencil, ["n", "per_point", "coeffs"]),
+              "pe_wr_problem": (b.PeWrProblem, [f for f, _ in b.PeWrProblem._fields_])}
     src = ['#include "%s"' % HEADER, "#include <stdio.h>", "#include <stddef.h>", "int main(void){"]
     for cname, (_, names) in fields.items():
         src.append('printf("%%zu\\n", sizeof(%s));' % cname)
