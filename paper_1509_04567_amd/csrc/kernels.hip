@@ -16,6 +16,8 @@
 // produce in the first Krylov steps.
 #include "kernels.h"
 
+#include <type_traits>
+
 #include <cmath>
 
 namespace pe {
@@ -283,7 +285,12 @@ __device__ __forceinline__ void cgs2_team(const double* Xi, int ldi, double* X, 
   for (int q = 0; q < RPL; ++q) {
     const int r = t + T * q;
 #pragma unroll
-    for (int a = 0; a < BWM; ++a) xr[q][a] = (a < bw && r < rows) ? Xi[r * ldi + a] : 0.0;
+    for (int a = 0; a < BWM; ++a) {
+      // unconditional load from a clamped address, then select: a guarded load would
+      // be compiled to a branch that waits for it, serialising the loads
+      const double v = Xi[(r < rows ? r : rows - 1) * ldi + (a < bw ? a : bw - 1)];
+      xr[q][a] = (a < bw && r < rows) ? v : 0.0;
+    }
   }
   // sum over the team of NA values (NA known at compile time); result in sd[]
   auto team_sums = [&](double* sd, int NA) {
@@ -310,8 +317,13 @@ __device__ __forceinline__ void cgs2_team(const double* Xi, int ldi, double* X, 
   for (int b = 0; b < BWM; ++b) {
     if (b < bw) {
       const double n0 = ref[b];
+      // The second pass reduces the squared column norm together with its projections;
+      // the norm after it follows by Pythagoras (the second-pass coefficients are at
+      // rounding level), so a column costs two team reductions.
+      double nsq = 0.0, s2sum = 0.0;
 #pragma unroll
       for (int pass = 0; pass < 2; ++pass) {
+        if (pass == 0 && b == 0) continue;
         double sd[BWM];
 #pragma unroll
         for (int a = 0; a < BWM; ++a) sd[a] = 0.0;
@@ -319,7 +331,11 @@ __device__ __forceinline__ void cgs2_team(const double* Xi, int ldi, double* X, 
         for (int q = 0; q < RPL; ++q)
 #pragma unroll
           for (int a = 0; a < b; ++a) sd[a] += xr[q][a] * xr[q][b];
-        team_sums(sd, b);
+        if (pass == 1) {
+#pragma unroll
+          for (int q = 0; q < RPL; ++q) sd[b] += xr[q][b] * xr[q][b];
+        }
+        team_sums(sd, pass == 1 ? b + 1 : b);
 #pragma unroll
         for (int q = 0; q < RPL; ++q)
 #pragma unroll
@@ -327,13 +343,13 @@ __device__ __forceinline__ void cgs2_team(const double* Xi, int ldi, double* X, 
         if (t == 0)
 #pragma unroll
           for (int a = 0; a < b; ++a) R[a * bw + b] += sd[a];
-      }
-      double nn[BWM];
-      nn[0] = 0.0;
+        if (pass == 1) {
+          nsq = sd[b];
 #pragma unroll
-      for (int q = 0; q < RPL; ++q) nn[0] += xr[q][b] * xr[q][b];
-      team_sums(nn, 1);
-      const double nr = sqrt(nn[0]);
+          for (int a = 0; a < b; ++a) s2sum += sd[a] * sd[a];
+        }
+      }
+      const double nr = sqrt(nsq > s2sum ? nsq - s2sum : 0.0);
       if (nr > PE_DEP_TOL * n0 && nr > 1e-300) {
         const double inv = 1.0 / nr;
 #pragma unroll
@@ -469,7 +485,8 @@ __device__ __forceinline__ void bulk_load(int64_t cnt, Src src, Put put) {
 #pragma unroll
     for (int k = 0; k < kBulkDepth; ++k) {
       const int64_t e = e0 + (int64_t)k * T;
-      v[k] = e < cnt ? src(e) : 0.0;
+      const double x = src(e < cnt ? e : cnt - 1);  // clamped, unconditional (see cgs2_team)
+      v[k] = e < cnt ? x : 0.0;
     }
 #pragma unroll
     for (int k = 0; k < kBulkDepth; ++k) {
@@ -481,57 +498,47 @@ __device__ __forceinline__ void bulk_load(int64_t cnt, Src src, Put put) {
 
 __device__ __forceinline__ int64_t wrap_row(int64_t g, int64_t n) { return g < 0 ? g + n : (g >= n ? g - n : g); }
 
-// Flat multi-segment copy global -> LDS: segment s moves cnt contiguous elements from
-// d (double) or f (float, when non-null) to dst.  Segment lookup is unrolled over NS so
-// no division or dynamic indexing is involved; kBulkDepth loads stay in flight.
+// Flat multi-segment copy global -> LDS: segment q moves cnt contiguous elements of
+// type T from src to dst (as double).  The segment lookup is unrolled over NS and the
+// loads are unconditional (clamped to the last element), so no division, dynamic
+// indexing or load-guarding branch is involved and kBulkDepth loads stay in flight.
+template <typename T>
 struct CopySeg {
-  const double* d;
-  const float* f;
+  const T* src;
   int64_t cnt;
   double* dst;
 };
-template <int NS>
-__device__ __forceinline__ void bulk_copy(const CopySeg (&sg)[NS]) {
-  const int T = blockDim.x;
+template <typename T, int NS>
+__device__ __forceinline__ void bulk_copy(const CopySeg<T> (&sg)[NS]) {
+  const int TH = blockDim.x;
   int64_t total = 0;
 #pragma unroll
   for (int q = 0; q < NS; ++q) total += sg[q].cnt;
-  for (int64_t e0 = threadIdx.x; e0 < total; e0 += kBulkDepth * (int64_t)T) {
+  if (total == 0) return;
+  for (int64_t e0 = threadIdx.x; e0 < total; e0 += kBulkDepth * (int64_t)TH) {
     double v[kBulkDepth];
     double* dp[kBulkDepth];
 #pragma unroll
     for (int k = 0; k < kBulkDepth; ++k) {
-      int64_t off = e0 + (int64_t)k * T;
-      const double* sd = nullptr;
-      const float* sf = nullptr;
-      double* dd = nullptr;
+      const int64_t e = e0 + (int64_t)k * TH;
+      int64_t off = e < total ? e : total - 1;
+      const T* sp = sg[0].src;
+      double* dd = sg[0].dst;
 #pragma unroll
       for (int q = 0; q < NS; ++q) {
         if (off >= 0 && off < sg[q].cnt) {
-          sd = sg[q].d + off;
-          sf = sg[q].f ? sg[q].f + off : nullptr;
+          sp = sg[q].src + off;
           dd = sg[q].dst + off;
         }
         off -= sg[q].cnt;
       }
-      dp[k] = dd;
-      v[k] = dd ? (sf ? (double)*sf : *sd) : 0.0;
+      v[k] = (double)*sp;
+      dp[k] = e < total ? dd : nullptr;
     }
 #pragma unroll
     for (int k = 0; k < kBulkDepth; ++k)
       if (dp[k]) *dp[k] = v[k];
   }
-}
-
-template <typename TS>
-__device__ __forceinline__ CopySeg basis_seg(const TS* src, int64_t cnt, double* dst);
-template <>
-__device__ __forceinline__ CopySeg basis_seg<double>(const double* src, int64_t cnt, double* dst) {
-  return CopySeg{src, nullptr, cnt, dst};
-}
-template <>
-__device__ __forceinline__ CopySeg basis_seg<float>(const float* src, int64_t cnt, double* dst) {
-  return CopySeg{nullptr, src, cnt, dst};
 }
 
 // Input block X (rows x bw, leading dimension ld, LDS) of the update kernel's chunk
@@ -554,7 +561,8 @@ __device__ __forceinline__ void form_block(const ProbDev& p, int mode, int pass,
         [&](int64_t e) -> double {
           const int c = (int)(e / rows);
           const int64_t g = r0 + e % rows;
-          return c < p.m ? p.U[(int64_t)c * n + g] : p.x[g];
+          const double* ptr = c < p.m ? p.U + (int64_t)c * n + g : p.x + g;
+          return *ptr;
         },
         [&](int64_t e, double v) { X[(e % rows) * ld + e / rows] = v; });
   } else if (pass == 0 && mode == MODE_GIVEN) {
@@ -562,15 +570,16 @@ __device__ __forceinline__ void form_block(const ProbDev& p, int mode, int pass,
         (int64_t)rows * bw,
         [&](int64_t e) -> double {
           const int gc = j * bw + (int)(e / rows);
-          return gc < p.m ? p.Xg[(int64_t)gc * p.ldXg + r0 + e % rows] : 0.0;
+          const double v = p.Xg[(int64_t)(gc < p.m ? gc : p.m - 1) * p.ldXg + r0 + e % rows];
+          return gc < p.m ? v : 0.0;
         },
         [&](int64_t e, double v) { X[(e % rows) * ld + e / rows] = v; });
   } else if (pass == 0) {  // MODE_ARNOLDI: W = L V_j, V_j read from the basis
     const TS* vj = V + (int64_t)j * blk;
     const int64_t gm = wrap_row(r0 - 1, n), gp = wrap_row(r0 + rows, n);
-    const CopySeg sg[3] = {basis_seg<TS>(vj + gm * bw, bw, Qrow),
-                           basis_seg<TS>(vj + r0 * bw, (int64_t)rows * bw, Qrow + bw),
-                           basis_seg<TS>(vj + gp * bw, bw, Qrow + (int64_t)(rows + 1) * bw)};
+    const CopySeg<TS> sg[3] = {{vj + gm * bw, bw, Qrow},
+                               {vj + r0 * bw, (int64_t)rows * bw, Qrow + bw},
+                               {vj + gp * bw, bw, Qrow + (int64_t)(rows + 1) * bw}};
     bulk_copy(sg);
     __syncthreads();
     if (act)
@@ -580,8 +589,8 @@ __device__ __forceinline__ void form_block(const ProbDev& p, int mode, int pass,
         X[rr * ld + col] = cm * Qrow[rr * bw + col] + cz * Qrow[(rr + 1) * bw + col] + cp * Qrow[(rr + 2) * bw + col];
       }
   } else {  // pass 1: X = Q1 = Qloc1 Qs1 on this chunk
-    const CopySeg sg[2] = {{p.Qloc1 + r0 * bw, nullptr, (int64_t)rows * bw, Qrow},
-                           {p.Qs1 + (int64_t)chunk_of(p, r0) * bw2, nullptr, bw2, Qsl}};
+    const CopySeg<double> sg[2] = {{p.Qloc1 + r0 * bw, (int64_t)rows * bw, Qrow},
+                                   {p.Qs1 + (int64_t)chunk_of(p, r0) * bw2, bw2, Qsl}};
     bulk_copy(sg);
     __syncthreads();
     if (act)
@@ -618,8 +627,8 @@ __device__ __forceinline__ bool arrive_last(unsigned* counter, unsigned expected
 // W = L V_j); each thread then owns one output of one slot over all rows of the chunk.
 // The last workgroup of a slot group reduces the Cp chunk partials into S.
 template <typename TS>
-__global__ __launch_bounds__(256) void k_block_proj(ProbDev* probs, int j, int nb, int pass, int mode) {
-  const ProbDev& p = probs[blockIdx.y];
+__global__ __launch_bounds__(256) void k_block_proj(const ProbDev* __restrict__ probs, int j, int nb, int pass, int mode) {
+  const ProbDev p = probs[blockIdx.y];  // by value: uniform, loaded once
   if (!p.active || j >= p.l) return;
   const int bw = p.bw, nout = bw * bw, bw2 = nout;
   const int grp = blockIdx.x / p.Cp;
@@ -652,35 +661,49 @@ __global__ __launch_bounds__(256) void k_block_proj(ProbDev* probs, int j, int n
   const int u_lo = chunk_of(p, r0), u_hi = chunk_of(p, r0 + rows - 1);
   const int nm = u_hi - u_lo + 1;
   {
-    CopySeg sg[6 + kSlotGroup];
+    CopySeg<double> sg[6];
+    CopySeg<TS> sv[kSlotGroup];
 #pragma unroll
-    for (int q = 0; q < 6 + kSlotGroup; ++q) sg[q] = CopySeg{nullptr, nullptr, 0, Qrow};
+    for (int q = 0; q < 6; ++q) sg[q] = CopySeg<double>{nullptr, 0, Qrow};
+#pragma unroll
+    for (int q = 0; q < kSlotGroup; ++q) sv[q] = CopySeg<TS>{nullptr, 0, Qrow};
     if (arn0) {
       const int64_t gm = wrap_row(r0 - 1, n), gp = wrap_row(r0 + rows, n);
-      sg[0] = CopySeg{p.Qloc2 + gm * bw, nullptr, bw, Qrow};
-      sg[1] = CopySeg{p.Qloc2 + r0 * bw, nullptr, (int64_t)rows * bw, Qrow + bw};
-      sg[2] = CopySeg{p.Qloc2 + gp * bw, nullptr, bw, Qrow + (int64_t)(rows + 1) * bw};
-      sg[3] = CopySeg{p.Qs2 + (int64_t)u_lo * bw2, nullptr, (int64_t)nm * bw2, Qsl};
-      sg[4] = CopySeg{p.Qs2 + (int64_t)chunk_of(p, gm) * bw2, nullptr, bw2, Qsl + (int64_t)nm * bw2};
-      sg[5] = CopySeg{p.Qs2 + (int64_t)chunk_of(p, gp) * bw2, nullptr, bw2, Qsl + (int64_t)(nm + 1) * bw2};
+      sg[0] = CopySeg<double>{p.Qloc2 + gm * bw, bw, Qrow};
+      sg[1] = CopySeg<double>{p.Qloc2 + r0 * bw, (int64_t)rows * bw, Qrow + bw};
+      sg[2] = CopySeg<double>{p.Qloc2 + gp * bw, bw, Qrow + (int64_t)(rows + 1) * bw};
+      sg[3] = CopySeg<double>{p.Qs2 + (int64_t)u_lo * bw2, (int64_t)nm * bw2, Qsl};
+      sg[4] = CopySeg<double>{p.Qs2 + (int64_t)chunk_of(p, gm) * bw2, bw2, Qsl + (int64_t)nm * bw2};
+      sg[5] = CopySeg<double>{p.Qs2 + (int64_t)chunk_of(p, gp) * bw2, bw2, Qsl + (int64_t)(nm + 1) * bw2};
     } else if (!given0) {
-      sg[1] = CopySeg{p.Qloc1 + r0 * bw, nullptr, (int64_t)rows * bw, Qrow};
-      sg[3] = CopySeg{p.Qs1 + (int64_t)u_lo * bw2, nullptr, (int64_t)nm * bw2, Qsl};
+      sg[1] = CopySeg<double>{p.Qloc1 + r0 * bw, (int64_t)rows * bw, Qrow};
+      sg[3] = CopySeg<double>{p.Qs1 + (int64_t)u_lo * bw2, (int64_t)nm * bw2, Qsl};
     }
 #pragma unroll
     for (int kk = 0; kk < kSlotGroup; ++kk) {
       const int i = i_lo + kk;
       if (i < i_hi && !(arn0 && i == j))
-        sg[6 + kk] = basis_seg<TS>(V + (int64_t)i * blk + r0 * bw, (int64_t)rows * bw, Vs + (int64_t)kk * p.rows_p * bw);
+        sv[kk] = CopySeg<TS>{V + (int64_t)i * blk + r0 * bw, (int64_t)rows * bw, Vs + (int64_t)kk * p.rows_p * bw};
     }
-    bulk_copy(sg);
+    if constexpr (std::is_same<TS, double>::value) {
+      CopySeg<double> all[6 + kSlotGroup];
+#pragma unroll
+      for (int q = 0; q < 6; ++q) all[q] = sg[q];
+#pragma unroll
+      for (int q = 0; q < kSlotGroup; ++q) all[6 + q] = sv[q];
+      bulk_copy(all);
+    } else {
+      bulk_copy(sg);
+      bulk_copy(sv);
+    }
   }
   if (given0)
     bulk_load(
         (int64_t)rows * bw,
         [&](int64_t e) -> double {
           const int gc = j * bw + (int)(e / rows);
-          return gc < p.m ? p.Xg[(int64_t)gc * p.ldXg + r0 + e % rows] : 0.0;
+          const double v = p.Xg[(int64_t)(gc < p.m ? gc : p.m - 1) * p.ldXg + r0 + e % rows];
+          return gc < p.m ? v : 0.0;
         },
         [&](int64_t e, double v) { Xs[(e % rows) * bw + e / rows] = v; });
   __syncthreads();
@@ -752,7 +775,8 @@ __global__ __launch_bounds__(256) void k_block_proj(ProbDev* probs, int j, int n
 #pragma unroll
         for (int k = 0; k < 32; ++k) {
           const int c2 = cc + k * G;
-          v[k] = c2 < p.Cp ? ps[(int64_t)c2 * nout] : 0.0;
+          const double x = ps[(int64_t)(c2 < p.Cp ? c2 : p.Cp - 1) * nout];
+          v[k] = c2 < p.Cp ? x : 0.0;
         }
 #pragma unroll
         for (int k = 0; k < 32; ++k) acc += v[k];
@@ -809,11 +833,14 @@ __device__ __forceinline__ void subtract_proj_mfma(const TS* V, int64_t blk, con
         double a[PF][KT];
 #pragma unroll
         for (int f = 0; f < PF; ++f) {
-          const TS* vr = V + (int64_t)(i0 + kk0 + f) * blk + (r0 + row) * bw;
+          // clamped addresses and unconditional loads keep all PF * KT loads in flight
+          const bool fok = kk0 + f < k;
+          const TS* vr = V + (int64_t)(i0 + (fok ? kk0 + f : k - 1)) * blk + (r0 + (rok ? row : rows - 1)) * bw;
 #pragma unroll
           for (int kt = 0; kt < KT; ++kt) {
             const int ka = kt * 4 + lk;
-            a[f][kt] = (kk0 + f < k && rok && ka < bw) ? -(double)vr[ka] : 0.0;
+            const double x = (double)vr[ka < bw ? ka : bw - 1];
+            a[f][kt] = (fok && rok && ka < bw) ? -x : 0.0;
           }
         }
 #pragma unroll
@@ -845,8 +872,8 @@ __device__ __forceinline__ void subtract_proj_mfma(const TS* V, int64_t blk, con
 }
 
 template <typename TS>
-__global__ __launch_bounds__(256) void k_block_update(ProbDev* probs, int j, int nb, int pass, int mode) {
-  const ProbDev& p = probs[blockIdx.y];
+__global__ __launch_bounds__(256) void k_block_update(const ProbDev* __restrict__ probs, int j, int nb, int pass, int mode) {
+  const ProbDev p = probs[blockIdx.y];  // by value: uniform, loaded once
   if (!p.active || (mode != MODE_INIT && j >= p.l)) return;
   const int bw = p.bw, nout = bw * bw;
   const int u = blockIdx.x;
@@ -954,7 +981,8 @@ __global__ __launch_bounds__(256) void k_block_update(ProbDev* probs, int j, int
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
           const int u2 = uu + q * per;
-          v[q] = u2 < p.Cu ? p.Cn[(int64_t)u2 * bw + b] : 0.0;
+          const double x = p.Cn[(int64_t)(u2 < p.Cu ? u2 : p.Cu - 1) * bw + b];
+          v[q] = u2 < p.Cu ? x : 0.0;
         }
 #pragma unroll
         for (int q = 0; q < 8; ++q) acc += v[q];
@@ -999,8 +1027,8 @@ __global__ __launch_bounds__(256) void k_block_update(ProbDev* probs, int j, int
 
 // V_j = Qloc2 . Qs2 committed to basis block j
 template <typename TS>
-__global__ void k_block_commit(ProbDev* probs, int j) {
-  const ProbDev& p = probs[blockIdx.y];
+__global__ void k_block_commit(const ProbDev* __restrict__ probs, int j) {
+  const ProbDev p = probs[blockIdx.y];  // by value: uniform, loaded once
   if (!p.active) return;
   const int bw = p.bw;
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1067,8 +1095,8 @@ void launch_block_commit(ProbDev* d, int nprob, int grid_x, int j, int mixed, hi
 // Taylor polynomial of degree 16 (Paterson-Stockmeyer with A^2, A^3, A^4) on
 // A = (delta / 2^s) Ht, then s squarings; y = exp(delta Ht) b.
 // ------------------------------------------------------------------------------------
-__global__ void k_build_aug(ExpmDev* E) {
-  const ExpmDev& e = E[blockIdx.y];
+__global__ void k_build_aug(const ExpmDev* __restrict__ E) {
+  const ExpmDev e = E[blockIdx.y];  // by value: uniform, loaded once
   if (!e.active) return;
   const int N = e.N;
   const int64_t NN = (int64_t)N * N;
@@ -1104,8 +1132,8 @@ void launch_build_aug(ExpmDev* e, int nprob, int64_t maxNN, hipStream_t st) {
 // out[p] = ||Ht||_1 (largest absolute column sum); one wave per column, grid over column
 // groups; non-negative doubles order like their bit patterns, so the maximum is an
 // integer atomic max (out[] zeroed by the host)
-__global__ __launch_bounds__(256) void k_norm1(ExpmDev* E, double* out) {
-  const ExpmDev& e = E[blockIdx.y];
+__global__ __launch_bounds__(256) void k_norm1(const ExpmDev* __restrict__ E, double* out) {
+  const ExpmDev e = E[blockIdx.y];  // by value: uniform, loaded once
   if (!e.active) return;
   const int N = e.N;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -1127,8 +1155,8 @@ __device__ __constant__ double c_taylor[17] = {
     1.0 / 1307674368000.0, 1.0 / 20922789888000.0};
 
 // A = alpha Ht (op 0) or P = c16 A4 + c15 A3 + c14 A2 + c13 A + c12 I (op 1)
-__global__ void k_elementwise(ExpmDev* E, int op) {
-  const ExpmDev& e = E[blockIdx.y];
+__global__ void k_elementwise(const ExpmDev* __restrict__ E, int op) {
+  const ExpmDev e = E[blockIdx.y];  // by value: uniform, loaded once
   if (!e.active) return;
   const int N = e.N;
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1154,8 +1182,8 @@ void launch_elementwise(ExpmDev* e, int op, int nprob, int64_t maxNN, hipStream_
 //   op 4: P = T A4 + c7 A3 + c6 A2 + c5 A + c4 I
 //   op 5: T = P A4 + c3 A3 + c2 A2 + c1 A + c0 I
 //   op 6: squaring number k: (k even) P = T T, (k odd) T = P P; skipped when k >= nsq
-__global__ __launch_bounds__(256) void k_gemm(ExpmDev* E, int op, int k) {
-  const ExpmDev& e = E[blockIdx.y];
+__global__ __launch_bounds__(256) void k_gemm(const ExpmDev* __restrict__ E, int op, int k) {
+  const ExpmDev e = E[blockIdx.y];  // by value: uniform, loaded once
   if (!e.active) return;
   if (op == 6 && k >= e.nsq) return;
   const int N = e.N;
@@ -1184,21 +1212,37 @@ __global__ __launch_bounds__(256) void k_gemm(ExpmDev* E, int op, int k) {
   const int lane = t & 63, w = t >> 6;
   const int wi = w & 1, wj = w >> 1;
   dbl4 acc = {0.0, 0.0, 0.0, 0.0};
-  for (int kk = 0; kk < N; kk += 16) {
+  // the next K-tile is loaded into registers (clamped addresses, unconditional loads)
+  // while the current one is multiplied from LDS
+  double ra[2], rb[2];
+  auto load_tile = [&](int kk) {
+#pragma unroll
     for (int h = 0; h < 2; ++h) {
       const int q = t + 256 * h;
       {
-        const int kq = q / 32, iq = q % 32;
+        const int kq = q >> 5, iq = q & 31;
         const int gi = i0 + iq, gk = kk + kq;
-        As[kq][iq] = (gi < N && gk < N) ? A[(int64_t)gi + (int64_t)N * gk] : 0.0;
+        const double v = A[(int64_t)(gi < N ? gi : N - 1) + (int64_t)N * (gk < N ? gk : N - 1)];
+        ra[h] = (gi < N && gk < N) ? v : 0.0;
       }
       {
-        const int jq = q / 16, kq = q % 16;
+        const int jq = q >> 4, kq = q & 15;
         const int gj = j0 + jq, gk = kk + kq;
-        Bs[jq][kq] = (gj < N && gk < N) ? B[(int64_t)gk + (int64_t)N * gj] : 0.0;
+        const double v = B[(int64_t)(gk < N ? gk : N - 1) + (int64_t)N * (gj < N ? gj : N - 1)];
+        rb[h] = (gj < N && gk < N) ? v : 0.0;
       }
     }
+  };
+  load_tile(0);
+  for (int kk = 0; kk < N; kk += 16) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int q = t + 256 * h;
+      As[q >> 5][q & 31] = ra[h];
+      Bs[q >> 4][q & 15] = rb[h];
+    }
     __syncthreads();
+    if (kk + 16 < N) load_tile(kk + 16);
 #pragma unroll
     for (int k4 = 0; k4 < 16; k4 += 4) {
       const double a = As[k4 + (lane >> 4)][wi * 16 + (lane & 15)];
@@ -1233,8 +1277,8 @@ void launch_gemm(ExpmDev* e, int op, int k, int nprob, int tiles_max, hipStream_
 // A workgroup takes 64 rows; its 16 column groups (of 64 lanes each, one row per lane)
 // sum strided columns with eight loads in flight and reduce through LDS.
 constexpr int kApplySplit = 16;
-__global__ __launch_bounds__(1024) void k_expm_apply(ExpmDev* E, int level) {
-  const ExpmDev& e = E[blockIdx.y];
+__global__ __launch_bounds__(1024) void k_expm_apply(const ExpmDev* __restrict__ E, int level) {
+  const ExpmDev e = E[blockIdx.y];  // by value: uniform, loaded once
   if (!e.active || level > e.nsq) return;
   const int N = e.N;
   const int lane = threadIdx.x & 63, cs = threadIdx.x >> 6;
@@ -1250,8 +1294,10 @@ __global__ __launch_bounds__(1024) void k_expm_apply(ExpmDev* E, int level) {
 #pragma unroll
       for (int k = 0; k < 8; ++k) {
         const int c2 = c + k * kApplySplit;
-        v[k] = c2 < N ? M[(int64_t)r + (int64_t)N * c2] : 0.0;
-        bb[k] = c2 < N ? e.b[c2] : 0.0;
+        const int cc = c2 < N ? c2 : N - 1;
+        const double mv = M[(int64_t)r + (int64_t)N * cc], bv = e.b[cc];
+        v[k] = c2 < N ? mv : 0.0;
+        bb[k] = c2 < N ? bv : 0.0;
       }
 #pragma unroll
       for (int k = 0; k < 8; ++k) acc += v[k] * bb[k];
@@ -1268,8 +1314,8 @@ __global__ __launch_bounds__(1024) void k_expm_apply(ExpmDev* E, int level) {
 
 // out[2k] = |H_{l+1,l} y_k[(l-1)bw : l bw]| (residual of the Arnoldi relation at the end
 // of the step of level k), out[2k+1] = |y_k[0 : l bw]|
-__global__ __launch_bounds__(256) void k_expm_resid(ExpmDev* E, int level) {
-  const ExpmDev& e = E[blockIdx.x];
+__global__ __launch_bounds__(256) void k_expm_resid(const ExpmDev* __restrict__ E, int level) {
+  const ExpmDev e = E[blockIdx.x];  // by value: uniform, loaded once
   if (!e.active || level > e.nsq) return;
   __shared__ double red[16];
   const double* y = e.y + (int64_t)level * e.N;
@@ -1302,8 +1348,8 @@ void launch_expm_apply(ExpmDev* e, int level, int nprob, int maxN, hipStream_t s
 // S7: x = V_{0..l-1} y[0:l*bw]  (and the output column)
 // ------------------------------------------------------------------------------------
 template <typename TS>
-__global__ __launch_bounds__(256) void k_project(ProbDev* probs, ExpmDev* E) {
-  const ProbDev& p = probs[blockIdx.y];
+__global__ __launch_bounds__(256) void k_project(const ProbDev* __restrict__ probs, const ExpmDev* __restrict__ E) {
+  const ProbDev p = probs[blockIdx.y];  // by value: uniform, loaded once
   if (!p.active || !p.proj) return;
   (void)E;
   extern __shared__ double ys[];
