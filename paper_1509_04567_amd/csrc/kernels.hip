@@ -16,8 +16,6 @@
 // produce in the first Krylov steps.
 #include "kernels.h"
 
-#include <type_traits>
-
 #include <cmath>
 
 namespace pe {
@@ -498,49 +496,6 @@ __device__ __forceinline__ void bulk_load(int64_t cnt, Src src, Put put) {
 
 __device__ __forceinline__ int64_t wrap_row(int64_t g, int64_t n) { return g < 0 ? g + n : (g >= n ? g - n : g); }
 
-// Flat multi-segment copy global -> LDS: segment q moves cnt contiguous elements of
-// type T from src to dst (as double).  The segment lookup is unrolled over NS and the
-// loads are unconditional (clamped to the last element), so no division, dynamic
-// indexing or load-guarding branch is involved and kBulkDepth loads stay in flight.
-template <typename T>
-struct CopySeg {
-  const T* src;
-  int64_t cnt;
-  double* dst;
-};
-template <typename T, int NS>
-__device__ __forceinline__ void bulk_copy(const CopySeg<T> (&sg)[NS]) {
-  const int TH = blockDim.x;
-  int64_t total = 0;
-#pragma unroll
-  for (int q = 0; q < NS; ++q) total += sg[q].cnt;
-  if (total == 0) return;
-  for (int64_t e0 = threadIdx.x; e0 < total; e0 += kBulkDepth * (int64_t)TH) {
-    double v[kBulkDepth];
-    double* dp[kBulkDepth];
-#pragma unroll
-    for (int k = 0; k < kBulkDepth; ++k) {
-      const int64_t e = e0 + (int64_t)k * TH;
-      int64_t off = e < total ? e : total - 1;
-      const T* sp = sg[0].src;
-      double* dd = sg[0].dst;
-#pragma unroll
-      for (int q = 0; q < NS; ++q) {
-        if (off >= 0 && off < sg[q].cnt) {
-          sp = sg[q].src + off;
-          dd = sg[q].dst + off;
-        }
-        off -= sg[q].cnt;
-      }
-      v[k] = (double)*sp;
-      dp[k] = e < total ? dd : nullptr;
-    }
-#pragma unroll
-    for (int k = 0; k < kBulkDepth; ++k)
-      if (dp[k]) *dp[k] = v[k];
-  }
-}
-
 // Input block X (rows x bw, leading dimension ld, LDS) of the update kernel's chunk
 // [r0, r0 + rows) (one TSQR chunk).  Qrow: LDS staging of (rows + 2) x bw doubles, Qsl
 // of one bw x bw combine block.  Row/column walks are per thread (col = t % bw fixed) so
@@ -577,10 +532,13 @@ __device__ __forceinline__ void form_block(const ProbDev& p, int mode, int pass,
   } else if (pass == 0) {  // MODE_ARNOLDI: W = L V_j, V_j read from the basis
     const TS* vj = V + (int64_t)j * blk;
     const int64_t gm = wrap_row(r0 - 1, n), gp = wrap_row(r0 + rows, n);
-    const CopySeg<TS> sg[3] = {{vj + gm * bw, bw, Qrow},
-                               {vj + r0 * bw, (int64_t)rows * bw, Qrow + bw},
-                               {vj + gp * bw, bw, Qrow + (int64_t)(rows + 1) * bw}};
-    bulk_copy(sg);
+    const int64_t top = (int64_t)(rows + 1) * bw;
+    bulk_load(
+        top + bw,
+        [&](int64_t e) -> double {  // rows r0-1 .. r0+rows, the halo rows wrapped
+          return (double)vj[e < bw ? gm * bw + e : (e >= top ? gp * bw + (e - top) : (r0 - 1) * bw + e)];
+        },
+        [&](int64_t e, double v) { Qrow[e] = v; });
     __syncthreads();
     if (act)
       for (int rr = rr0; rr < rows; rr += rstep) {
@@ -589,9 +547,18 @@ __device__ __forceinline__ void form_block(const ProbDev& p, int mode, int pass,
         X[rr * ld + col] = cm * Qrow[rr * bw + col] + cz * Qrow[(rr + 1) * bw + col] + cp * Qrow[(rr + 2) * bw + col];
       }
   } else {  // pass 1: X = Q1 = Qloc1 Qs1 on this chunk
-    const CopySeg<double> sg[2] = {{p.Qloc1 + r0 * bw, (int64_t)rows * bw, Qrow},
-                                   {p.Qs1 + (int64_t)chunk_of(p, r0) * bw2, bw2, Qsl}};
-    bulk_copy(sg);
+    const int64_t nr = (int64_t)rows * bw;
+    const double* qs = p.Qs1 + (int64_t)chunk_of(p, r0) * bw2 - nr;
+    bulk_load(
+        nr + bw2,
+        [&](int64_t e) -> double {
+          const double* ptr = e < nr ? p.Qloc1 + r0 * bw + e : qs + e;  // select, then one load
+          return *ptr;
+        },
+        [&](int64_t e, double v) {
+          if (e < nr) Qrow[e] = v;
+          else Qsl[e - nr] = v;
+        });
     __syncthreads();
     if (act)
       for (int rr = rr0; rr < rows; rr += rstep) {
@@ -657,44 +624,71 @@ __global__ __launch_bounds__(256) void k_block_proj(const ProbDev* __restrict__ 
   const int col = t % bw, rstep = 256 / bw, rr0 = t / bw;
   const bool act = rr0 < rstep;
 
-  // ---- one bulk phase: input-block factors, then the slot rows
+  // ---- one bulk phase: every global load of the chunk is issued before any is
+  // consumed, with plain per-thread strides (rows_p * bw <= 1024, checked on the host)
   const int u_lo = chunk_of(p, r0), u_hi = chunk_of(p, r0 + rows - 1);
   const int nm = u_hi - u_lo + 1;
   {
-    CopySeg<double> sg[6];
-    CopySeg<TS> sv[kSlotGroup];
+    const int per_slot = rows * bw;
+    double vv[kSlotGroup][4];
 #pragma unroll
-    for (int q = 0; q < 6; ++q) sg[q] = CopySeg<double>{nullptr, 0, Qrow};
+    for (int kk = 0; kk < kSlotGroup; ++kk) {
+      const int i = i_lo + kk < nb ? i_lo + kk : nb - 1;
+      const TS* base = V + (int64_t)i * blk + r0 * bw;
 #pragma unroll
-    for (int q = 0; q < kSlotGroup; ++q) sv[q] = CopySeg<TS>{nullptr, 0, Qrow};
-    if (arn0) {
-      const int64_t gm = wrap_row(r0 - 1, n), gp = wrap_row(r0 + rows, n);
-      sg[0] = CopySeg<double>{p.Qloc2 + gm * bw, bw, Qrow};
-      sg[1] = CopySeg<double>{p.Qloc2 + r0 * bw, (int64_t)rows * bw, Qrow + bw};
-      sg[2] = CopySeg<double>{p.Qloc2 + gp * bw, bw, Qrow + (int64_t)(rows + 1) * bw};
-      sg[3] = CopySeg<double>{p.Qs2 + (int64_t)u_lo * bw2, (int64_t)nm * bw2, Qsl};
-      sg[4] = CopySeg<double>{p.Qs2 + (int64_t)chunk_of(p, gm) * bw2, bw2, Qsl + (int64_t)nm * bw2};
-      sg[5] = CopySeg<double>{p.Qs2 + (int64_t)chunk_of(p, gp) * bw2, bw2, Qsl + (int64_t)(nm + 1) * bw2};
-    } else if (!given0) {
-      sg[1] = CopySeg<double>{p.Qloc1 + r0 * bw, (int64_t)rows * bw, Qrow};
-      sg[3] = CopySeg<double>{p.Qs1 + (int64_t)u_lo * bw2, (int64_t)nm * bw2, Qsl};
+      for (int m = 0; m < 4; ++m) {
+        const int e = t + 256 * m;
+        vv[kk][m] = (double)base[e < per_slot ? e : per_slot - 1];
+      }
+    }
+    const double* Ql = arn0 ? p.Qloc2 : p.Qloc1;
+    const double* Qsb = arn0 ? p.Qs2 : p.Qs1;
+    const int64_t gm = wrap_row(r0 - 1, n), gp = wrap_row(r0 + rows, n);
+    const int nqr = (arn0 ? rows + 2 : rows) * bw;
+    double qv[5];
+#pragma unroll
+    for (int m = 0; m < 5; ++m) {
+      const int e0 = t + 256 * m;
+      const int e = e0 < nqr ? e0 : nqr - 1;
+      int64_t a;
+      if (arn0)  // halo rows wrap around the periodic grid
+        a = e < bw ? gm * bw + e : (e >= (rows + 1) * bw ? gp * bw + (e - (rows + 1) * bw) : (r0 - 1) * bw + e);
+      else
+        a = r0 * bw + e;
+      qv[m] = Ql[a];
+    }
+    const int ua = chunk_of(p, gm), ub = chunk_of(p, gp);
+    const int nqs = (nm + (arn0 ? 2 : 0)) * bw2;
+    const float inv_bw2 = 1.0f / (float)bw2;
+    auto qs_addr = [&](int e) -> int64_t {
+      const int b = (int)(((float)e + 0.5f) * inv_bw2);
+      const int u = b < nm ? u_lo + b : (b == nm ? ua : ub);
+      return (int64_t)u * bw2 + (e - b * bw2);
+    };
+    double sq[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int e0 = t + 256 * m;
+      sq[m] = Qsb[qs_addr(e0 < nqs ? e0 : nqs - 1)];
     }
 #pragma unroll
     for (int kk = 0; kk < kSlotGroup; ++kk) {
       const int i = i_lo + kk;
       if (i < i_hi && !(arn0 && i == j))
-        sv[kk] = CopySeg<TS>{V + (int64_t)i * blk + r0 * bw, (int64_t)rows * bw, Vs + (int64_t)kk * p.rows_p * bw};
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          const int e = t + 256 * m;
+          if (e < per_slot) Vs[(int64_t)kk * p.rows_p * bw + e] = vv[kk][m];
+        }
     }
-    if constexpr (std::is_same<TS, double>::value) {
-      CopySeg<double> all[6 + kSlotGroup];
+    if (!given0) {
 #pragma unroll
-      for (int q = 0; q < 6; ++q) all[q] = sg[q];
+      for (int m = 0; m < 5; ++m)
+        if (t + 256 * m < nqr) Qrow[t + 256 * m] = qv[m];
 #pragma unroll
-      for (int q = 0; q < kSlotGroup; ++q) all[6 + q] = sv[q];
-      bulk_copy(all);
-    } else {
-      bulk_copy(sg);
-      bulk_copy(sv);
+      for (int m = 0; m < 4; ++m)
+        if (t + 256 * m < nqs) Qsl[t + 256 * m] = sq[m];
+      for (int e = t + 1024; e < nqs; e += 256) Qsl[e] = Qsb[qs_addr(e)];  // wide blocks only
     }
   }
   if (given0)

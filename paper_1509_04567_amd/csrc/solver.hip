@@ -170,7 +170,7 @@ void set_geometry(ProbDev& d, int64_t n, int bw) {
   d.rows_u_log2 = 0;
   while ((1 << d.rows_u_log2) < d.rows_u) ++d.rows_u_log2;
   d.Cu = (int)std::max<int64_t>(1, n / d.rows_u);
-  d.rows_p = rows_p_for(bw);
+  d.rows_p = rows_p_for(bw);  // rows_p * bw <= 1024: the projection kernel's staging assumes it
   d.Cp = (int)((n + d.rows_p - 1) / d.rows_p);
 }
 
