@@ -16,6 +16,21 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary
+    (FETCH_SIZE + WRITE_SIZE, scaled by a device copy of known size), or None when the
+    summary is missing or was taken on a different kernel source."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"pmc_{kernel}_c2_n8192.txt")
+    src = os.path.join(ROOT, "paper_1509_04567_amd", "csrc", "kernels.hip")
+    try:
+        rec = json.loads(open(path).read().split("\n---\n", 1)[1])
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except (OSError, IndexError, ValueError):
+        return None
+    return rec["traffic_bytes_per_launch"] if rec.get("kernels_hip_sha256") == sha else None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -25,6 +40,8 @@ def main():
     ap.add_argument("--n", type=int, default=8192)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--roofline-kernel", default="block_update", choices=["block_update", "block_proj"])
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="run one device copy of this many MiB first (reference for memory counters)")
     ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work for the baseline")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -38,6 +55,12 @@ def main():
     import synth
     import paper_1509_04567_amd as pe
 
+    if args.calibrate_copy > 0:
+        src = torch.ones(args.calibrate_copy * (1 << 20) // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     prec = pe.PE_FP64 if args.precision == "fp64" else pe.PE_MIXED
     prob = synth.config_c2(n=args.n)
     ctx = pe.Context(0)
@@ -63,10 +86,11 @@ def main():
     launches, k_ms, k_bytes, k_flops = prof["launches"], prof["ms"], prof["bytes"], prof["flops"]
     ctx.profile_enable(None)
     roof = None
+    traffic = measured_traffic(args.roofline_kernel)
     if launches > 0 and k_ms > 0:
         achieved = k_bytes / (k_ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": args.roofline_kernel,
+                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": args.roofline_kernel,
                 "launches": launches, "avg_launch_us": 1e3 * k_ms / launches,
                 "algorithmic_bytes_per_launch": k_bytes / launches,
                 "flops_per_launch": k_flops / launches}
