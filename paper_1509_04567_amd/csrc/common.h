@@ -20,8 +20,8 @@ struct ProbDev {
   const double* coef;      // 3*n rows when per_point == 1
 
   // Krylov basis: (lmax+1) blocks of n*bw, row-major inside a block; fp64 or fp32 storage
-  double* V;
-  float* V32;
+  double* V;               // fp64 basis; with mixed storage only block 0, in fp64
+  float* V32;              // fp32 basis (mixed storage)
   int32_t mixed;           // 1: basis stored in fp32 (V32), arithmetic in fp64
   double* Qloc1;           // n*bw local Q factors of the two TSQR passes
   double* Qloc2;

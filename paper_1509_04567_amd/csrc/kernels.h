@@ -29,7 +29,9 @@ void launch_stencil_cols(int64_t n, int per_point, const double* c3, const doubl
 void launch_add_column(int64_t n, int s, const double* G, int64_t ldG, const double* add, double* Gh,
                        int64_t ldGh, hipStream_t st);
 
-// block orthogonalisation (batched over problems; basis storage fp32 when `mixed`)
+// block orthogonalisation (batched over problems; basis storage fp32 when `mixed`);
+// init_block_kernels sets their launch attributes once (also called by the launchers)
+void init_block_kernels();
 void launch_block_proj(ProbDev* d, int nprob, int grid_x, size_t smem, int j, int nb, int pass, int mode,
                        int mixed, hipStream_t st);
 void launch_block_update(ProbDev* d, int nprob, int grid_x, size_t smem, int j, int nb, int pass, int mode,

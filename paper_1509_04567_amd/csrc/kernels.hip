@@ -16,6 +16,8 @@
 // produce in the first Krylov steps.
 #include "kernels.h"
 
+#include <type_traits>
+
 #include <cmath>
 
 namespace pe {
@@ -713,7 +715,11 @@ __global__ __launch_bounds__(256) void k_block_proj(const ProbDev* __restrict__ 
         for (int k = 0; k < bw; ++k) v += q[k] * sq[k * bw];
         const TS vs = (TS)v;
         Vh[rr * bw + col] = (double)vs;
-        if (commit && rr >= 1 && rr <= rows) V[(int64_t)j * blk + (r0 - 1 + rr) * bw + col] = vs;
+        if (commit && rr >= 1 && rr <= rows) {
+          V[(int64_t)j * blk + (r0 - 1 + rr) * bw + col] = vs;
+          // fp32 storage: block 0 is also kept unrounded for the state projection
+          if (!std::is_same<TS, double>::value && j == 0) p.V[(r0 - 1 + rr) * bw + col] = v;
+        }
       }
     __syncthreads();
     if (act)
@@ -1032,19 +1038,23 @@ __global__ void k_block_commit(const ProbDev* __restrict__ probs, int j) {
   basis_ptr<TS>(p)[(int64_t)j * p.n * bw + e] = (TS)tsqr_entry(p, p.Qloc2, p.Qs2, r, col);
 }
 
+void init_block_kernels() {
+  static bool done = false;
+  if (done) return;
+  // opt in to large dynamic LDS (gfx950 has 160 KiB per CU); a refusal leaves the 64 KiB
+  // default, which the host-side geometry check then enforces
+  const void* fns[4] = {(const void*)k_block_proj<double>, (const void*)k_block_proj<float>,
+                        (const void*)k_block_update<double>, (const void*)k_block_update<float>};
+  for (const void* f : fns)
+    if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, kUpdateLdsMax) != hipSuccess)
+      (void)hipGetLastError();
+  done = true;
+}
+
 void launch_block_proj(ProbDev* d, int nprob, int grid_x, size_t smem, int j, int nb, int pass, int mode,
                        int mixed, hipStream_t st) {
   if (grid_x <= 0 || nprob <= 0 || nb <= 0) return;
-  static bool attr_set = false;
-  if (!attr_set) {
-    if (hipFuncSetAttribute((const void*)k_block_proj<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            kUpdateLdsMax) != hipSuccess)
-      (void)hipGetLastError();
-    if (hipFuncSetAttribute((const void*)k_block_proj<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            kUpdateLdsMax) != hipSuccess)
-      (void)hipGetLastError();
-    attr_set = true;
-  }
+  init_block_kernels();
   dim3 grid((unsigned)grid_x, (unsigned)nprob);
   if (mixed)
     hipLaunchKernelGGL(k_block_proj<float>, grid, dim3(256), smem, st, d, j, nb, pass, mode);
@@ -1055,18 +1065,7 @@ void launch_block_proj(ProbDev* d, int nprob, int grid_x, size_t smem, int j, in
 void launch_block_update(ProbDev* d, int nprob, int grid_x, size_t smem, int j, int nb, int pass, int mode,
                          int mixed, hipStream_t st) {
   if (grid_x <= 0 || nprob <= 0) return;
-  static bool attr_set = false;
-  if (!attr_set) {
-    // opt in to large dynamic LDS (gfx950 has 160 KiB per CU); a refusal leaves the
-    // 64 KiB default, which the host-side geometry check then enforces
-    if (hipFuncSetAttribute((const void*)k_block_update<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            kUpdateLdsMax) != hipSuccess)
-      (void)hipGetLastError();
-    if (hipFuncSetAttribute((const void*)k_block_update<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            kUpdateLdsMax) != hipSuccess)
-      (void)hipGetLastError();
-    attr_set = true;
-  }
+  init_block_kernels();
   dim3 grid((unsigned)grid_x, (unsigned)nprob);
   if (mixed)
     hipLaunchKernelGGL(k_block_update<float>, grid, dim3(256), smem, st, d, j, nb, pass, mode);
@@ -1356,7 +1355,13 @@ __global__ __launch_bounds__(256) void k_project(const ProbDev* __restrict__ pro
   const TS* V = basis_ptr<TS>(p);
   const int64_t blk = p.n * bw;
   double acc = 0.0;
-  for (int i = 0; i < p.l; ++i) {
+  // block 0 (the orthonormalised [U | x]) carries most of the state: with fp32 storage
+  // it is read from its fp64 copy, so short steps do not re-round the state
+  if (!std::is_same<TS, double>::value) {
+    const double* row = p.V + r * bw;
+    for (int c = 0; c < bw; ++c) acc += row[c] * ys[c];
+  }
+  for (int i = std::is_same<TS, double>::value ? 0 : 1; i < p.l; ++i) {
     const TS* row = V + (int64_t)i * blk + r * bw;
     for (int c = 0; c < bw; ++c) acc += (double)row[c] * ys[i * bw + c];
   }

@@ -226,12 +226,14 @@ BlockCaps block_caps(int64_t n, int bwmax, int nbmax, int64_t H_rows, int64_t H_
 }
 
 struct BlockOffsets {
-  size_t V, Qloc1, Qloc2, Rloc, Cn, Qs1, Qs2, Rf, Part, S, H, cnt;
+  size_t V, V0, Qloc1, Qloc2, Rloc, Cn, Qs1, Qs2, Rf, Part, S, H, cnt;
 };
 
 BlockOffsets carve_block(Carver& cv, const BlockCaps& c, bool mixed) {
   BlockOffsets o;
   o.V = mixed ? cv.take<float>(c.basis) : cv.take<double>(c.basis);
+  // mixed: block 0 (the orthonormalised [U | x]) is also kept in fp64 for the projection
+  o.V0 = mixed ? cv.take<double>((size_t)c.n * c.bwmax) : 0;
   o.Qloc1 = cv.take<double>(c.qloc);
   o.Qloc2 = cv.take<double>(c.qloc);
   o.Rloc = cv.take<double>(c.rloc);
@@ -247,7 +249,7 @@ BlockOffsets carve_block(Carver& cv, const BlockCaps& c, bool mixed) {
 }
 
 void bind_block(ProbDev& d, char* base, const BlockOffsets& o, bool mixed, int nbmax) {
-  d.V = mixed ? nullptr : (double*)(base + o.V);
+  d.V = mixed ? (double*)(base + o.V0) : (double*)(base + o.V);
   d.V32 = mixed ? (float*)(base + o.V) : nullptr;
   d.mixed = mixed ? 1 : 0;
   d.Qloc1 = (double*)(base + o.Qloc1);

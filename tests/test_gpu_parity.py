@@ -175,3 +175,27 @@ def test_c2_full_size_fp64(ctx):
     outs, reps = ctx.solve_batch([p])
     assert reps[0]["rank"] == 7 and reps[0]["q"] == 7
     assert rel(gpu_out(outs[0]), ref) < FP64_TOL, reps[0]
+
+
+# ------------------------------------------------------------------ mixed precision (fp32 basis storage)
+@pytest.mark.parametrize("name", ["c1", "rand_shift"])
+def test_mixed_basis_storage(ctx, name):
+    import paper_1509_04567_amd as pe
+    if name == "c1":
+        p = synth.config_c1()
+    else:
+        p = synth.random_ade_problem(21, 300, n_out=5)
+    p.tol = 1e-9  # the fp32 basis sets the floor of the residual estimate
+    ref, _ = oracle.solve_window(p, "dense")
+    outs, reps = ctx.solve_batch([p], pe.PE_MIXED)
+    assert rel(gpu_out(outs[0]), ref) < MIXED_TOL, reps[0]
+
+
+def test_c2_full_size_mixed(ctx):
+    import paper_1509_04567_amd as pe
+    p = synth.config_c2()
+    p.tol = 1e-8
+    ref, _ = oracle.solve_window(p, "spectral")
+    outs, reps = ctx.solve_batch([p], pe.PE_MIXED)
+    assert rel(gpu_out(outs[0]), ref) < MIXED_TOL, reps[0]
+
