@@ -565,6 +565,7 @@ struct HostState {
   bool pending = false, accepted = false;
   int level = 0;
   double rho = 1.0;
+  double pexp = 0.0;  // local order of the error estimate in the step (0: unknown)
 };
 
 pe_status march_batch(pe_ctx* ctx, const pe_problem* probs, const int* idx, int nb_prob, const double* const* Ul,
@@ -848,6 +849,14 @@ pe_status march_batch(pe_ctx* ctx, const pe_problem* probs, const int* idx, int 
           h.flags |= PE_FLAG_NOT_CONVERGED;
         }
         if (best >= 0) {
+          // local order p of the estimate, err ~ delta^p, from two squaring levels
+          // (their steps differ by 2); only where both are well above rounding
+          const int lo = best < ns ? best : best - 1;
+          if (lo >= 0) {
+            const double e_lo = ho[2 * lo], e_hi = ho[2 * (lo + 1)];
+            if (std::isfinite(e_hi) && e_lo > 1e-6 * best_lim && e_hi > 2.0 * e_lo)
+              h.pexp = std::min(40.0, std::max(2.0, std::log2(e_hi / e_lo)));
+          }
           h.accepted = true;
           h.pending = false;
           h.level = best;
@@ -901,8 +910,10 @@ pe_status march_batch(pe_ctx* ctx, const pe_problem* probs, const int* idx, int 
       // a step clipped at an output time does not limit the next one
       if (!landed || h.dtry >= h.dlast) h.dlast = h.dtry;
       {
-        const double ex = 1.0 / std::max(2.0, p.krylov_steps / 3.0);
-        h.dgrow = std::min(4.0, std::max(1.25, 0.9 * std::pow(std::max(h.rho, 1e-30), -ex)));
+        // next step from the error model err ~ delta^p of this step (aiming at 0.95 of
+        // the limit); without an estimate of p, the order of a Krylov space of l steps
+        const double ex = h.pexp > 0.0 ? 1.0 / h.pexp : 1.0 / std::max(2.0, p.krylov_steps / 3.0);
+        h.dgrow = std::min(4.0, std::max(0.5, 0.95 * std::pow(std::max(h.rho, 1e-30), -ex)));
       }
       h.xzero = false;
       ++h.cycles;
