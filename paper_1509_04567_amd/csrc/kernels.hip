@@ -1175,6 +1175,7 @@ void launch_elementwise(ExpmDev* e, int op, int nprob, int64_t maxNN, hipStream_
 //   op 4: P = T A4 + c7 A3 + c6 A2 + c5 A + c4 I
 //   op 5: T = P A4 + c3 A3 + c2 A2 + c1 A + c0 I
 //   op 6: squaring number k: (k even) P = T T, (k odd) T = P P; skipped when k >= nsq
+constexpr int kGemmK = 64;  // K extent of one staged tile pair
 __global__ __launch_bounds__(256) void k_gemm(const ExpmDev* __restrict__ E, int op, int k) {
   const ExpmDev e = E[blockIdx.y];  // by value: uniform, loaded once
   if (!e.active) return;
@@ -1199,27 +1200,29 @@ __global__ __launch_bounds__(256) void k_gemm(const ExpmDev* __restrict__ E, int
       else { A = e.T; B = e.T; C = e.P; }
       break;
   }
-  __shared__ double As[16][33];
-  __shared__ double Bs[32][17];
+  // K-tiles of kGemmK: A tile 32 x kGemmK (k-major), B tile kGemmK x 32 (column-major)
+  constexpr int KT = kGemmK, EPT = 32 * KT / 256;  // elements of each tile per thread
+  __shared__ double As[KT][33];
+  __shared__ double Bs[32][KT + 1];
   const int t = threadIdx.x;
   const int lane = t & 63, w = t >> 6;
   const int wi = w & 1, wj = w >> 1;
   dbl4 acc = {0.0, 0.0, 0.0, 0.0};
   // the next K-tile is loaded into registers (clamped addresses, unconditional loads)
   // while the current one is multiplied from LDS
-  double ra[2], rb[2];
+  double ra[EPT], rb[EPT];
   auto load_tile = [&](int kk) {
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
+    for (int h = 0; h < EPT; ++h) {
       const int q = t + 256 * h;
       {
-        const int kq = q >> 5, iq = q & 31;
+        const int kq = q >> 5, iq = q & 31;  // 32 consecutive rows of one column
         const int gi = i0 + iq, gk = kk + kq;
         const double v = A[(int64_t)(gi < N ? gi : N - 1) + (int64_t)N * (gk < N ? gk : N - 1)];
         ra[h] = (gi < N && gk < N) ? v : 0.0;
       }
       {
-        const int jq = q >> 4, kq = q & 15;
+        const int jq = q / KT, kq = q % KT;  // KT consecutive k of one column
         const int gj = j0 + jq, gk = kk + kq;
         const double v = B[(int64_t)(gk < N ? gk : N - 1) + (int64_t)N * (gj < N ? gj : N - 1)];
         rb[h] = (gj < N && gk < N) ? v : 0.0;
@@ -1227,17 +1230,17 @@ __global__ __launch_bounds__(256) void k_gemm(const ExpmDev* __restrict__ E, int
     }
   };
   load_tile(0);
-  for (int kk = 0; kk < N; kk += 16) {
+  for (int kk = 0; kk < N; kk += KT) {
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
+    for (int h = 0; h < EPT; ++h) {
       const int q = t + 256 * h;
       As[q >> 5][q & 31] = ra[h];
-      Bs[q >> 4][q & 15] = rb[h];
+      Bs[q / KT][q % KT] = rb[h];
     }
     __syncthreads();
-    if (kk + 16 < N) load_tile(kk + 16);
+    if (kk + KT < N) load_tile(kk + KT);
 #pragma unroll
-    for (int k4 = 0; k4 < 16; k4 += 4) {
+    for (int k4 = 0; k4 < KT; k4 += 4) {
       const double a = As[k4 + (lane >> 4)][wi * 16 + (lane & 15)];
       const double b = Bs[wj * 16 + (lane & 15)][k4 + (lane >> 4)];
       acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
