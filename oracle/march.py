@@ -146,6 +146,15 @@ class _SpectralStepper:
         return z[:, 0], z[0, 1:].real.copy()
 
 
+_GROWTH = 100.0
+
+
+def _chebyshev_w(seg, t):
+    """w(t) = [T_k(x(t))], x = (2t - ta - tb) / (tb - ta), of a source segment."""
+    x = (2.0 * t - seg.ta - seg.tb) / (seg.tb - seg.ta)
+    return chebyshev_vandermonde(np.array([x]), seg.q)[0]
+
+
 def _march(route, n, segments: List[_Segment], x0, t_start, t_out):
     """Advance the state through consecutive segments, recording it at t_out."""
     stepper = _SpectralStepper(n) if route == "spectral" else _DenseStepper(n)
@@ -162,7 +171,22 @@ def _march(route, n, segments: List[_Segment], x0, t_start, t_out):
             seg = segments[si]
             te = min(tk, seg.tb)
             if te > t:
-                st, w = stepper.advance(seg, st, w, te - t)
+                if seg.q:
+                    # The polynomial block's exponential over a long step multiplies
+                    # rounding by the Chebyshev re-expansion coefficients of the shift
+                    # (about (1 + sqrt(2c))^q for a shift of c = 2 step / window in x),
+                    # which reaches 1e12 for q = 32 over a whole window.  Since
+                    # exp(d A) = exp(d A / m)^m, a long step is taken as m equal pieces
+                    # whose growth factor stays below _GROWTH, each starting from the
+                    # exact w(t) = [T_k(x(t))] that the augmented system carries.
+                    c_max = 0.5 * (_GROWTH ** (1.0 / seg.q) - 1.0) ** 2
+                    m = max(1, int(math.ceil(2.0 * (te - t) / (seg.tb - seg.ta) / c_max)))
+                    d = (te - t) / m
+                    for i in range(m):
+                        w = _chebyshev_w(seg, t + i * d)
+                        st, w = stepper.advance(seg, st, w, d)
+                else:
+                    st, w = stepper.advance(seg, st, w, te - t)
                 t = te
             if t >= seg.tb and si + 1 < len(segments):
                 si += 1
