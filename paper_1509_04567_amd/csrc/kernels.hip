@@ -604,6 +604,7 @@ __global__ __launch_bounds__(256) void k_block_proj(const ProbDev* __restrict__ 
   const int c = blockIdx.x % p.Cp;
   const int ngroups = (nb + kSlotGroup - 1) / kSlotGroup;
   if (grp >= ngroups) return;
+  if (mode == MODE_ARNOLDI && pass == 1 && p.cnt[2 * p.nbmax + 1]) return;  // reorthogonalisation not needed
   const int64_t n = p.n;
   const int64_t r0 = (int64_t)c * p.rows_p;
   if (r0 >= n) return;
@@ -871,6 +872,8 @@ __device__ __forceinline__ void subtract_proj_mfma(const TS* V, int64_t blk, con
   __syncthreads();
 }
 
+constexpr double kReorthSkip = 0.1;
+
 template <typename TS>
 __global__ __launch_bounds__(256) void k_block_update(const ProbDev* __restrict__ probs, int j, int nb, int pass, int mode) {
   const ProbDev p = probs[blockIdx.y];  // by value: uniform, loaded once
@@ -898,6 +901,26 @@ __global__ __launch_bounds__(256) void k_block_update(const ProbDev* __restrict_
   const TS* V = basis_ptr<TS>(p);
   const int64_t blk = n * bw;
   const bool hcol = (mode != MODE_INIT && pass == 1);
+
+  // Arnoldi steps whose first pass kept enough of every column skip the second pass:
+  // V_{j+1} = Q1, H column = S1 and subdiagonal block Rf1 (W = V S1 + Q1 Rf1 exactly)
+  if (mode == MODE_ARNOLDI && pass == 1 && p.cnt[2 * p.nbmax + 1]) {
+    const double* R1 = p.Rf;
+    const double* S1 = p.S;
+    for (int e = t; e < rows * bw; e += 256) p.Qloc2[r0 * bw + e] = p.Qloc1[r0 * bw + e];
+    for (int o = t; o < nout; o += 256) p.Qs2[(int64_t)u * nout + o] = p.Qs1[(int64_t)u * nout + o];
+    for (int i = u; i < nb; i += p.Cu)
+      for (int o = t; o < nout; o += 256)
+        p.H[(int64_t)(i * bw + o / bw) + p.ldH * (int64_t)(j * bw + o % bw)] = S1[(int64_t)i * nout + o];
+    if (u == 0)
+      for (int o = t; o < nout; o += 256)
+        p.H[(int64_t)(nb * bw + o / bw) + p.ldH * (int64_t)(j * bw + o % bw)] = R1[o];
+    const int64_t r_lo = (int64_t)(nb + 1) * bw;
+    const int64_t zcnt = (p.ldH - r_lo) * bw;
+    for (int64_t e = (int64_t)u * 256 + t; e < zcnt; e += (int64_t)p.Cu * 256)
+      p.H[r_lo + e / bw + p.ldH * (int64_t)(j * bw + e % bw)] = 0.0;
+    return;
+  }
 
   // 0. pass 1: blocks i < nb of column block j of H (of R in MODE_GIVEN), one block per
   //    workgroup: H_ij = S1_i + S2_i Rf1 (the block nb needs the combine below)
@@ -1012,6 +1035,19 @@ __global__ __launch_bounds__(256) void k_block_update(const ProbDev* __restrict_
   }
   double* Rout = p.Rf + (mode == MODE_INIT ? 2 : pass) * nout;
   for (int o = t; o < nout; o += 256) Rout[o] = Rl[o];
+  if (mode == MODE_ARNOLDI && pass == 0 && t == 0) {
+    // keep fraction of each column after the first projection (R column norm against
+    // the pre-projection norm); above kReorthSkip every column of Q1 is orthogonal to
+    // the basis to ~eps / kReorthSkip and the second pass is skipped
+    double mn = 1e300;
+    for (int b = 0; b < bw; ++b) {
+      double c2 = 0.0;
+      for (int a = 0; a <= b; ++a) c2 += Rl[a * bw + b] * Rl[a * bw + b];
+      const double r = Rn[b] > 0.0 ? sqrt(c2) / Rn[b] : 0.0;
+      mn = r < mn ? r : mn;
+    }
+    p.cnt[2 * p.nbmax + 1] = mn >= kReorthSkip ? 1u : 0u;
+  }
   if (hcol) {
     // W = V (S1 + S2 Rf1) + Q2 (Rf2 Rf1): the subdiagonal block of column block j
     const double* R1 = p.Rf;

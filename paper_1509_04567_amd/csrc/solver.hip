@@ -219,7 +219,7 @@ BlockCaps block_caps(int64_t n, int bwmax, int nbmax, int64_t H_rows, int64_t H_
   c.part = 2 * (size_t)nbmax * cp_bw2;
   c.S = 2 * (size_t)nbmax * bwmax * bwmax;
   c.H = (size_t)H_rows * H_cols;
-  c.cnt = 2 * (size_t)nbmax + 1;
+  c.cnt = 2 * (size_t)nbmax + 2;  // projection groups (2 passes), update counter, reorth flag
   c.ldH_rows = H_rows;
   c.H_cols = H_cols;
   return c;
