@@ -1450,6 +1450,21 @@ __global__ __launch_bounds__(256) void k_jacobi_svd(const double* R, int64_t ldR
   }
   for (int64_t e = t; e < (int64_t)r * r; e += blockDim.x) J[e] = ((e % r) == (e / r)) ? 1.0 : 0.0;
   __syncthreads();
+  // largest squared row norm: pairs whose coupling is below rounding of the largest
+  // singular value (noise rows of the factor) count as converged
+  {
+    double mx = 0.0;
+    for (int i = w; i < r; i += 4) {
+      double q = 0.0;
+      for (int k = lane; k < s; k += 64) q += A[(int64_t)i * s + k] * A[(int64_t)i * s + k];
+      mx = fmax(mx, wave_sum(q));
+    }
+    if (lane == 0) wmax[w] = mx;
+    __syncthreads();
+    if (t == 0) red[0] = fmax(fmax(wmax[0], wmax[1]), fmax(wmax[2], wmax[3]));
+    __syncthreads();
+  }
+  const double floor2 = 1e-15 * red[0];
   const int r2 = r + (r & 1);
   int sweep = 0;
   for (; sweep < 30 && r > 1; ++sweep) {
@@ -1476,7 +1491,7 @@ __global__ __launch_bounds__(256) void k_jacobi_svd(const double* R, int64_t ldR
         al = wave_sum(al);
         be = wave_sum(be);
         ga = wave_sum(ga);
-        if (ga == 0.0 || al == 0.0 || be == 0.0) continue;
+        if (ga == 0.0 || al == 0.0 || be == 0.0 || fabs(ga) <= floor2) continue;
         const double rel = fabs(ga) / sqrt(al * be);
         off = fmax(off, rel);
         if (rel < 1e-15) continue;
@@ -1528,7 +1543,6 @@ __global__ __launch_bounds__(256) void k_jacobi_svd(const double* R, int64_t ldR
     }
     info[0] = sweep;
   }
-  (void)red;
 }
 
 void launch_jacobi_svd(const double* R, int64_t ldR, const int* sel, int s, int r, double* A, double* J,
