@@ -644,8 +644,11 @@ __global__ __launch_bounds__(256) void k_block_proj(const ProbDev* __restrict__ 
         vv[kk][m] = (double)base[e < per_slot ? e : per_slot - 1];
       }
     }
-    const double* Ql = arn0 ? p.Qloc2 : p.Qloc1;
-    const double* Qsb = arn0 ? p.Qs2 : p.Qs1;
+    // V_j is the last pass's TSQR output: the first pass's when the previous step
+    // skipped its second pass
+    const bool first = !arn0 || p.cnt[2 * p.nbmax + 1] != 0;
+    const double* Ql = first ? p.Qloc1 : p.Qloc2;
+    const double* Qsb = first ? p.Qs1 : p.Qs2;
     const int64_t gm = wrap_row(r0 - 1, n), gp = wrap_row(r0 + rows, n);
     const int nqr = (arn0 ? rows + 2 : rows) * bw;
     double qv[5];
@@ -902,25 +905,9 @@ __global__ __launch_bounds__(256) void k_block_update(const ProbDev* __restrict_
   const int64_t blk = n * bw;
   const bool hcol = (mode != MODE_INIT && pass == 1);
 
-  // Arnoldi steps whose first pass kept enough of every column skip the second pass:
-  // V_{j+1} = Q1, H column = S1 and subdiagonal block Rf1 (W = V S1 + Q1 Rf1 exactly)
-  if (mode == MODE_ARNOLDI && pass == 1 && p.cnt[2 * p.nbmax + 1]) {
-    const double* R1 = p.Rf;
-    const double* S1 = p.S;
-    for (int e = t; e < rows * bw; e += 256) p.Qloc2[r0 * bw + e] = p.Qloc1[r0 * bw + e];
-    for (int o = t; o < nout; o += 256) p.Qs2[(int64_t)u * nout + o] = p.Qs1[(int64_t)u * nout + o];
-    for (int i = u; i < nb; i += p.Cu)
-      for (int o = t; o < nout; o += 256)
-        p.H[(int64_t)(i * bw + o / bw) + p.ldH * (int64_t)(j * bw + o % bw)] = S1[(int64_t)i * nout + o];
-    if (u == 0)
-      for (int o = t; o < nout; o += 256)
-        p.H[(int64_t)(nb * bw + o / bw) + p.ldH * (int64_t)(j * bw + o % bw)] = R1[o];
-    const int64_t r_lo = (int64_t)(nb + 1) * bw;
-    const int64_t zcnt = (p.ldH - r_lo) * bw;
-    for (int64_t e = (int64_t)u * 256 + t; e < zcnt; e += (int64_t)p.Cu * 256)
-      p.H[r_lo + e / bw + p.ldH * (int64_t)(j * bw + e % bw)] = 0.0;
-    return;
-  }
+  // Arnoldi steps whose first pass kept enough of every column skip the second pass
+  // (decided, and column block j of H written, by the first pass's last workgroup)
+  if (mode == MODE_ARNOLDI && pass == 1 && p.cnt[2 * p.nbmax + 1]) return;
 
   // 0. pass 1: blocks i < nb of column block j of H (of R in MODE_GIVEN), one block per
   //    workgroup: H_ij = S1_i + S2_i Rf1 (the block nb needs the combine below)
@@ -1035,18 +1022,37 @@ __global__ __launch_bounds__(256) void k_block_update(const ProbDev* __restrict_
   }
   double* Rout = p.Rf + (mode == MODE_INIT ? 2 : pass) * nout;
   for (int o = t; o < nout; o += 256) Rout[o] = Rl[o];
-  if (mode == MODE_ARNOLDI && pass == 0 && t == 0) {
+  if (mode == MODE_INIT && t == 0) p.cnt[2 * p.nbmax + 1] = 0u;
+  if (mode == MODE_ARNOLDI && pass == 0) {
     // keep fraction of each column after the first projection (R column norm against
     // the pre-projection norm); above kReorthSkip every column of Q1 is orthogonal to
-    // the basis to ~eps / kReorthSkip and the second pass is skipped
-    double mn = 1e300;
-    for (int b = 0; b < bw; ++b) {
-      double c2 = 0.0;
-      for (int a = 0; a <= b; ++a) c2 += Rl[a * bw + b] * Rl[a * bw + b];
-      const double r = Rn[b] > 0.0 ? sqrt(c2) / Rn[b] : 0.0;
-      mn = r < mn ? r : mn;
+    // the basis to ~eps / kReorthSkip and the second pass is skipped:
+    // V_{j+1} = Q1, H column = S1 and subdiagonal block Rf1 (W = V S1 + Q1 Rf1 exactly)
+    __shared__ int skip;
+    if (t == 0) {
+      double mn = 1e300;
+      for (int b = 0; b < bw; ++b) {
+        double c2 = 0.0;
+        for (int a = 0; a <= b; ++a) c2 += Rl[a * bw + b] * Rl[a * bw + b];
+        const double r = Rn[b] > 0.0 ? sqrt(c2) / Rn[b] : 0.0;
+        mn = r < mn ? r : mn;
+      }
+      skip = mn >= kReorthSkip ? 1 : 0;
+      p.cnt[2 * p.nbmax + 1] = (unsigned)skip;
     }
-    p.cnt[2 * p.nbmax + 1] = mn >= kReorthSkip ? 1u : 0u;
+    __syncthreads();
+    if (skip) {
+      const double* S1 = p.S;
+      for (int e = t; e < nb * nout; e += 256) {
+        const int i = e / nout, o = e - i * nout;
+        p.H[(int64_t)(i * bw + o / bw) + p.ldH * (int64_t)(j * bw + o % bw)] = S1[e];
+      }
+      for (int o = t; o < nout; o += 256)
+        p.H[(int64_t)(nb * bw + o / bw) + p.ldH * (int64_t)(j * bw + o % bw)] = Rl[o];
+      const int64_t r_lo = (int64_t)(nb + 1) * bw;
+      for (int64_t e = t; e < (p.ldH - r_lo) * bw; e += 256)
+        p.H[r_lo + e / bw + p.ldH * (int64_t)(j * bw + e % bw)] = 0.0;
+    }
   }
   if (hcol) {
     // W = V (S1 + S2 Rf1) + Q2 (Rf2 Rf1): the subdiagonal block of column block j
