@@ -64,7 +64,10 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     prec = pe.PE_FP64 if args.precision == "fp64" else pe.PE_MIXED
-    probs = [synth.config_c2(n=args.n, seed=2 + i) for i in range(max(1, args.batch))]
+    # the FP32-stored basis puts a floor of ~1e-9 under the residual estimate, so the
+    # mixed path runs at tol 1e-8 (its accuracy target is 1e-7 against the FP64 oracle)
+    tol = 1e-12 if args.precision == "fp64" else 1e-8
+    probs = [synth.config_c2(n=args.n, seed=2 + i, tol=tol) for i in range(max(1, args.batch))]
     prob = probs[0]
     ctx = pe.Context(0)
     staged = ctx.prepare(probs, prec)
@@ -89,8 +92,8 @@ def main():
     launches, k_ms, k_bytes, k_flops = prof["launches"], prof["ms"], prof["bytes"], prof["flops"]
     ctx.profile_enable(None)
     roof = None
-    # the committed counter summary covers the single-window workload only
-    traffic = measured_traffic(args.roofline_kernel) if args.batch <= 1 else None
+    # the committed counter summary covers the single-window FP64 workload only
+    traffic = measured_traffic(args.roofline_kernel) if args.batch <= 1 and args.precision == "fp64" else None
     if launches > 0 and k_ms > 0:
         achieved = k_bytes / (k_ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -206,10 +206,11 @@ pe_status pe_wr_burgers(pe_ctx* ctx, const pe_wr_problem* wr, pe_report* reports
                         void* stream);
 
 /* Kernel timing for roofline measurements.  Enables HIP-event timing, on the stream of
- * each call, of every launch of one kernel family: "block_update" (block Gram-Schmidt
- * update + chunk QR + TSQR combine), "block_proj" (block projections), "stencil"
+ * each call, of one kernel family: "block_update" (block Gram-Schmidt update + chunk QR
+ * + TSQR combine) or "block_proj" (block projections) -- the first orthogonalisation
+ * pass of every block Arnoldi step, which always runs in full -- or "stencil"
  * (pe_stencil_apply), or NULL to switch timing off.  Resets the accumulators.  Timing
- * adds two event records per launch, so time throughput separately. */
+ * adds two event records per launch. */
 pe_status pe_profile_enable(pe_ctx* ctx, const char* family);
 /* Read and reset the accumulators: timed launches, their summed duration (ms), and the
  * algorithmic traffic (bytes, each datum read or written once per launch) and flops of

@@ -359,11 +359,14 @@ struct StepCost {
 
 void run_block_step(pe_ctx* ctx, ProbDev* dd, int nprob, int gx_proj, size_t smem_p, int gx_upd, size_t smem_u,
                     int j, int nb, int mode, int mixed, const StepCost& cost, hipStream_t st) {
+  // Timing covers the first pass, which every step runs in full; the second pass runs
+  // only where the first lost too much of a column (decided on the device), so its
+  // launches do not all carry the algorithmic traffic of the cost model.
   for (int pass = 0; pass < 2; ++pass) {
-    int ev = prof_begin(ctx, "block_proj", st);
+    int ev = pass == 0 ? prof_begin(ctx, "block_proj", st) : -1;
     pe::launch_block_proj(dd, nprob, gx_proj, smem_p, j, nb, pass, mode, mixed, st);
     prof_end(ctx, ev, cost.proj_bytes, cost.flops, st);
-    ev = prof_begin(ctx, "block_update", st);
+    ev = pass == 0 ? prof_begin(ctx, "block_update", st) : -1;
     pe::launch_block_update(dd, nprob, gx_upd, smem_u, j, nb, pass, mode, mixed, st);
     prof_end(ctx, ev, cost.upd_bytes, cost.flops, st);
   }
