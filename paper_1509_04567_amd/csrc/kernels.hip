@@ -61,19 +61,6 @@ __device__ double block_sum(double v, double* red) {
   return t;
 }
 
-__device__ double block_max(double v, double* red) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-  __syncthreads();
-  if (l == 0) red[w] = v;
-  __syncthreads();
-  double t = 0.0;
-  const int nw = blockDim.x >> 6;
-  for (int i = 0; i < nw; ++i) t = fmax(t, red[i]);
-  return t;
-}
-
 // splitmix64 finaliser (Steele, Lea & Flood 2014) -> uniform double in [-1, 1)
 __device__ __forceinline__ double hash_unit(uint64_t a, uint64_t b) {
   uint64_t z = a * 0x9E3779B97F4A7C15ull + (b + 1) * 0xD1B54A32D192ED03ull;
