@@ -28,7 +28,8 @@
  *     return after it has completed (the solver's step control reads scalars back);
  *   - errors are negative pe_status values with a message in pe_last_error(); a
  *     non-converged solve is not an error: its report carries PE_FLAG_* bits and the
- *     outputs are still written.
+ *     outputs are still written (NaN at output times that a march does not reach
+ *     within its cap of 100000 restart cycles).
  */
 #ifndef PARAEXP_H
 #define PARAEXP_H
@@ -51,7 +52,7 @@ typedef enum {
 
 /* report flags (informational, outputs are written) */
 enum {
-  PE_FLAG_NOT_CONVERGED = 1,  /* a step was taken at the minimum step with error above tol */
+  PE_FLAG_NOT_CONVERGED = 1,  /* a step at the minimum step had error above tol, or the cycle cap was hit */
   PE_FLAG_BREAKDOWN = 2,      /* Krylov space became invariant (exact, "happy") early      */
   PE_FLAG_RANK_CAPPED = 4,    /* truncation wanted more than rank_max singular vectors     */
   PE_FLAG_FIT_CAPPED = 8      /* fit residual above fit_tol at q_max terms                 */

@@ -57,6 +57,7 @@ struct ProbDev {
   int32_t rows_u;          // rows per update chunk (>= bw); last chunk takes the remainder
   int32_t rows_u_log2;     // rows_u is a power of two
   int32_t Cu;              // number of update chunks
+  int32_t comb_global;     // 1: the TSQR combine works on the stacked factors in global memory
   int32_t rows_p;          // rows per projection chunk
   int32_t Cp;              // number of projection chunks
 };

@@ -179,35 +179,59 @@ __device__ __forceinline__ void mgs2_qr(Ptr X, int rows, int ld, int bw, double*
   }
 }
 
-// Classical Gram-Schmidt applied twice, column by column, by one wave (TSQR chunk and
-// combine QR).  All dot products of a column with the previous columns are reduced
-// together, so a column costs three dependent wave reductions instead of 2b+1.
-// Dependence test and replacement as in mgs2_qr (bw <= 32).
-__device__ __forceinline__ void cgs2_qr_wave(double* X, int rows, int ld, int bw, double* R, uint64_t seed, const double* ref,
-                             int stack) {
-  const int t = threadIdx.x & 63;
+// Classical Gram-Schmidt applied twice, column by column, by a team of NW waves (NW = 1:
+// one wave, no barriers; NW > 1: the whole workgroup, barriers inside) on a rows x bw
+// array X with leading dimension ld, in LDS or global memory (thread t owns rows t,
+// t + 64 NW, ..., so no row is touched by two threads).  All dot products of a column
+// with the previous columns are reduced together: three team reductions per column.
+// A column whose remainder is <= PE_DEP_TOL times its reference norm ref[b] is
+// dependent: it becomes a zero column with a zero row in R (deflation), so it adds no
+// direction and later columns do not couple to it.  R (bw x bw, row-major, pre-zeroed)
+// receives the triangular factor.  `red`: LDS scratch of 32 NW doubles (NW > 1).
+template <int NW>
+__device__ __forceinline__ void cgs2_qr_team(double* X, int rows, int ld, int bw, double* R, const double* ref,
+                                             double* red) {
+  const int t = (NW == 1) ? (int)(threadIdx.x & 63) : (int)threadIdx.x;
+  const int w = t >> 6;
+  constexpr int T = 64 * NW;
+  auto team_sums = [&](double* sd, int na) {
+#pragma unroll
+    for (int a = 0; a < 32; ++a)
+      if (a < na) sd[a] = wave_sum(sd[a]);
+    if (NW > 1) {
+      __syncthreads();
+      if ((t & 63) == 0)
+#pragma unroll
+        for (int a = 0; a < 32; ++a)
+          if (a < na) red[w * 32 + a] = sd[a];
+      __syncthreads();
+#pragma unroll
+      for (int a = 0; a < 32; ++a)
+        if (a < na) {
+          double v = 0.0;
+          for (int ww = 0; ww < NW; ++ww) v += red[ww * 32 + a];
+          sd[a] = v;
+        }
+    }
+  };
   for (int b = 0; b < bw; ++b) {
-    const double n0 = ref[b];
-    const int npass = 2;
-    for (int pass = 0; pass < npass; ++pass) {
+    for (int pass = 0; pass < 2; ++pass) {
       double sd[32];
 #pragma unroll
       for (int a = 0; a < 32; ++a) sd[a] = 0.0;
-      for (int r = t; r < rows; r += 64) {
-        const double xb = X[r * ld + b];
+      for (int r = t; r < rows; r += T) {
+        const double xb = X[(int64_t)r * ld + b];
 #pragma unroll
         for (int a = 0; a < 32; ++a)
-          if (a < b) sd[a] += X[r * ld + a] * xb;
+          if (a < b) sd[a] += X[(int64_t)r * ld + a] * xb;
       }
-#pragma unroll
-      for (int a = 0; a < 32; ++a)
-        if (a < b) sd[a] = wave_sum(sd[a]);
-      for (int r = t; r < rows; r += 64) {
-        double acc = X[r * ld + b];
+      team_sums(sd, b);
+      for (int r = t; r < rows; r += T) {
+        double acc = X[(int64_t)r * ld + b];
 #pragma unroll
         for (int a = 0; a < 32; ++a)
-          if (a < b) acc -= sd[a] * X[r * ld + a];
-        X[r * ld + b] = acc;
+          if (a < b) acc -= sd[a] * X[(int64_t)r * ld + a];
+        X[(int64_t)r * ld + b] = acc;
       }
       if (t == 0) {
 #pragma unroll
@@ -215,55 +239,26 @@ __device__ __forceinline__ void cgs2_qr_wave(double* X, int rows, int ld, int bw
           if (a < b) R[a * bw + b] += sd[a];
       }
     }
-    double s1 = 0.0;
-    for (int r = t; r < rows; r += 64) s1 += X[r * ld + b] * X[r * ld + b];
-    const double nr = sqrt(wave_sum(s1));
-    if (nr > PE_DEP_TOL * n0 && nr > 1e-300) {
-      const double inv = 1.0 / nr;
-      for (int r = t; r < rows; r += 64) X[r * ld + b] *= inv;
-      if (t == 0) R[b * bw + b] = nr;
-    } else {
-      if (t == 0) R[b * bw + b] = 0.0;
-      for (int r = t; r < rows; r += 64)
-        X[r * ld + b] = (stack > 0 && (r % stack) != b) ? 0.0 : hash_unit(seed + (uint64_t)r, (uint64_t)b);
-      for (int pass = 0; pass < 3; ++pass) {
-        double sd[32];
-#pragma unroll
-        for (int a = 0; a < 32; ++a) sd[a] = 0.0;
-        for (int r = t; r < rows; r += 64) {
-          const double xb = X[r * ld + b];
-#pragma unroll
-          for (int a = 0; a < 32; ++a)
-            if (a < b) sd[a] += X[r * ld + a] * xb;
-        }
-#pragma unroll
-        for (int a = 0; a < 32; ++a)
-          if (a < b) sd[a] = wave_sum(sd[a]);
-        for (int r = t; r < rows; r += 64) {
-          double acc = X[r * ld + b];
-#pragma unroll
-          for (int a = 0; a < 32; ++a)
-            if (a < b) acc -= sd[a] * X[r * ld + a];
-          X[r * ld + b] = acc;
-        }
-      }
-      double s2 = 0.0;
-      for (int r = t; r < rows; r += 64) s2 += X[r * ld + b] * X[r * ld + b];
-      const double n2 = sqrt(wave_sum(s2));
-      const double inv = n2 > 0.0 ? 1.0 / n2 : 0.0;
-      for (int r = t; r < rows; r += 64) X[r * ld + b] *= inv;
-    }
+    double s1[32];
+    s1[0] = 0.0;
+    for (int r = t; r < rows; r += T) s1[0] += X[(int64_t)r * ld + b] * X[(int64_t)r * ld + b];
+    team_sums(s1, 1);
+    const double nr = sqrt(s1[0]);
+    const bool dep = !(nr > PE_DEP_TOL * ref[b] && nr > 1e-300);
+    const double inv = dep ? 0.0 : 1.0 / nr;
+    for (int r = t; r < rows; r += T) X[(int64_t)r * ld + b] *= inv;
+    if (t == 0) R[b * bw + b] = dep ? 0.0 : nr;
   }
 }
 
 // Register-resident CGS2 QR of a rows x bw array (LDS, leading dimension ld) by a team
 // of NW waves (NW = 1: no barriers; NW > 1: the whole workgroup, barriers inside).
 // Thread t of the team keeps rows t + 64 NW q, q < RPL, in registers; column loops are
-// unrolled to BWM >= bw so register indices are compile-time constants.  Dependence
-// test and replacement as in mgs2_qr.  `red` is LDS scratch of NW * BWM doubles.
+// unrolled to BWM >= bw so register indices are compile-time constants.  Dependent
+// columns are deflated as in cgs2_qr_team.  `red` is LDS scratch of NW * BWM doubles.
 template <int BWM, int RPL, int NW>
 __device__ __forceinline__ void cgs2_team(const double* Xi, int ldi, double* X, int ld, int rows, int bw, double* R,
-                                          uint64_t seed, const double* ref, int stack, double* red) {
+                                          const double* ref, double* red) {
   const int t = (NW == 1) ? (int)(threadIdx.x & 63) : (int)threadIdx.x;
   const int w = t >> 6;
   constexpr int T = 64 * NW;
@@ -337,42 +332,11 @@ __device__ __forceinline__ void cgs2_team(const double* Xi, int ldi, double* X, 
         }
       }
       const double nr = sqrt(nsq > s2sum ? nsq - s2sum : 0.0);
-      if (nr > PE_DEP_TOL * n0 && nr > 1e-300) {
-        const double inv = 1.0 / nr;
+      const bool dep = !(nr > PE_DEP_TOL * n0 && nr > 1e-300);
+      const double inv = dep ? 0.0 : 1.0 / nr;
 #pragma unroll
-        for (int q = 0; q < RPL; ++q) xr[q][b] *= inv;
-        if (t == 0) R[b * bw + b] = nr;
-      } else {
-        if (t == 0) R[b * bw + b] = 0.0;
-#pragma unroll
-        for (int q = 0; q < RPL; ++q) {
-          const int r = t + T * q;
-          xr[q][b] = (r >= rows || (stack > 0 && (r % stack) != b)) ? 0.0 : hash_unit(seed + (uint64_t)r, (uint64_t)b);
-        }
-#pragma unroll
-        for (int pass = 0; pass < 3; ++pass) {
-          double sd[BWM];
-#pragma unroll
-          for (int a = 0; a < BWM; ++a) sd[a] = 0.0;
-#pragma unroll
-          for (int q = 0; q < RPL; ++q)
-#pragma unroll
-            for (int a = 0; a < b; ++a) sd[a] += xr[q][a] * xr[q][b];
-          team_sums(sd, b);
-#pragma unroll
-          for (int q = 0; q < RPL; ++q)
-#pragma unroll
-            for (int a = 0; a < b; ++a) xr[q][b] -= sd[a] * xr[q][a];
-        }
-        double m2[BWM];
-        m2[0] = 0.0;
-#pragma unroll
-        for (int q = 0; q < RPL; ++q) m2[0] += xr[q][b] * xr[q][b];
-        team_sums(m2, 1);
-        const double inv = m2[0] > 0.0 ? 1.0 / sqrt(m2[0]) : 0.0;
-#pragma unroll
-        for (int q = 0; q < RPL; ++q) xr[q][b] *= inv;
-      }
+      for (int q = 0; q < RPL; ++q) xr[q][b] *= inv;
+      if (t == 0) R[b * bw + b] = dep ? 0.0 : nr;
     }
   }
 #pragma unroll
@@ -389,17 +353,17 @@ __device__ __forceinline__ void cgs2_team(const double* Xi, int ldi, double* X, 
 // Xi (ld ldi) is read once, the Q factor written to X (ld ld), which may alias Xi
 template <int NW>
 __device__ __forceinline__ bool cgs2_dispatch(const double* Xi, int ldi, double* X, int ld, int rows, int bw, double* R,
-                                              uint64_t seed, const double* ref, int stack, double* red) {
+                                              const double* ref, double* red) {
   const int rpl = (rows + 64 * NW - 1) / (64 * NW);
   if (bw <= 8) {
-    if (rpl <= 1) { cgs2_team<8, 1, NW>(Xi, ldi, X, ld, rows, bw, R, seed, ref, stack, red); return true; }
-    if (rpl <= 2) { cgs2_team<8, 2, NW>(Xi, ldi, X, ld, rows, bw, R, seed, ref, stack, red); return true; }
-    if (rpl <= 4) { cgs2_team<8, 4, NW>(Xi, ldi, X, ld, rows, bw, R, seed, ref, stack, red); return true; }
+    if (rpl <= 1) { cgs2_team<8, 1, NW>(Xi, ldi, X, ld, rows, bw, R, ref, red); return true; }
+    if (rpl <= 2) { cgs2_team<8, 2, NW>(Xi, ldi, X, ld, rows, bw, R, ref, red); return true; }
+    if (rpl <= 4) { cgs2_team<8, 4, NW>(Xi, ldi, X, ld, rows, bw, R, ref, red); return true; }
   } else if (bw <= 16) {
-    if (rpl <= 1) { cgs2_team<16, 1, NW>(Xi, ldi, X, ld, rows, bw, R, seed, ref, stack, red); return true; }
-    if (rpl <= 2) { cgs2_team<16, 2, NW>(Xi, ldi, X, ld, rows, bw, R, seed, ref, stack, red); return true; }
+    if (rpl <= 1) { cgs2_team<16, 1, NW>(Xi, ldi, X, ld, rows, bw, R, ref, red); return true; }
+    if (rpl <= 2) { cgs2_team<16, 2, NW>(Xi, ldi, X, ld, rows, bw, R, ref, red); return true; }
   }
-  return false;  // wider blocks use the LDS-resident cgs2_qr_wave
+  return false;  // wider blocks or more rows: cgs2_qr_team on an LDS or global array
 }
 
 // ------------------------------------------------------------------------------------
@@ -880,7 +844,7 @@ __global__ __launch_bounds__(256) void k_block_update(const ProbDev* __restrict_
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const bool reg_comb = combine_in_registers(bw, p.Cu);
   extern __shared__ double smem[];
-  const int64_t xs_cap = (int64_t)ld * (reg_comb || rmax > p.Cu * bw ? rmax : p.Cu * bw);
+  const int64_t xs_cap = (int64_t)ld * (reg_comb || p.comb_global || rmax > p.Cu * bw ? rmax : p.Cu * bw);
   double* X = smem;                               // xs_cap
   double* Sb = X + xs_cap;                        // kSb
   double* Rl = Sb + kSb;                          // bw^2
@@ -943,16 +907,14 @@ __global__ __launch_bounds__(256) void k_block_update(const ProbDev* __restrict_
   // 3. local QR of the chunk (wave 0)
   for (int o = t; o < nout; o += 256) Rl[o] = 0.0;
   __syncthreads();
-  const uint64_t seed = ((uint64_t)(j + 1) * 1000003ull + (uint64_t)pass * 7919ull + (uint64_t)mode * 104729ull) *
-                            0x100000001B3ull + (uint64_t)r0;
   // Q of the chunk goes straight from registers to Qloc (row-major, ld bw)
   double* Qloc = (pass == 0 ? p.Qloc1 : p.Qloc2) + r0 * bw;
   __shared__ int reg_qr;
   if (t == 0) reg_qr = 1;
   __syncthreads();
   if (w == 0) {
-    if (!cgs2_dispatch<1>(X, ld, Qloc, bw, rows, bw, Rl, seed, Rn, 0, nullptr)) {
-      cgs2_qr_wave(X, rows, ld, bw, Rl, seed, Rn, 0);
+    if (!cgs2_dispatch<1>(X, ld, Qloc, bw, rows, bw, Rl, Rn, nullptr)) {
+      cgs2_qr_team<1>(X, rows, ld, bw, Rl, Rn, nullptr);
       if (lane == 0) reg_qr = 0;
     }
   }
@@ -993,19 +955,25 @@ __global__ __launch_bounds__(256) void k_block_update(const ProbDev* __restrict_
     Rn[b] = sqrt(s0);
   }
   __syncthreads();
-  const uint64_t cseed = seed ^ 0x5bd1e995ull;
   if (reg_comb) {
     // stacked chunk factors read straight from global memory into registers
-    cgs2_dispatch<4>(p.Rloc, bw, Qs, bw, srows, bw, Rl, cseed, Rn, bw, Qsl);
+    cgs2_dispatch<4>(p.Rloc, bw, Qs, bw, srows, bw, Rl, Rn, Qsl);
     __syncthreads();
-  } else {
+  } else if (!p.comb_global) {
     bulk_load(
         (int64_t)srows * bw, [&](int64_t e) -> double { return p.Rloc[e]; },
         [&](int64_t e, double v) { X[(e / bw) * ld + (e % bw)] = v; });
     __syncthreads();
-    if (w == 0) cgs2_qr_wave(X, srows, ld, bw, Rl, cseed, Rn, bw);
+    cgs2_qr_team<4>(X, srows, ld, bw, Rl, Rn, Qsl);
     __syncthreads();
     for (int e = t; e < srows * bw; e += 256) Qs[e] = X[(e / bw) * ld + (e % bw)];
+  } else {
+    // stack too tall for LDS: QR in place in Qs (global); each row is copied and then
+    // worked on by the one thread that owns it, so no fence is needed inside
+    for (int r = t; r < srows; r += 256)
+      for (int b = 0; b < bw; ++b) Qs[(int64_t)r * bw + b] = p.Rloc[(int64_t)r * bw + b];
+    cgs2_qr_team<4>(Qs, srows, bw, bw, Rl, Rn, Qsl);
+    __syncthreads();
   }
   double* Rout = p.Rf + (mode == MODE_INIT ? 2 : pass) * nout;
   for (int o = t; o < nout; o += 256) Rout[o] = Rl[o];
@@ -1021,7 +989,7 @@ __global__ __launch_bounds__(256) void k_block_update(const ProbDev* __restrict_
       for (int b = 0; b < bw; ++b) {
         double c2 = 0.0;
         for (int a = 0; a <= b; ++a) c2 += Rl[a * bw + b] * Rl[a * bw + b];
-        const double r = Rn[b] > 0.0 ? sqrt(c2) / Rn[b] : 0.0;
+        const double r = Rn[b] > 0.0 ? sqrt(c2) / Rn[b] : 1.0;  // a zero column loses nothing
         mn = r < mn ? r : mn;
       }
       skip = mn >= kReorthSkip ? 1 : 0;

@@ -101,8 +101,13 @@ constexpr int kMaxTrials = 6;
 constexpr double kSigmaFloor = 1e-12;  // relative singular values treated as zero
 constexpr int kRowsU = 64;
 
+// bound on the re-expansion growth of the Chebyshev source basis over one step
+constexpr double kGrowthCap = 100.0;
+// restart cycles per march before it gives up (flagged, unreached outputs NaN)
+constexpr int kCycleCap = 100000;
+
 // PARAEXP_TRACE=1 prints one line per restart trial to stderr;
-// PARAEXP_MAX_CYCLES=k stops a march after k cycles (outputs left unwritten, flagged).
+// PARAEXP_MAX_CYCLES=k lowers the cycle cap to k.
 int env_int(const char* name, int dflt) {
   const char* v = std::getenv(name);
   return v ? std::atoi(v) : dflt;
@@ -152,21 +157,37 @@ size_t update_smem(const ProbDev& d);
 size_t proj_smem(const ProbDev& d);
 int rows_p_for(int bw) { return bw <= 8 ? 128 : (bw <= 16 ? 64 : 32); }
 
-int rows_u_for(int64_t n, int bw) {
-  int ru = kRowsU;
-  while (true) {
-    ProbDev d{};
-    d.bw = bw;
-    d.rows_u = ru;
-    d.Cu = (int)std::max<int64_t>(1, n / ru);
-    if (update_smem(d) <= (size_t)pe::kUpdateLdsMax || ru >= 4096) return ru;
-    ru *= 2;
+// Rows per update chunk: the smallest power of two from kRowsU up for which the update
+// kernel (chunk staging plus a register- or LDS-resident TSQR combine) fits in LDS; when
+// none does (wide blocks on long grids), the largest chunk whose staging fits, with the
+// combine working on the stacked chunk factors in global memory.
+void choose_update_chunks(int64_t n, int bw, int& rows_u, int& comb_global) {
+  for (int glob = 0; glob < 2; ++glob) {
+    int best = 0;
+    for (int ru = kRowsU; ru <= 4096; ru *= 2) {
+      ProbDev d{};
+      d.bw = bw;
+      d.rows_u = ru;
+      d.Cu = (int)std::max<int64_t>(1, n / ru);
+      d.comb_global = glob;
+      if (update_smem(d) <= (size_t)pe::kUpdateLdsMax) {
+        best = ru;
+        if (!glob) break;
+      }
+    }
+    if (best) {
+      rows_u = best;
+      comb_global = glob;
+      return;
+    }
   }
+  rows_u = kRowsU;  // nothing fits: geometry_fits reports it
+  comb_global = 1;
 }
 
 void set_geometry(ProbDev& d, int64_t n, int bw) {
   d.bw = bw;
-  d.rows_u = rows_u_for(n, bw);
+  choose_update_chunks(n, bw, d.rows_u, d.comb_global);
   d.rows_u_log2 = 0;
   while ((1 << d.rows_u_log2) < d.rows_u) ++d.rows_u_log2;
   d.Cu = (int)std::max<int64_t>(1, n / d.rows_u);
@@ -187,7 +208,7 @@ size_t update_smem(const ProbDev& d) {
   const size_t ld = d.bw + 1;
   const size_t rmax = 2 * (size_t)d.rows_u;
   const bool reg = pe::combine_in_registers(d.bw, d.Cu);
-  const size_t xs = (reg || rmax > (size_t)d.Cu * d.bw) ? rmax * ld : (size_t)d.Cu * d.bw * ld;
+  const size_t xs = (reg || d.comb_global || rmax > (size_t)d.Cu * d.bw) ? rmax * ld : (size_t)d.Cu * d.bw * ld;
   const size_t bw2 = (size_t)d.bw * d.bw;
   return sizeof(double) * (xs + pe::kSb + bw2 + d.bw + (rmax + 2) * d.bw + std::max<size_t>(bw2, 128)) + 64;
 }
@@ -714,6 +735,14 @@ pe_status march_batch(pe_ctx* ctx, const pe_problem* probs, const int* idx, int 
       h.target = h.src ? std::min(p.t_out[h.k], p.t1) : p.t_out[h.k];
       const double rem = h.target - h.tau;
       h.dtry = std::min(rem, h.dgrow * h.dlast);
+      if (h.src && ql[ii] > 0) {
+        // The exponential of the Chebyshev generator over a step re-expands the basis at
+        // a shift of c = 2 step / (t1 - t0) in x, with coefficients growing like
+        // (1 + sqrt(2c))^q; rounding in the projected exponential grows with them.  Steps
+        // are capped so that the growth stays below kGrowthCap.
+        const double g = std::pow(kGrowthCap, 1.0 / ql[ii]) - 1.0;
+        h.dtry = std::min(h.dtry, 0.25 * g * g * (p.t1 - p.t0));
+      }
       h.bw = h.src ? (h.xzero ? m : m + 1) : 1;
       d.m = h.src ? m : 0;
       d.with_x = h.xzero ? 0 : 1;
@@ -748,9 +777,18 @@ pe_status march_batch(pe_ctx* ctx, const pe_problem* probs, const int* idx, int 
       }
     }
     if (nact == 0) break;
-    if (++guard > 10000000) return pe_fail(ctx, PE_ERR_DEVICE, "march did not terminate");
-    if (max_cycles > 0 && guard > max_cycles) {
-      for (int ii = 0; ii < nb_prob; ++ii) hs[ii].flags |= PE_FLAG_NOT_CONVERGED;
+    if (++guard > (max_cycles > 0 ? max_cycles : kCycleCap)) {
+      // out of cycles (a tolerance below the attainable accuracy crawls at the minimum
+      // step): flag, and mark the outputs not reached with NaN
+      for (int ii = 0; ii < nb_prob; ++ii) {
+        HostState& h = hs[ii];
+        const pe_problem& p = probs[idx[ii]];
+        if (h.done) continue;
+        h.flags |= PE_FLAG_NOT_CONVERGED;
+        for (; h.k < p.n_out; ++h.k)
+          pe::launch_fill(p.out + (int64_t)h.k * p.ldOut, p.op.n, 1, p.op.n, std::nan(""), st);
+        h.done = true;
+      }
       break;
     }
     HCK(hipMemcpyAsync(dd, hd.data(), sizeof(ProbDev) * nb_prob, hipMemcpyHostToDevice, st));
@@ -852,6 +890,8 @@ pe_status march_batch(pe_ctx* ctx, const pe_problem* probs, const int* idx, int 
           h.flags |= PE_FLAG_NOT_CONVERGED;
         }
         if (best >= 0) {
+          // a residual block that vanished exactly: the Krylov space is invariant
+          if (ho[2 * ns] == 0.0 && ho[2 * ns + 1] > 0.0) h.flags |= PE_FLAG_BREAKDOWN;
           // local order p of the estimate, err ~ delta^p, from two squaring levels
           // (their steps differ by 2); only where both are well above rounding
           const int lo = best < ns ? best : best - 1;

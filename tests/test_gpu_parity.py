@@ -199,3 +199,55 @@ def test_c2_full_size_mixed(ctx):
     outs, reps = ctx.solve_batch([p], pe.PE_MIXED)
     assert rel(gpu_out(outs[0]), ref) < MIXED_TOL, reps[0]
 
+
+
+# ------------------------------------------------------------------ edge cases
+def test_empty_batch_and_no_outputs(ctx):
+    outs, reps = ctx.solve_batch([])
+    assert outs == [] and reps == []
+    p = synth.random_ade_problem(31, 64, n_out=2)
+    p.t_out = np.zeros(0)
+    outs, reps = ctx.solve_batch([p])
+    assert tuple(outs[0].shape)[0] == 0
+
+
+def _many_mode_problem(n, rank_max, krylov_steps, s=48):
+    # a source of rank > 31 (40 modes in x, each with its own time frequency)
+    rng = np.random.default_rng(7)
+    x = synth.grid(n)
+    ts = synth.chebyshev_lobatto(0.0, 0.1, s)
+    G = sum(np.outer(np.sin(2 * np.pi * k * x + rng.uniform(0, 6.3)), np.cos(k * ts * 20.0 + k))
+            for k in range(1, 41))
+    return synth.Problem(n=n, coeffs=synth.ade_coeffs(n, 1.0, 1e-2), u0=np.sin(2 * np.pi * x), t0=0.0, t1=0.1,
+                         t_samples=ts, G=G, t_out=np.array([0.05, 0.1]), shift=True, krylov_steps=krylov_steps,
+                         rank_max=rank_max, q_max=32, tol=1e-12, svd_tol=1e-14, fit_tol=1e-13)
+
+
+@pytest.mark.parametrize("n,rank_max,krylov_steps", [(160, 31, 6), (160, 15, 12), (1024, 31, 6)])
+def test_wide_blocks_rank_cap_and_exhausted_space(ctx, n, rank_max, krylov_steps):
+    # block width up to 32 (rank capped at rank_max, fit order capped at q_max = 32);
+    # n = 160: (krylov_steps + 1) blocks exceed the dimension, so late blocks are fully
+    # dependent and deflate; n = 1024 at width 32 combines the chunk factors in global
+    # memory; q = 32 makes long steps ill-conditioned, so the step cap must hold
+    p = _many_mode_problem(n, rank_max, krylov_steps)
+    mdl = oracle.window_model(p)
+    ref, _ = oracle.solve_window(p, "dense" if n <= 256 else "spectral", model=mdl)
+    outs, reps = ctx.solve_batch([p])
+    assert reps[0]["rank"] == mdl["m"] == rank_max
+    assert reps[0]["flags"] & 12 == mdl["flags"] == 12  # rank and fit order both capped
+    assert not reps[0]["flags"] & 1, reps[0]
+    assert rel(gpu_out(outs[0]), ref) < FP64_TOL, reps[0]
+
+
+@pytest.mark.parametrize("n,s", [(4, 2), (5, 3)])
+def test_smallest_grids_and_sample_counts(ctx, n, s):
+    x = synth.grid(n)
+    ts = synth.chebyshev_lobatto(0.0, 0.2, s)
+    G = np.outer(np.cos(2 * np.pi * x), 1.0 + ts)
+    p = synth.Problem(n=n, coeffs=synth.ade_coeffs(n, 1.0, 1e-2), u0=1.0 + np.sin(2 * np.pi * x), t0=0.0,
+                      t1=0.2, t_samples=ts, G=G, t_out=np.array([0.1, 0.2, 0.3]), shift=True, krylov_steps=3,
+                      rank_max=2, q_max=4, tol=1e-12, svd_tol=1e-13, fit_tol=1e-13)
+    ref, _ = oracle.solve_window(p, "dense")
+    outs, reps = ctx.solve_batch([p])
+    assert rel(gpu_out(outs[0]), ref) < FP64_TOL, reps[0]
+    assert reps[0]["flags"] & 2, reps[0]  # the space is exhausted: PE_FLAG_BREAKDOWN
