@@ -251,7 +251,8 @@ __device__ __forceinline__ void cgs2_qr_team(double* X, int rows, int ld, int bw
   }
 }
 
-// Register-resident CGS2 QR of a rows x bw array (LDS, leading dimension ld) by a team
+// Register-resident Gram-Schmidt QR (classical, second pass where needed) of a rows x bw
+// array (LDS, leading dimension ld) by a team
 // of NW waves (NW = 1: no barriers; NW > 1: the whole workgroup, barriers inside).
 // Thread t of the team keeps rows t + 64 NW q, q < RPL, in registers; column loops are
 // unrolled to BWM >= bw so register indices are compile-time constants.  Dependent
@@ -299,25 +300,23 @@ __device__ __forceinline__ void cgs2_team(const double* Xi, int ldi, double* X, 
   for (int b = 0; b < BWM; ++b) {
     if (b < bw) {
       const double n0 = ref[b];
-      // The second pass reduces the squared column norm together with its projections;
-      // the norm after it follows by Pythagoras (the second-pass coefficients are at
-      // rounding level), so a column costs two team reductions.
-      double nsq = 0.0, s2sum = 0.0;
-#pragma unroll
-      for (int pass = 0; pass < 2; ++pass) {
-        if (pass == 0 && b == 0) continue;
+      // First pass: the projections on the previous columns and the squared norm are
+      // reduced together; the norm after the pass follows by Pythagoras.  A second pass
+      // runs only when the first removed more than half of the squared norm ("twice is
+      // enough", Kahan and Parlett): otherwise the remainder is already orthogonal to
+      // working precision.  A column thus costs one team reduction, or two.
+      double nsq, s2sum = 0.0;
+      {
         double sd[BWM];
 #pragma unroll
         for (int a = 0; a < BWM; ++a) sd[a] = 0.0;
 #pragma unroll
-        for (int q = 0; q < RPL; ++q)
+        for (int q = 0; q < RPL; ++q) {
 #pragma unroll
           for (int a = 0; a < b; ++a) sd[a] += xr[q][a] * xr[q][b];
-        if (pass == 1) {
-#pragma unroll
-          for (int q = 0; q < RPL; ++q) sd[b] += xr[q][b] * xr[q][b];
+          sd[b] += xr[q][b] * xr[q][b];
         }
-        team_sums(sd, pass == 1 ? b + 1 : b);
+        team_sums(sd, b + 1);
 #pragma unroll
         for (int q = 0; q < RPL; ++q)
 #pragma unroll
@@ -325,11 +324,32 @@ __device__ __forceinline__ void cgs2_team(const double* Xi, int ldi, double* X, 
         if (t == 0)
 #pragma unroll
           for (int a = 0; a < b; ++a) R[a * bw + b] += sd[a];
-        if (pass == 1) {
-          nsq = sd[b];
+        nsq = sd[b];
 #pragma unroll
-          for (int a = 0; a < b; ++a) s2sum += sd[a] * sd[a];
+        for (int a = 0; a < b; ++a) s2sum += sd[a] * sd[a];
+      }
+      if (b > 0 && nsq - s2sum < 0.5 * nsq) {
+        double sd[BWM];
+#pragma unroll
+        for (int a = 0; a < BWM; ++a) sd[a] = 0.0;
+#pragma unroll
+        for (int q = 0; q < RPL; ++q) {
+#pragma unroll
+          for (int a = 0; a < b; ++a) sd[a] += xr[q][a] * xr[q][b];
+          sd[b] += xr[q][b] * xr[q][b];
         }
+        team_sums(sd, b + 1);
+#pragma unroll
+        for (int q = 0; q < RPL; ++q)
+#pragma unroll
+          for (int a = 0; a < b; ++a) xr[q][b] -= sd[a] * xr[q][a];
+        if (t == 0)
+#pragma unroll
+          for (int a = 0; a < b; ++a) R[a * bw + b] += sd[a];
+        nsq = sd[b];
+        s2sum = 0.0;
+#pragma unroll
+        for (int a = 0; a < b; ++a) s2sum += sd[a] * sd[a];
       }
       const double nr = sqrt(nsq > s2sum ? nsq - s2sum : 0.0);
       const bool dep = !(nr > PE_DEP_TOL * n0 && nr > 1e-300);
@@ -874,13 +894,7 @@ __global__ __launch_bounds__(256) void k_block_update(const ProbDev* __restrict_
         for (int k = 0; k < bw; ++k) v += S2[(int64_t)i * nout + a * bw + k] * R1[k * bw + b];
         p.H[(int64_t)(i * bw + a) + p.ldH * (int64_t)(j * bw + b)] = v;
       }
-    // rows below the subdiagonal block stay zero
-    const int64_t r_lo = (int64_t)(nb + 1) * bw;
-    const int64_t zcnt = (p.ldH - r_lo) * bw;
-    for (int64_t e = (int64_t)u * 256 + t; e < zcnt; e += (int64_t)p.Cu * 256) {
-      const int64_t rr = r_lo + e / bw, b = e % bw;
-      p.H[rr + p.ldH * (int64_t)(j * bw + b)] = 0.0;
-    }
+    // blocks below the subdiagonal block are never written: readers take them as zero
   }
   // 1. input block of this chunk
   form_block<TS>(p, mode, pass, j, r0, rows, X, ld, Qrow, Qsl);
@@ -984,16 +998,18 @@ __global__ __launch_bounds__(256) void k_block_update(const ProbDev* __restrict_
     // the basis to ~eps / kReorthSkip and the second pass is skipped:
     // V_{j+1} = Q1, H column = S1 and subdiagonal block Rf1 (W = V S1 + Q1 Rf1 exactly)
     __shared__ int skip;
-    if (t == 0) {
-      double mn = 1e300;
-      for (int b = 0; b < bw; ++b) {
+    if (w == 0) {
+      bool ok = true;  // lane b: column b kept enough (a zero column loses nothing)
+      if (lane < bw) {
         double c2 = 0.0;
-        for (int a = 0; a <= b; ++a) c2 += Rl[a * bw + b] * Rl[a * bw + b];
-        const double r = Rn[b] > 0.0 ? sqrt(c2) / Rn[b] : 1.0;  // a zero column loses nothing
-        mn = r < mn ? r : mn;
+        for (int a = 0; a <= lane; ++a) c2 += Rl[a * bw + lane] * Rl[a * bw + lane];
+        ok = !(Rn[lane] > 0.0) || sqrt(c2) >= kReorthSkip * Rn[lane];
       }
-      skip = mn >= kReorthSkip ? 1 : 0;
-      p.cnt[2 * p.nbmax + 1] = (unsigned)skip;
+      const bool all_ok = __all(ok);
+      if (lane == 0) {
+        skip = all_ok ? 1 : 0;
+        p.cnt[2 * p.nbmax + 1] = (unsigned)skip;
+      }
     }
     __syncthreads();
     if (skip) {
@@ -1004,9 +1020,6 @@ __global__ __launch_bounds__(256) void k_block_update(const ProbDev* __restrict_
       }
       for (int o = t; o < nout; o += 256)
         p.H[(int64_t)(nb * bw + o / bw) + p.ldH * (int64_t)(j * bw + o % bw)] = Rl[o];
-      const int64_t r_lo = (int64_t)(nb + 1) * bw;
-      for (int64_t e = t; e < (p.ldH - r_lo) * bw; e += 256)
-        p.H[r_lo + e / bw + p.ldH * (int64_t)(j * bw + e % bw)] = 0.0;
     }
   }
   if (hcol) {
@@ -1096,7 +1109,8 @@ __global__ void k_build_aug(const ExpmDev* __restrict__ E) {
     const int r = (int)(idx % N), c = (int)(idx / N);
     double v = 0.0;
     if (r < lbw && c < lbw) {
-      v = e.H[(int64_t)r + e.ldH * c];
+      // block upper Hessenberg: blocks below the subdiagonal are zero (never written)
+      if (r / bw <= c / bw + 1) v = e.H[(int64_t)r + e.ldH * c];
     } else if (r < bw && c >= lbw) {
       const int k = c - lbw;
       for (int cc = 0; cc < e.m; ++cc) v += e.R0[r * bw + cc] * e.Pi[cc + (int64_t)e.ldPi * k];
