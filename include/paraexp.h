@@ -211,7 +211,8 @@ pe_status pe_wr_burgers(pe_ctx* ctx, const pe_wr_problem* wr, pe_report* reports
  * + TSQR combine) or "block_proj" (block projections) -- the first orthogonalisation
  * pass of every block Arnoldi step, which always runs in full -- or "stencil"
  * (pe_stencil_apply), or NULL to switch timing off.  Resets the accumulators.  Timing
- * adds two event records per launch. */
+ * adds two event records per timed launch; within a march only every 8th restart cycle
+ * is timed (all of its block steps), which keeps the markers' cost small. */
 pe_status pe_profile_enable(pe_ctx* ctx, const char* family);
 /* Read and reset the accumulators: timed launches, their summed duration (ms), and the
  * algorithmic traffic (bytes, each datum read or written once per launch) and flops of

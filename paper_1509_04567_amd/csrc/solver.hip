@@ -43,6 +43,7 @@ struct pe_ctx {
   size_t ev_used = 0;
   int64_t prof_launches = 0;
   double prof_ms = 0.0, prof_bytes = 0.0, prof_flops = 0.0;
+  bool prof_sample = true;  // false: the current restart cycle is not timed
 };
 
 static pe_status pe_fail(pe_ctx* ctx, pe_status st, const std::string& msg, hipError_t e = hipSuccess) {
@@ -63,7 +64,7 @@ namespace {
 
 // ---- kernel timing with HIP events on the launch stream ----------------------------
 int prof_begin(pe_ctx* ctx, const char* family, hipStream_t st) {
-  if (ctx->prof_name.empty() || ctx->prof_name != family) return -1;
+  if (!ctx->prof_sample || ctx->prof_name.empty() || ctx->prof_name != family) return -1;
   while (ctx->ev.size() < ctx->ev_used + 2) {
     hipEvent_t e;
     if (hipEventCreate(&e) != hipSuccess) return -1;
@@ -103,6 +104,8 @@ constexpr int kRowsU = 64;
 
 // bound on the re-expansion growth of the Chebyshev source basis over one step
 constexpr double kGrowthCap = 100.0;
+// restart cycles of a march between two timed ones (pe_profile_enable)
+constexpr int kProfEvery = 8;
 // restart cycles per march before it gives up (flagged, unreached outputs NaN)
 constexpr int kCycleCap = 100000;
 
@@ -596,6 +599,10 @@ pe_status march_batch(pe_ctx* ctx, const pe_problem* probs, const int* idx, int 
                       const double* const* Pil, const int* ldPil, const int* ml, const int* ql, pe_report* reports,
                       hipStream_t st) {
   if (nb_prob == 0) return PE_OK;
+  struct SampleReset {  // launches outside a march are always timed
+    pe_ctx* c;
+    ~SampleReset() { c->prof_sample = true; }
+  } sample_reset{ctx};
   const bool mixed = probs[idx[0]].prec == PE_MIXED;
   int qmax_all = 1;
   for (int ii = 0; ii < nb_prob; ++ii) qmax_all = std::max(qmax_all, ql[ii]);
@@ -777,6 +784,9 @@ pe_status march_batch(pe_ctx* ctx, const pe_problem* probs, const int* idx, int 
       }
     }
     if (nact == 0) break;
+    // event markers cost GPU time, so a march times every kProfEvery-th restart cycle
+    // (all of its block steps, so the sample spans the same step mix)
+    ctx->prof_sample = (guard % kProfEvery) == 0;
     if (++guard > (max_cycles > 0 ? max_cycles : kCycleCap)) {
       // out of cycles (a tolerance below the attainable accuracy crawls at the minimum
       // step): flag, and mark the outputs not reached with NaN
