@@ -164,6 +164,15 @@ pe_status pe_expaction_batch(pe_ctx* ctx, const pe_problem* probs, const double*
 pe_status pe_solve_batch(pe_ctx* ctx, const pe_problem* probs, int32_t nprob,
                          pe_report* reports, void* stream);
 
+/* Device memory that pe_solve_batch on these problems may need, in bytes: the largest
+ * context workspace (compression of any one problem, or the batched march with every
+ * problem at rank rank_max and min(q_max, s) polynomial terms -- the most its
+ * compression can give) plus the compressed sources it allocates for the call.  Only
+ * the size fields are read (n, s, krylov_steps, rank_max, q_max, prec); data pointers
+ * may be NULL.  Pure host arithmetic: ctx may be NULL, and no device is touched.  The
+ * workspace persists in ctx and grows on demand (released by pe_destroy). */
+pe_status pe_workspace_query(pe_ctx* ctx, const pe_problem* probs, int32_t nprob, size_t* bytes);
+
 /* Step S8 (eq. 2.9): u[:, k] = u0 + sum_{j<P} v_j[:, k], summed in window order.
  * u0 device n; v host array of P device pointers, each n x n_out with ld ldv;
  * u device n x n_out with ld ldu (may alias none of the inputs). */

@@ -15,4 +15,5 @@ from .binding import (  # noqa: F401
     FLAG_BREAKDOWN,
     FLAG_RANK_CAPPED,
     FLAG_FIT_CAPPED,
+    workspace_query,
 )

@@ -34,8 +34,8 @@ FLAG_RANK_CAPPED = 4
 FLAG_FIT_CAPPED = 8
 
 EXPORTED = ["pe_create", "pe_destroy", "pe_last_error", "pe_version", "pe_stencil_apply", "pe_compress",
-            "pe_expaction_batch", "pe_solve_batch", "pe_superpose", "pe_wr_burgers", "pe_profile_enable",
-            "pe_profile_read"]
+            "pe_expaction_batch", "pe_solve_batch", "pe_workspace_query", "pe_superpose", "pe_wr_burgers",
+            "pe_profile_enable", "pe_profile_read"]
 
 
 class PeStencil(ctypes.Structure):
@@ -142,6 +142,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.pe_expaction_batch.argtypes = [vp, ctypes.POINTER(PeProblem), ctypes.POINTER(vp), ctypes.POINTER(vp),
                                        ctypes.POINTER(i32), ctypes.POINTER(i32), i32, ctypes.POINTER(PeReport), vp]
     lib.pe_solve_batch.argtypes = [vp, ctypes.POINTER(PeProblem), i32, ctypes.POINTER(PeReport), vp]
+    lib.pe_workspace_query.argtypes = [vp, ctypes.POINTER(PeProblem), i32, ctypes.POINTER(ctypes.c_size_t)]
     lib.pe_superpose.argtypes = [vp, vp, ctypes.POINTER(vp), i32, i64, i32, i64, vp, i64, vp]
     lib.pe_wr_burgers.argtypes = [vp, ctypes.POINTER(PeWrProblem), ctypes.POINTER(PeReport),
                                   ctypes.POINTER(ctypes.c_double), vp]
@@ -245,6 +246,29 @@ def make_problem(src, device, precision: int = PE_FP64, out=None) -> DeviceProbl
     return DeviceProblem(struct=st, out=out[:n_out], keep=keep)
 
 
+def workspace_query(problems: Sequence, precision: int = PE_FP64, ctx=None) -> int:
+    """pe_workspace_query: bytes of device memory pe_solve_batch may need for these
+    problems.  Only sizes are read; host arithmetic, so no GPU is needed."""
+    lib = load_library()
+    arr = (PeProblem * max(1, len(problems)))()
+    for i, p in enumerate(problems):
+        st = arr[i]
+        st.op = PeStencil(int(p.n), 0, None)
+        ts = getattr(p, "t_samples", None)
+        st.s = int(len(ts)) if ts is not None else int(getattr(p, "s", 0))
+        st.krylov_steps = int(p.krylov_steps)
+        st.rank_max = int(p.rank_max)
+        st.q_max = int(p.q_max)
+        st.prec = int(precision)
+    out = ctypes.c_size_t(0)
+    h = ctx.h if ctx is not None else None
+    status = lib.pe_workspace_query(h, arr, len(problems), ctypes.byref(out))
+    if status != PE_OK:
+        msg = lib.pe_last_error(h).decode() if h is not None else "pe_workspace_query failed"
+        raise PeError(status, msg)
+    return int(out.value)
+
+
 class Context:
     """One library context on a HIP device (workspace is cached across calls)."""
 
@@ -319,6 +343,9 @@ class Context:
         reps = (PeReport * len(dps))()
         self._check(self.lib.pe_solve_batch(self.h, arr, len(dps), reps, _stream_ptr()))
         return [d.out for d in dps], [r.as_dict() for r in reps]
+
+    def workspace_query(self, problems: Sequence, precision: int = PE_FP64) -> int:
+        return workspace_query(problems, precision, self)
 
     def prepare(self, problems: Sequence, precision: int = PE_FP64):
         """Stage a batch on the device once (for repeated solves, e.g. benchmarking)."""

@@ -44,6 +44,9 @@ struct pe_ctx {
   int64_t prof_launches = 0;
   double prof_ms = 0.0, prof_bytes = 0.0, prof_flops = 0.0;
   bool prof_sample = true;  // false: the current restart cycle is not timed
+  // workspace query: ensure_arena records the size and stops the call there
+  bool query = false;
+  size_t query_bytes = 0;
 };
 
 static pe_status pe_fail(pe_ctx* ctx, pe_status st, const std::string& msg, hipError_t e = hipSuccess) {
@@ -128,7 +131,15 @@ struct Carver {
   }
 };
 
+// status of a call stopped by a workspace query at its first allocation (never returned
+// through the ABI)
+constexpr pe_status kQueryStop = (pe_status)1;
+
 pe_status ensure_arena(pe_ctx* ctx, size_t bytes) {
+  if (ctx->query) {
+    ctx->query_bytes = std::max(ctx->query_bytes, bytes);
+    return kQueryStop;
+  }
   if (bytes <= ctx->arena_cap) return PE_OK;
   if (ctx->arena) {
     hipDeviceSynchronize();
@@ -1346,6 +1357,66 @@ pe_status pe_wr_burgers(pe_ctx* ctx, const pe_wr_problem* wr, pe_report* reports
   hipFree(base);
   if (res != PE_OK) return res;
   HCK(hipGetLastError());
+  return PE_OK;
+}
+
+pe_status pe_workspace_query(pe_ctx* ctx, const pe_problem* probs, int32_t nprob, size_t* bytes) {
+  pe_ctx local;  // host-only arithmetic: a null ctx is allowed
+  pe_ctx* c = ctx ? ctx : &local;
+  if (!bytes || nprob < 0 || (nprob > 0 && !probs)) return pe_fail(c, PE_ERR_ARG, "pe_workspace_query: bad arguments");
+  *bytes = 0;
+  struct QueryScope {
+    pe_ctx* c;
+    ~QueryScope() {
+      c->query = false;
+      c->query_bytes = 0;
+    }
+  } scope{c};
+  size_t arena = 0, src = 0;
+  std::vector<int> ml(nprob), ql(nprob);
+  for (int i = 0; i < nprob; ++i) {
+    const pe_problem& p = probs[i];
+    if (p.op.n < 4 || p.s < 1 || p.krylov_steps < 1 || p.krylov_steps > 512 || p.q_max < 1 || p.q_max > 64 ||
+        (p.prec != PE_FP64 && p.prec != PE_MIXED))
+      return pe_fail(c, PE_ERR_ARG, "pe_workspace_query: bad problem sizes");
+    if (p.rank_max < 0 || p.rank_max > 31) return pe_fail(c, PE_ERR_UNSUPPORTED, "rank_max must be in [0, 31]");
+    if (p.op.n < p.rank_max + 1) return pe_fail(c, PE_ERR_ARG, "n too small for rank_max");
+    // compression (S1-S4): its own arena layout
+    c->query = true;
+    c->query_bytes = 0;
+    CompressOut co;
+    pe_status s = compress_one(c, p, nullptr, p.op.n, nullptr, std::max(1, p.rank_max), co, nullptr);
+    if (s != kQueryStop) return s == PE_OK ? pe_fail(c, PE_ERR_DEVICE, "query did not stop") : s;
+    arena = std::max(arena, c->query_bytes);
+    // compressed sources, allocated per call (as in pe_solve_batch)
+    src = (src + 255) & ~(size_t)255;
+    src += sizeof(double) * (size_t)p.op.n * std::max(1, p.rank_max);
+    src = (src + 255) & ~(size_t)255;
+    src += sizeof(double) * (size_t)std::max(1, p.rank_max) * p.q_max;
+    // the march at the largest rank and polynomial order the problem allows
+    ml[i] = std::min(p.rank_max, p.s);
+    ql[i] = std::min(p.q_max, p.s);
+  }
+  for (int prec = 0; prec < 2; ++prec) {
+    std::vector<int> idx, m, q, ld;
+    for (int i = 0; i < nprob; ++i)
+      if ((int)probs[i].prec == prec) {
+        idx.push_back(i);
+        m.push_back(ml[i]);
+        q.push_back(ql[i]);
+        ld.push_back(std::max(1, probs[i].rank_max));
+      }
+    if (idx.empty()) continue;
+    std::vector<const double*> nul(idx.size(), nullptr);
+    std::vector<pe_report> rep(nprob);
+    c->query = true;
+    c->query_bytes = 0;
+    pe_status s = march_batch(c, probs, idx.data(), (int)idx.size(), nul.data(), nul.data(), ld.data(), m.data(),
+                              q.data(), rep.data(), nullptr);
+    if (s != kQueryStop) return s == PE_OK ? pe_fail(c, PE_ERR_DEVICE, "query did not stop") : s;
+    arena = std::max(arena, c->query_bytes);
+  }
+  *bytes = arena + src;
   return PE_OK;
 }
 
