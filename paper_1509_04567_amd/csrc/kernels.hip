@@ -1425,21 +1425,11 @@ __global__ __launch_bounds__(256) void k_jacobi_svd(const double* R, int64_t ldR
   }
   for (int64_t e = t; e < (int64_t)r * r; e += blockDim.x) J[e] = ((e % r) == (e / r)) ? 1.0 : 0.0;
   __syncthreads();
-  // largest squared row norm: pairs whose coupling is below rounding of the largest
-  // singular value (noise rows of the factor) count as converged
-  {
-    double mx = 0.0;
-    for (int i = w; i < r; i += 4) {
-      double q = 0.0;
-      for (int k = lane; k < s; k += 64) q += A[(int64_t)i * s + k] * A[(int64_t)i * s + k];
-      mx = fmax(mx, wave_sum(q));
-    }
-    if (lane == 0) wmax[w] = mx;
-    __syncthreads();
-    if (t == 0) red[0] = fmax(fmax(wmax[0], wmax[1]), fmax(wmax[2], wmax[3]));
-    __syncthreads();
-  }
-  const double floor2 = 1e-15 * red[0];
+  // A pair counts as orthogonal when its coupling is below tol times the geometric mean
+  // of the two squared norms, tol = sqrt(s) eps (the one-sided Jacobi test of Demmel and
+  // Veselic, as in LAPACK's dgesvj).  A test relative to each pair keeps the small
+  // singular values accurate; the rows passed in are already above 1e-12 of the norm.
+  const double tol = sqrt((double)s) * 2.220446049250313e-16;
   const int r2 = r + (r & 1);
   int sweep = 0;
   for (; sweep < 30 && r > 1; ++sweep) {
@@ -1466,10 +1456,10 @@ __global__ __launch_bounds__(256) void k_jacobi_svd(const double* R, int64_t ldR
         al = wave_sum(al);
         be = wave_sum(be);
         ga = wave_sum(ga);
-        if (ga == 0.0 || al == 0.0 || be == 0.0 || fabs(ga) <= floor2) continue;
+        if (ga == 0.0 || al == 0.0 || be == 0.0) continue;
         const double rel = fabs(ga) / sqrt(al * be);
         off = fmax(off, rel);
-        if (rel < 1e-15) continue;
+        if (rel <= tol) continue;
         const double zeta = (be - al) / (2.0 * ga);
         const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
         const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
@@ -1493,7 +1483,7 @@ __global__ __launch_bounds__(256) void k_jacobi_svd(const double* R, int64_t ldR
     __syncthreads();
     const double o = fmax(fmax(wmax[0], wmax[1]), fmax(wmax[2], wmax[3]));
     __syncthreads();
-    if (o < 1e-14) {
+    if (o <= tol) {
       ++sweep;
       break;
     }
