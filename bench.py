@@ -117,7 +117,7 @@ def main():
     cpu = None
     if not args.no_cpu:
         reps_cpu, spent = 1, t_oracle
-        while spent < args.cpu_budget and reps_cpu < 50:
+        while spent < args.cpu_budget and reps_cpu < 1000:
             tc = time.perf_counter()
             oracle.solve_window(prob, "spectral")
             spent += time.perf_counter() - tc
