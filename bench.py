@@ -1,8 +1,11 @@
 """Benchmark of the Paraexp exp-action path on one MI355X.
 
-One step = one complete window solve of the 8192-point advection-diffusion workload
+One step = one complete solve of the 8192-point advection-diffusion workload on [0, 1]
 (shifted samples, truncated SVD, Chebyshev fit, restarted block Arnoldi with the
 projected exponential, outputs at 32 times), inputs already resident in device memory.
+By default the interval is split into 4 Paraexp windows (Sec. 2.2): the window
+subproblems, 64 samples each, run as one batch and u = u0 + sum_j v_j is superposed;
+--windows 1 solves it as one window with 256 samples.
 Prints one JSON line.  Only one GPU is used: --gpus above 1 exits with a message.
 """
 import argparse
@@ -16,12 +19,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary
-    (FETCH_SIZE + WRITE_SIZE, scaled by a device copy of known size), or None when the
-    summary is missing or was taken on a different kernel source."""
+def measured_traffic(kernel, windows):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary of
+    the same window split (FETCH_SIZE + WRITE_SIZE, scaled by a device copy of known
+    size), or None when the summary is missing or was taken on a different kernel source."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", f"pmc_{kernel}_c2_n8192.txt")
+    tag = f"_paraexp{windows}" if windows > 1 else ""
+    path = os.path.join(ROOT, "profiles", f"pmc_{kernel}_c2_n8192{tag}.txt")
     src = os.path.join(ROOT, "paper_1509_04567_amd", "csrc", "kernels.hip")
     try:
         rec = json.loads(open(path).read().split("\n---\n", 1)[1])
@@ -40,6 +44,9 @@ def main():
     ap.add_argument("--n", type=int, default=8192)
     ap.add_argument("--batch", type=int, default=1,
                     help="independent windows solved together per step (seeds 2, 3, ...); 1 = the workload")
+    ap.add_argument("--windows", type=int, default=4,
+                    help="Paraexp windows per solve (Sec. 2.2): the window subproblems run as one batch "
+                         "(s / P samples each) and u = u0 + sum_j v_j is superposed; 1 = one window")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--roofline-kernel", default="block_update", choices=["block_update", "block_proj"])
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -69,12 +76,27 @@ def main():
     tol = 1e-12 if args.precision == "fp64" else 1e-8
     probs = [synth.config_c2(n=args.n, seed=2 + i, tol=tol) for i in range(max(1, args.batch))]
     prob = probs[0]
+    P = max(1, args.windows)
+    if P > 1:
+        # each instance as P Paraexp windows, all windows of all instances in one batch
+        subs = []
+        for i, pr in enumerate(probs):
+            _, g_at = synth.c2_source(args.n, 2 + i)
+            subs += synth.split_windows(pr, P, g_at, s=max(2, pr.s // P))
+    else:
+        subs = probs
     ctx = pe.Context(0)
-    staged = ctx.prepare(probs, prec)
+    staged = ctx.prepare(subs, prec)
+
+    def solve():
+        outs, reps = ctx.solve_prepared(staged)
+        if P > 1:
+            outs = [ctx.superpose(pr.u0, outs[i * P:(i + 1) * P]) for i, pr in enumerate(probs)]
+        return outs, reps
     torch.cuda.synchronize()
     for i in range(args.warmup):
         tw = time.perf_counter()
-        ctx.solve_prepared(staged)
+        solve()
         print(f"warmup {i}: {time.perf_counter() - tw:.3f} s", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     # per-launch HIP-event timing of the dominant kernel family, on the solve's stream
@@ -82,7 +104,7 @@ def main():
     t0 = time.perf_counter()
     for i in range(args.steps):
         ts = time.perf_counter()
-        outs, reps = ctx.solve_prepared(staged)
+        outs, reps = solve()
         print(f"step {i}: {time.perf_counter() - ts:.3f} s cycles={reps[0]['cycles']} "
               f"rejected={reps[0]['rejected']}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
@@ -93,7 +115,8 @@ def main():
     ctx.profile_enable(None)
     roof = None
     # the committed counter summary covers the single-window FP64 workload only
-    traffic = measured_traffic(args.roofline_kernel) if args.batch <= 1 and args.precision == "fp64" else None
+    traffic = (measured_traffic(args.roofline_kernel, P)
+               if args.batch <= 1 and args.n == 8192 and args.precision == "fp64" else None)
     if launches > 0 and k_ms > 0:
         achieved = k_bytes / (k_ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -111,6 +134,8 @@ def main():
         ref, _ = oracle.solve_window(pr, "spectral")
         if i == 0:
             t_oracle = time.perf_counter() - tc
+        if P > 1:  # the superposed u(t_k) = u0 + v(t_k)
+            ref = pr.u0[:, None] + ref
         got = outs[i].detach().cpu().numpy().T
         err = max(err, float(np.linalg.norm(got - ref) / np.linalg.norm(ref)))
 
@@ -146,7 +171,9 @@ def main():
         "dtype": "f64" if prec == pe.PE_FP64 else "f64+f32basis",
         "data": "synthetic",
         "config": {"workload": f"c2_advection_diffusion_n{args.n}_krylov60_s256_nout32"
+                               + (f"_paraexp{P}" if P > 1 else "")
                                + (f"_batch{len(probs)}" if len(probs) > 1 else ""), "n": args.n, "batch": len(probs),
+                   "windows": P,
                    "krylov_steps": prob.krylov_steps, "samples": prob.s, "n_out": len(prob.t_out),
                    "precision": args.precision},
         "rel_l2_vs_oracle": err,

@@ -23,5 +23,6 @@ from .workloads import (  # noqa: F401
     config_c4_subset,
     manufactured_ade,
     split_windows,
+    c2_source,
     random_ade_problem,
 )

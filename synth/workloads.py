@@ -181,6 +181,13 @@ def config_c2(n: int = 8192, seed: int = 2, krylov_steps: int = 60, s: int = 256
                    svd_tol=1e-12, fit_tol=1e-13, name=f"c2_ade_n{n}")
 
 
+def c2_source(n: int = 8192, seed: int = 2):
+    """(u0, g_at) of config_c2 with the same seed: the source as a function of time, for
+    sampling it on Paraexp windows."""
+    rng = np.random.default_rng(seed)
+    return smooth_field(rng, n, 8, 6)
+
+
 def config_c3(n: int = 4096, K: int = 12, s: int = 512, jacobian: bool = True,
               krylov_steps: int = 80) -> BurgersProblem:
     """Viscous Burgers, n=4096, nu=5e-3, T=0.5, u0 = sin(2 pi x) + 0.5 sin(6 pi x),
