@@ -115,8 +115,11 @@ def main():
     ctx.profile_enable(None)
     roof = None
     # the committed counter summary covers the single-window FP64 workload only
+    # the counter record of the single-window split covers three whole restart cycles,
+    # whose launch mix is the solve's; with several windows the early cycles carry every
+    # window at full width and later ones fewer, so that record is not the timed launches'
     traffic = (measured_traffic(args.roofline_kernel, P)
-               if args.batch <= 1 and args.n == 8192 and args.precision == "fp64" else None)
+               if args.batch <= 1 and P == 1 and args.n == 8192 and args.precision == "fp64" else None)
     if launches > 0 and k_ms > 0:
         achieved = k_bytes / (k_ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
