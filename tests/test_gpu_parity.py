@@ -177,6 +177,19 @@ def test_c2_full_size_fp64(ctx):
     assert rel(gpu_out(outs[0]), ref) < FP64_TOL, reps[0]
 
 
+def test_c2_full_size_as_paraexp_windows(ctx):
+    # the benchmark's default launch configuration: the 8192-point problem as 4 Paraexp
+    # windows of 64 samples each in one batch, superposed (eqs. 2.7-2.9)
+    p = synth.config_c2()
+    _, g_at = synth.c2_source(p.n, 2)
+    wins = synth.split_windows(p, 4, g_at, s=p.s // 4)
+    ref, _ = oracle.solve_window(p, "spectral")
+    outs, reps = ctx.solve_batch(wins)
+    u = ctx.superpose(p.u0, outs)
+    assert all(r["rank"] == 7 for r in reps)
+    assert rel(gpu_out(u), p.u0[:, None] + ref) < FP64_TOL, reps
+
+
 # ------------------------------------------------------------------ mixed precision (fp32 basis storage)
 @pytest.mark.parametrize("name", ["c1", "rand_shift"])
 def test_mixed_basis_storage(ctx, name):
