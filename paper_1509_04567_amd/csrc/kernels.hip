@@ -846,7 +846,9 @@ __device__ __forceinline__ void subtract_proj_mfma(const TS* V, int64_t blk, con
   __syncthreads();
 }
 
-constexpr double kReorthSkip = 0.1;
+// a column must keep at least this fraction of its norm through the first projection
+// for the second pass to be skipped (0.1 lost orthogonality over 99-step spaces)
+constexpr double kReorthSkip = 0.3;
 
 template <typename TS>
 __global__ __launch_bounds__(256) void k_block_update(const ProbDev* __restrict__ probs, int j, int nb, int pass, int mode) {

@@ -16,7 +16,7 @@ from __future__ import annotations
 
 import dataclasses
 import math
-from typing import Callable, List, Optional
+from typing import Callable, List, Optional, Sequence
 
 import numpy as np
 
@@ -199,9 +199,11 @@ def config_c3(n: int = 4096, K: int = 12, s: int = 512, jacobian: bool = True,
 
 
 def config_c4(count: int = 512, seed: int = 4, n_lo: int = 512, n_hi: int = 16384,
-              l_lo: int = 40, l_hi: int = 100, tol: float = 1e-9) -> List[Problem]:
+              l_lo: int = 40, l_hi: int = 100, tol: float = 1e-9,
+              indices: Optional[Sequence[int]] = None) -> List[Problem]:
     """512 independent advection-diffusion instances with seeded n, nu, a, rank and
-    Krylov dimension; T=1, 64 Chebyshev-Lobatto samples, 32 output times."""
+    Krylov dimension; T=1, 64 Chebyshev-Lobatto samples, 32 output times.  `indices`
+    builds only those instances (the same ones the full list holds)."""
     rng = np.random.default_rng(seed)
     ns = rng.integers(n_lo, n_hi + 1, count)
     nus = np.exp(rng.uniform(np.log(1e-4), np.log(1e-1), count))
@@ -211,7 +213,7 @@ def config_c4(count: int = 512, seed: int = 4, n_lo: int = 512, n_hi: int = 1638
     seeds = rng.integers(0, 2**31 - 1, count)
     ts = chebyshev_lobatto(0.0, 1.0, 64)
     out = []
-    for i in range(count):
+    for i in (range(count) if indices is None else indices):
         sub = np.random.default_rng(int(seeds[i]))
         u0, g_at = smooth_field(sub, int(ns[i]), int(rs[i]), 7)
         out.append(Problem(n=int(ns[i]), coeffs=ade_coeffs(int(ns[i]), float(avs[i]), float(nus[i])),

@@ -118,6 +118,17 @@ def test_solve_batch_ragged_instances(ctx):
         assert rel(gpu_out(o), ref) < FP64_TOL, (p.name, p.n, r)
 
 
+def test_deep_krylov_space_keeps_orthogonality(ctx):
+    # instance 136 of the 512-instance batch at full size (n = 14966, width 9, l = 99):
+    # a looser skip rule for the second Gram-Schmidt pass lost orthogonality here
+    # around t = 0.05 and the march stalled
+    p = synth.config_c4(indices=[136], tol=1e-12)[0]
+    ref, mdl = oracle.solve_window(p, "spectral")
+    outs, reps = ctx.solve_batch([p])
+    assert not reps[0]["flags"] & 1, reps[0]
+    assert rel(gpu_out(outs[0]), ref) < FP64_TOL, reps[0]
+
+
 def test_paraexp_windows_superposition(ctx):
     rng = np.random.default_rng(21)
     n = 180
