@@ -48,7 +48,9 @@ def main():
                     help="Paraexp windows per solve (Sec. 2.2): the window subproblems run as one batch "
                          "(s / P samples each) and u = u0 + sum_j v_j is superposed; 1 = one window")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--roofline-kernel", default="block_update", choices=["block_update", "block_proj"])
+    ap.add_argument("--roofline-kernel", default=None, choices=["block_update", "block_proj"],
+                    help="kernel family of the roofline figure (default: the one with the most GPU time, "
+                         "block_update for one window, block_proj for the window split)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="run one device copy of this many MiB first (reference for memory counters)")
     ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work for the baseline")
@@ -77,6 +79,8 @@ def main():
     probs = [synth.config_c2(n=args.n, seed=2 + i, tol=tol) for i in range(max(1, args.batch))]
     prob = probs[0]
     P = max(1, args.windows)
+    if args.roofline_kernel is None:
+        args.roofline_kernel = "block_proj" if P > 1 else "block_update"
     if P > 1:
         # each instance as P Paraexp windows, all windows of all instances in one batch
         subs = []
