@@ -118,7 +118,6 @@ def main():
     launches, k_ms, k_bytes, k_flops = prof["launches"], prof["ms"], prof["bytes"], prof["flops"]
     ctx.profile_enable(None)
     roof = None
-    # the committed counter summary covers the single-window FP64 workload only
     # the counter record of the single-window split covers three whole restart cycles,
     # whose launch mix is the solve's; with several windows the early cycles carry every
     # window at full width and later ones fewer, so that record is not the timed launches'
