@@ -170,7 +170,9 @@ pe_status pe_solve_batch(pe_ctx* ctx, const pe_problem* probs, int32_t nprob,
  * compression can give) plus the compressed sources it allocates for the call.  Only
  * the size fields are read (n, s, krylov_steps, rank_max, q_max, prec); data pointers
  * may be NULL.  Pure host arithmetic: ctx may be NULL, and no device is touched.  The
- * workspace persists in ctx and grows on demand (released by pe_destroy). */
+ * workspace persists in ctx and grows on demand (released by pe_destroy).  Returns
+ * PE_ERR_UNSUPPORTED if some restart cycle the problems can meet has no kernel
+ * geometry within the workspace (the solve would fail the same way). */
 pe_status pe_workspace_query(pe_ctx* ctx, const pe_problem* probs, int32_t nprob, size_t* bytes);
 
 /* Step S8 (eq. 2.9): u[:, k] = u0 + sum_{j<P} v_j[:, k], summed in window order.

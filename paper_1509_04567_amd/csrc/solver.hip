@@ -1396,6 +1396,19 @@ pe_status pe_workspace_query(pe_ctx* ctx, const pe_problem* probs, int32_t nprob
     // the march at the largest rank and polynomial order the problem allows
     ml[i] = std::min(p.rank_max, p.s);
     ql[i] = std::min(p.q_max, p.s);
+    // every cycle geometry the march can meet (rank m' <= ml, block width m' in the
+    // zero-state cycle, m' + 1 after it, 1 past the window) must fit its workspace
+    const int l = p.krylov_steps;
+    for (int mm = 0; mm <= ml[i]; ++mm) {
+      const int bwc = mm + 1;
+      const BlockCaps caps = block_caps(p.op.n, bwc, l + 1, (int64_t)(l + 1) * bwc, (int64_t)l * bwc);
+      for (int bw : {1, std::max(1, mm), bwc}) {
+        ProbDev d{};
+        set_geometry(d, p.op.n, bw);
+        if (!geometry_fits(d, caps, l + 1))
+          return pe_fail(c, PE_ERR_UNSUPPORTED, "cycle geometry exceeds the workspace");
+      }
+    }
   }
   for (int prec = 0; prec < 2; ++prec) {
     std::vector<int> idx, m, q, ld;

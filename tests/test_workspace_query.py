@@ -52,3 +52,19 @@ def test_query_rejects_unsupported_sizes(pe):
     with pytest.raises(pe.PeError) as ei:
         pe.workspace_query([p])
     assert ei.value.status == -1
+
+
+def test_every_block_width_has_a_geometry_at_every_size(pe):
+    # block widths 1..32 on grids from 4 to 2^20 points: every cycle geometry fits
+    # (wide blocks on long grids fall back to the global-memory TSQR combine)
+    for n in (4, 33, 160, 1024, 8192, 65536, 1 << 20):
+        for rank_max in sorted({0, 1, 7, 8, 9, 15, 16, 17, 24, 31}):
+            if n < rank_max + 1:
+                continue
+            p = synth.random_ade_problem(1, 64, s=40)
+            p.n, p.rank_max, p.krylov_steps = n, rank_max, 60
+            assert pe.workspace_query([p]) > 0
+    # the largest workload shape: 2^20 points, rank 32 samples, 120 block steps
+    p = synth.random_ade_problem(1, 64, s=64)
+    p.n, p.rank_max, p.krylov_steps = 1 << 20, 31, 120
+    assert pe.workspace_query([p]) > 121 * (1 << 20) * 32 * 8
