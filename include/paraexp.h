@@ -28,8 +28,10 @@
  *     return after it has completed (the solver's step control reads scalars back);
  *   - errors are negative pe_status values with a message in pe_last_error(); a
  *     non-converged solve is not an error: its report carries PE_FLAG_* bits and the
- *     outputs are still written (NaN at output times that a march does not reach
- *     within its cap of 100000 restart cycles).
+ *     outputs are still written (NaN at output times that a march does not reach: it
+ *     stops at once when no sub-step down to 1e-13 of its time span meets tol or when
+ *     its projected matrix is not finite, and after at most 100000 restart cycles);
+ *     the other problems of a batch are not affected.
  */
 #ifndef PARAEXP_H
 #define PARAEXP_H
@@ -52,7 +54,9 @@ typedef enum {
 
 /* report flags (informational, outputs are written) */
 enum {
-  PE_FLAG_NOT_CONVERGED = 1,  /* a step at the minimum step had error above tol, or the cycle cap was hit */
+  PE_FLAG_NOT_CONVERGED = 1,  /* the march stopped: no sub-step down to the minimum met tol, the
+                                 projected matrix or its estimate was not finite, or the cycle cap
+                                 was hit; outputs it did not reach are NaN                   */
   PE_FLAG_BREAKDOWN = 2,      /* Krylov space became invariant (exact, "happy") early      */
   PE_FLAG_RANK_CAPPED = 4,    /* truncation wanted more than rank_max singular vectors     */
   PE_FLAG_FIT_CAPPED = 8      /* fit residual above fit_tol at q_max terms                 */
@@ -149,7 +153,9 @@ pe_status pe_stencil_apply(pe_ctx* ctx, const pe_stencil* op, const double* X, i
 pe_status pe_compress(pe_ctx* ctx, const pe_problem* prob, double* U, double* Pi, int32_t* m,
                       int32_t* q, double* sigma, pe_report* report, void* stream);
 
-/* Steps S5-S8 for nprob independent problems with a given compressed source
+/* Steps S5-S8 (Sec. 2.1, eq. 2.4: the block Krylov space of [x | U] and the exponential
+ * of the projected source-augmented matrix; Sec. 2.2 for the window subproblem) for
+ * nprob independent problems with a given compressed source
  * (stage parity: every problem uses U[i] (n x m[i], ld n) and Pi[i] (m[i] x q[i],
  * ld m[i]) -- device pointers; U[i]/Pi[i] may be NULL when m[i] = 0).  The sample
  * fields of the problems (t_samples, G, svd_tol, fit_tol) are ignored; t0, t1 still
@@ -160,7 +166,11 @@ pe_status pe_expaction_batch(pe_ctx* ctx, const pe_problem* probs, const double*
                              int32_t nprob, pe_report* reports, void* stream);
 
 /* Steps S1-S8 for nprob independent window subproblems (instances and/or Paraexp
- * windows) in one batched pipeline.  reports: host array of nprob. */
+ * windows) in one batched pipeline: the linear PEBK algorithm of Sec. 2.2 (Fig. 2.1)
+ * per problem -- shifted samples (eq. 2.6), truncated SVD and time fit (eq. 2.3),
+ * restarted block Krylov exp-action (eq. 2.4) to every output time.  Windows of one
+ * problem are independent (eqs. 2.7-2.8) and are superposed with pe_superpose (eq. 2.9).
+ * probs: host array of nprob; reports: host array of nprob, written. */
 pe_status pe_solve_batch(pe_ctx* ctx, const pe_problem* probs, int32_t nprob,
                          pe_report* reports, void* stream);
 

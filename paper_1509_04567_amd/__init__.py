@@ -16,4 +16,10 @@ from .binding import (  # noqa: F401
     FLAG_RANK_CAPPED,
     FLAG_FIT_CAPPED,
     workspace_query,
+    policy_step,
+    policy_step_growth,
+    policy_reorth_skip,
+    PE_STEP_ACCEPT,
+    PE_STEP_REJECT,
+    PE_STEP_STOP,
 )

@@ -35,7 +35,12 @@ FLAG_FIT_CAPPED = 8
 
 EXPORTED = ["pe_create", "pe_destroy", "pe_last_error", "pe_version", "pe_stencil_apply", "pe_compress",
             "pe_expaction_batch", "pe_solve_batch", "pe_workspace_query", "pe_superpose", "pe_wr_burgers",
-            "pe_profile_enable", "pe_profile_read"]
+            "pe_profile_enable", "pe_profile_read",
+            # host-only decision rules (include/paraexp_policy.h)
+            "pe_policy_step", "pe_policy_step_growth", "pe_policy_reorth_skip"]
+PE_STEP_ACCEPT = 0
+PE_STEP_REJECT = 1
+PE_STEP_STOP = 2
 
 
 class PeStencil(ctypes.Structure):
@@ -107,6 +112,21 @@ class PeWrProblem(ctypes.Structure):
     ]
 
 
+class PeStepTrial(ctypes.Structure):
+    _fields_ = [("nsq", ctypes.c_int32), ("est", ctypes.c_void_p), ("alpha", ctypes.c_double),
+                ("tol", ctypes.c_double), ("ref", ctypes.c_double), ("tspan", ctypes.c_double),
+                ("dmin", ctypes.c_double), ("krylov_steps", ctypes.c_int32), ("pexp", ctypes.c_double)]
+
+
+class PeStepDecision(ctypes.Structure):
+    _fields_ = [("action", ctypes.c_int32), ("level", ctypes.c_int32), ("flags", ctypes.c_int32),
+                ("step", ctypes.c_double), ("rho", ctypes.c_double), ("pexp", ctypes.c_double),
+                ("err", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class PeError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"paraexp status {status}: {msg}")
@@ -149,11 +169,41 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.pe_profile_enable.argtypes = [vp, ctypes.c_char_p]
     lib.pe_profile_read.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double),
                                     ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+    lib.pe_policy_step.argtypes = [ctypes.POINTER(PeStepTrial), ctypes.POINTER(PeStepDecision)]
+    lib.pe_policy_step.restype = None
+    lib.pe_policy_step_growth.argtypes = [ctypes.c_double, ctypes.c_double, i32]
+    lib.pe_policy_step_growth.restype = ctypes.c_double
+    lib.pe_policy_reorth_skip.argtypes = [vp, vp, i32, ctypes.c_double]
+    lib.pe_policy_reorth_skip.restype = i32
     for name in ["pe_create", "pe_destroy", "pe_stencil_apply", "pe_compress", "pe_expaction_batch",
                  "pe_solve_batch", "pe_superpose", "pe_wr_burgers", "pe_profile_enable", "pe_profile_read"]:
         getattr(lib, name).restype = ctypes.c_int
     _LIB = lib
     return lib
+
+
+def policy_step(est, alpha, tol, ref, tspan, dmin, krylov_steps, pexp=0.0):
+    """pe_policy_step (host only): the library's decision on one step-size trial.
+    est: per squaring level k = 0..nsq the pair (error estimate, |y_k|)."""
+    lib = load_library()
+    arr, ptr = _host_doubles(np.asarray(est, dtype=np.float64).reshape(-1))
+    t = PeStepTrial(nsq=arr.size // 2 - 1, est=ptr, alpha=alpha, tol=tol, ref=ref, tspan=tspan, dmin=dmin,
+                    krylov_steps=krylov_steps, pexp=pexp)
+    out = PeStepDecision()
+    lib.pe_policy_step(ctypes.byref(t), ctypes.byref(out))
+    return out.as_dict()
+
+
+def policy_step_growth(rho, pexp, krylov_steps):
+    return float(load_library().pe_policy_step_growth(rho, pexp, krylov_steps))
+
+
+def policy_reorth_skip(R, Rn, kappa=0.3):
+    """pe_policy_reorth_skip (host only): R (bw x bw upper triangular), Rn (bw,)."""
+    lib = load_library()
+    Ra, Rp = _host_doubles(R)
+    na, npp = _host_doubles(Rn)
+    return bool(lib.pe_policy_reorth_skip(Rp, npp, int(Ra.shape[0]), float(kappa)))
 
 
 def _torch():

@@ -4,17 +4,19 @@
 //   S0  stencil operator (Sec. 3, eq. 3.2)                       k_stencil_cols, fused in k_block_*
 //   S3  QR of the source samples (Sec. 2.1, eq. 2.2-2.3)         k_block_* in MODE_GIVEN
 //   S5  block Arnoldi on K_l(A, [x|U]) (eq. 2.4)                 k_block_* in MODE_ARNOLDI / MODE_INIT
-//   S6  exponential of the projected augmented matrix            k_gemm (MFMA f64), k_lincomb, ...
+//   S6  exponential of the projected augmented matrix            k_build_aug, k_gemm (MFMA f64),
+//                                                                k_elementwise, k_expm_apply
 //   S7  state/output projection V y                              k_project
 //   S8  superposition u = u0 + sum_j v_j (eq. 2.9)               k_superpose
 //
-// Block orthogonalisation = two passes of block classical Gram-Schmidt, each followed by
-// a tall-skinny QR (TSQR: per-chunk wave-level MGS2, then a QR of the stacked chunk R
-// factors done by the last workgroup to finish).  The intra-block QR must be
-// Householder-quality: Cholesky-based block normalisation loses orthogonality when the
-// new block is nearly rank deficient, which the Fourier-mode sources of these problems
-// produce in the first Krylov steps.
+// Block orthogonalisation = block classical Gram-Schmidt, a second pass only where the
+// first leaves the new block insufficiently orthogonal to the basis, each pass followed
+// by a tall-skinny QR (TSQR: a register-resident classical Gram-Schmidt QR of each row
+// chunk, with a second in-chunk pass where needed, then a QR of the stacked chunk R
+// factors by the last workgroup to finish).  Dependent columns are deflated (zero
+// column, zero row of R) rather than replaced.
 #include "kernels.h"
+#include "policy.h"
 
 #include <type_traits>
 
@@ -61,15 +63,6 @@ __device__ double block_sum(double v, double* red) {
   return t;
 }
 
-// splitmix64 finaliser (Steele, Lea & Flood 2014) -> uniform double in [-1, 1)
-__device__ __forceinline__ double hash_unit(uint64_t a, uint64_t b) {
-  uint64_t z = a * 0x9E3779B97F4A7C15ull + (b + 1) * 0xD1B54A32D192ED03ull;
-  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-  z ^= z >> 31;
-  return (double)(z >> 11) * (2.0 / 9007199254740992.0) - 1.0;
-}
-
 template <typename TS>
 __device__ __forceinline__ TS* basis_ptr(const ProbDev& p);
 template <>
@@ -107,75 +100,32 @@ __device__ __forceinline__ double tsqr_entry(const ProbDev& p, const double* Qlo
   return acc;
 }
 
-// Modified Gram-Schmidt with reorthogonalisation on a row-major rows x bw array with
-// leading dimension ld.  A "team" (one wave, or the whole workgroup when BLOCK) owns the
-// array; thread t handles rows t, t+T, ...  R (bw x bw, row-major, pre-zeroed) receives
-// the triangular factor (written by team thread 0).
-// A column is numerically dependent when its remainder is <= kDepTol times its reference
-// norm ref[b] (the column norm before the block projections; when ref is null, the norm
-// of the column as given).  Such a column gets a zero diagonal in R and is replaced by a
-// pseudo-random unit vector orthogonal to the previous columns, so Q stays orthonormal;
-// with stack > 0 the replacement lives on rows r = b (mod stack) only, i.e. on the
-// replacement directions of the chunk factors in a TSQR combine.
-#define PE_DEP_TOL 1e-12
-template <bool BLOCK, typename Ptr>
-__device__ __forceinline__ void mgs2_qr(Ptr X, int rows, int ld, int bw, double* R, uint64_t seed, double* red, const double* ref,
-                        int stack) {
-  const int T = BLOCK ? (int)blockDim.x : 64;
-  const int t = BLOCK ? (int)threadIdx.x : (int)(threadIdx.x & 63);
-  auto rsum = [&](double v) -> double { return BLOCK ? block_sum(v, red) : wave_sum(v); };
+// Modified Gram-Schmidt applied twice, column by column, by the whole workgroup on a
+// row-major rows x bw array X (leading dimension ld, any bw); thread t handles rows t,
+// t + blockDim.x, ...  A column whose remainder is <= dep_tol times its norm as given is
+// dependent and deflated: a zero column with a zero diagonal in R.  R (bw x bw,
+// row-major, pre-zeroed) receives the triangular factor; `red` holds >= 16 doubles.
+__device__ void mgs2_qr_block(double* X, int rows, int ld, int bw, double* R, double dep_tol, double* red) {
+  const int T = (int)blockDim.x, t = (int)threadIdx.x;
   for (int b = 0; b < bw; ++b) {
-    double n0;
-    if (ref) {
-      n0 = ref[b];
-    } else {
-      double s0 = 0.0;
-      for (int r = t; r < rows; r += T) {
-        double v = X[(int64_t)r * ld + b];
-        s0 += v * v;
-      }
-      n0 = sqrt(rsum(s0));
-    }
-    for (int pass = 0; pass < 2; ++pass) {
+    double s0 = 0.0;
+    for (int r = t; r < rows; r += T) s0 += X[(int64_t)r * ld + b] * X[(int64_t)r * ld + b];
+    const double n0 = sqrt(block_sum(s0, red));
+    for (int pass = 0; pass < 2; ++pass)
       for (int a = 0; a < b; ++a) {
         double s = 0.0;
         for (int r = t; r < rows; r += T) s += X[(int64_t)r * ld + a] * X[(int64_t)r * ld + b];
-        const double d = rsum(s);
+        const double d = block_sum(s, red);
         for (int r = t; r < rows; r += T) X[(int64_t)r * ld + b] -= d * X[(int64_t)r * ld + a];
         if (t == 0) R[a * bw + b] += d;
       }
-    }
     double s1 = 0.0;
-    for (int r = t; r < rows; r += T) {
-      double v = X[(int64_t)r * ld + b];
-      s1 += v * v;
-    }
-    const double nr = sqrt(rsum(s1));
-    if (nr > PE_DEP_TOL * n0 && nr > 1e-300) {
-      const double inv = 1.0 / nr;
-      for (int r = t; r < rows; r += T) X[(int64_t)r * ld + b] *= inv;
-      if (t == 0) R[b * bw + b] = nr;
-    } else {
-      if (t == 0) R[b * bw + b] = 0.0;
-      for (int r = t; r < rows; r += T)
-        X[(int64_t)r * ld + b] = (stack > 0 && (r % stack) != b) ? 0.0 : hash_unit(seed + (uint64_t)r, (uint64_t)b);
-      for (int pass = 0; pass < 3; ++pass) {
-        for (int a = 0; a < b; ++a) {
-          double s = 0.0;
-          for (int r = t; r < rows; r += T) s += X[(int64_t)r * ld + a] * X[(int64_t)r * ld + b];
-          const double d = rsum(s);
-          for (int r = t; r < rows; r += T) X[(int64_t)r * ld + b] -= d * X[(int64_t)r * ld + a];
-        }
-      }
-      double s2 = 0.0;
-      for (int r = t; r < rows; r += T) {
-        double v = X[(int64_t)r * ld + b];
-        s2 += v * v;
-      }
-      const double n2 = sqrt(rsum(s2));
-      const double inv = n2 > 0.0 ? 1.0 / n2 : 0.0;
-      for (int r = t; r < rows; r += T) X[(int64_t)r * ld + b] *= inv;
-    }
+    for (int r = t; r < rows; r += T) s1 += X[(int64_t)r * ld + b] * X[(int64_t)r * ld + b];
+    const double nr = sqrt(block_sum(s1, red));
+    const bool dep = !(nr > dep_tol * n0 && nr > 1e-300);
+    const double inv = dep ? 0.0 : 1.0 / nr;
+    for (int r = t; r < rows; r += T) X[(int64_t)r * ld + b] *= inv;
+    if (t == 0) R[b * bw + b] = dep ? 0.0 : nr;
   }
 }
 
@@ -184,13 +134,13 @@ __device__ __forceinline__ void mgs2_qr(Ptr X, int rows, int ld, int bw, double*
 // array X with leading dimension ld, in LDS or global memory (thread t owns rows t,
 // t + 64 NW, ..., so no row is touched by two threads).  All dot products of a column
 // with the previous columns are reduced together: three team reductions per column.
-// A column whose remainder is <= PE_DEP_TOL times its reference norm ref[b] is
+// A column whose remainder is <= dep_tol times its reference norm ref[b] is
 // dependent: it becomes a zero column with a zero row in R (deflation), so it adds no
 // direction and later columns do not couple to it.  R (bw x bw, row-major, pre-zeroed)
 // receives the triangular factor.  `red`: LDS scratch of 32 NW doubles (NW > 1).
 template <int NW>
 __device__ __forceinline__ void cgs2_qr_team(double* X, int rows, int ld, int bw, double* R, const double* ref,
-                                             double* red) {
+                                             double dep_tol, double* red) {
   const int t = (NW == 1) ? (int)(threadIdx.x & 63) : (int)threadIdx.x;
   const int w = t >> 6;
   constexpr int T = 64 * NW;
@@ -244,7 +194,7 @@ __device__ __forceinline__ void cgs2_qr_team(double* X, int rows, int ld, int bw
     for (int r = t; r < rows; r += T) s1[0] += X[(int64_t)r * ld + b] * X[(int64_t)r * ld + b];
     team_sums(s1, 1);
     const double nr = sqrt(s1[0]);
-    const bool dep = !(nr > PE_DEP_TOL * ref[b] && nr > 1e-300);
+    const bool dep = !(nr > dep_tol * ref[b] && nr > 1e-300);
     const double inv = dep ? 0.0 : 1.0 / nr;
     for (int r = t; r < rows; r += T) X[(int64_t)r * ld + b] *= inv;
     if (t == 0) R[b * bw + b] = dep ? 0.0 : nr;
@@ -259,7 +209,7 @@ __device__ __forceinline__ void cgs2_qr_team(double* X, int rows, int ld, int bw
 // columns are deflated as in cgs2_qr_team.  `red` is LDS scratch of NW * BWM doubles.
 template <int BWM, int RPL, int NW>
 __device__ __forceinline__ void cgs2_team(const double* Xi, int ldi, double* X, int ld, int rows, int bw, double* R,
-                                          const double* ref, double* red) {
+                                          const double* ref, double dep_tol, double* red) {
   const int t = (NW == 1) ? (int)(threadIdx.x & 63) : (int)threadIdx.x;
   const int w = t >> 6;
   constexpr int T = 64 * NW;
@@ -352,7 +302,7 @@ __device__ __forceinline__ void cgs2_team(const double* Xi, int ldi, double* X, 
         for (int a = 0; a < b; ++a) s2sum += sd[a] * sd[a];
       }
       const double nr = sqrt(nsq > s2sum ? nsq - s2sum : 0.0);
-      const bool dep = !(nr > PE_DEP_TOL * n0 && nr > 1e-300);
+      const bool dep = !(nr > dep_tol * n0 && nr > 1e-300);
       const double inv = dep ? 0.0 : 1.0 / nr;
 #pragma unroll
       for (int q = 0; q < RPL; ++q) xr[q][b] *= inv;
@@ -373,15 +323,15 @@ __device__ __forceinline__ void cgs2_team(const double* Xi, int ldi, double* X, 
 // Xi (ld ldi) is read once, the Q factor written to X (ld ld), which may alias Xi
 template <int NW>
 __device__ __forceinline__ bool cgs2_dispatch(const double* Xi, int ldi, double* X, int ld, int rows, int bw, double* R,
-                                              const double* ref, double* red) {
+                                              const double* ref, double dep_tol, double* red) {
   const int rpl = (rows + 64 * NW - 1) / (64 * NW);
   if (bw <= 8) {
-    if (rpl <= 1) { cgs2_team<8, 1, NW>(Xi, ldi, X, ld, rows, bw, R, ref, red); return true; }
-    if (rpl <= 2) { cgs2_team<8, 2, NW>(Xi, ldi, X, ld, rows, bw, R, ref, red); return true; }
-    if (rpl <= 4) { cgs2_team<8, 4, NW>(Xi, ldi, X, ld, rows, bw, R, ref, red); return true; }
+    if (rpl <= 1) { cgs2_team<8, 1, NW>(Xi, ldi, X, ld, rows, bw, R, ref, dep_tol, red); return true; }
+    if (rpl <= 2) { cgs2_team<8, 2, NW>(Xi, ldi, X, ld, rows, bw, R, ref, dep_tol, red); return true; }
+    if (rpl <= 4) { cgs2_team<8, 4, NW>(Xi, ldi, X, ld, rows, bw, R, ref, dep_tol, red); return true; }
   } else if (bw <= 16) {
-    if (rpl <= 1) { cgs2_team<16, 1, NW>(Xi, ldi, X, ld, rows, bw, R, ref, red); return true; }
-    if (rpl <= 2) { cgs2_team<16, 2, NW>(Xi, ldi, X, ld, rows, bw, R, ref, red); return true; }
+    if (rpl <= 1) { cgs2_team<16, 1, NW>(Xi, ldi, X, ld, rows, bw, R, ref, dep_tol, red); return true; }
+    if (rpl <= 2) { cgs2_team<16, 2, NW>(Xi, ldi, X, ld, rows, bw, R, ref, dep_tol, red); return true; }
   }
   return false;  // wider blocks or more rows: cgs2_qr_team on an LDS or global array
 }
@@ -846,8 +796,8 @@ __device__ __forceinline__ void subtract_proj_mfma(const TS* V, int64_t blk, con
   __syncthreads();
 }
 
-// a column must keep at least this fraction of its norm through the first projection
-// for the second pass to be skipped (0.1 lost orthogonality over 99-step spaces)
+// the second Gram-Schmidt pass of an Arnoldi step is skipped when every column of the
+// first pass's Q1 is orthogonal to the basis to ~eps / kReorthSkip (reorth_column_ok)
 constexpr double kReorthSkip = 0.3;
 
 template <typename TS>
@@ -929,8 +879,8 @@ __global__ __launch_bounds__(256) void k_block_update(const ProbDev* __restrict_
   if (t == 0) reg_qr = 1;
   __syncthreads();
   if (w == 0) {
-    if (!cgs2_dispatch<1>(X, ld, Qloc, bw, rows, bw, Rl, Rn, nullptr)) {
-      cgs2_qr_team<1>(X, rows, ld, bw, Rl, Rn, nullptr);
+    if (!cgs2_dispatch<1>(X, ld, Qloc, bw, rows, bw, Rl, Rn, p.dep_tol, nullptr)) {
+      cgs2_qr_team<1>(X, rows, ld, bw, Rl, Rn, p.dep_tol, nullptr);
       if (lane == 0) reg_qr = 0;
     }
   }
@@ -973,14 +923,14 @@ __global__ __launch_bounds__(256) void k_block_update(const ProbDev* __restrict_
   __syncthreads();
   if (reg_comb) {
     // stacked chunk factors read straight from global memory into registers
-    cgs2_dispatch<4>(p.Rloc, bw, Qs, bw, srows, bw, Rl, Rn, Qsl);
+    cgs2_dispatch<4>(p.Rloc, bw, Qs, bw, srows, bw, Rl, Rn, p.dep_tol, Qsl);
     __syncthreads();
   } else if (!p.comb_global) {
     bulk_load(
         (int64_t)srows * bw, [&](int64_t e) -> double { return p.Rloc[e]; },
         [&](int64_t e, double v) { X[(e / bw) * ld + (e % bw)] = v; });
     __syncthreads();
-    cgs2_qr_team<4>(X, srows, ld, bw, Rl, Rn, Qsl);
+    cgs2_qr_team<4>(X, srows, ld, bw, Rl, Rn, p.dep_tol, Qsl);
     __syncthreads();
     for (int e = t; e < srows * bw; e += 256) Qs[e] = X[(e / bw) * ld + (e % bw)];
   } else {
@@ -988,25 +938,21 @@ __global__ __launch_bounds__(256) void k_block_update(const ProbDev* __restrict_
     // worked on by the one thread that owns it, so no fence is needed inside
     for (int r = t; r < srows; r += 256)
       for (int b = 0; b < bw; ++b) Qs[(int64_t)r * bw + b] = p.Rloc[(int64_t)r * bw + b];
-    cgs2_qr_team<4>(Qs, srows, bw, bw, Rl, Rn, Qsl);
+    cgs2_qr_team<4>(Qs, srows, bw, bw, Rl, Rn, p.dep_tol, Qsl);
     __syncthreads();
   }
   double* Rout = p.Rf + (mode == MODE_INIT ? 2 : pass) * nout;
   for (int o = t; o < nout; o += 256) Rout[o] = Rl[o];
   if (mode == MODE_INIT && t == 0) p.cnt[2 * p.nbmax + 1] = 0u;
   if (mode == MODE_ARNOLDI && pass == 0) {
-    // keep fraction of each column after the first projection (R column norm against
-    // the pre-projection norm); above kReorthSkip every column of Q1 is orthogonal to
-    // the basis to ~eps / kReorthSkip and the second pass is skipped:
-    // V_{j+1} = Q1, H column = S1 and subdiagonal block Rf1 (W = V S1 + Q1 Rf1 exactly)
+    // the loss of orthogonality of each column of Q1 = W' R1^{-1} to the basis is bounded
+    // through R1^{-1} and the pre-projection norms (reorth_column_ok); when every column
+    // passes, the second pass is skipped: V_{j+1} = Q1, H column = S1 and subdiagonal
+    // block Rf1 (W = V S1 + Q1 Rf1 exactly)
     __shared__ int skip;
     if (w == 0) {
-      bool ok = true;  // lane b: column b kept enough (a zero column loses nothing)
-      if (lane < bw) {
-        double c2 = 0.0;
-        for (int a = 0; a <= lane; ++a) c2 += Rl[a * bw + lane] * Rl[a * bw + lane];
-        ok = !(Rn[lane] > 0.0) || sqrt(c2) >= kReorthSkip * Rn[lane];
-      }
+      bool ok = true;  // lane b: column b of Q1 orthogonal enough
+      if (lane < bw) ok = reorth_column_ok(Rl, Rn, bw, lane, kReorthSkip);
       const bool all_ok = __all(ok);
       if (lane == 0) {
         skip = all_ok ? 1 : 0;
@@ -1430,7 +1376,7 @@ __global__ __launch_bounds__(256) void k_jacobi_svd(const double* R, int64_t ldR
   // A pair counts as orthogonal when its coupling is below tol times the geometric mean
   // of the two squared norms, tol = sqrt(s) eps (the one-sided Jacobi test of Demmel and
   // Veselic, as in LAPACK's dgesvj).  A test relative to each pair keeps the small
-  // singular values accurate; the rows passed in are already above 1e-12 of the norm.
+  // singular values accurate; the rows passed in are the non-deflated rows of R.
   const double tol = sqrt((double)s) * 2.220446049250313e-16;
   const int r2 = r + (r & 1);
   int sweep = 0;
@@ -1579,7 +1525,7 @@ __global__ __launch_bounds__(256) void k_fit(const double* A, int s, const int* 
   for (int e = t; e < qcap * qcap; e += blockDim.x) Rt[e] = 0.0;
   __threadfence_block();
   __syncthreads();
-  mgs2_qr<true>(Tq, s, qcap, qcap, Rt, 0x2545F491ull, red, nullptr, 0);
+  mgs2_qr_block(Tq, s, qcap, qcap, Rt, 1e-12, red);
   __threadfence_block();
   __syncthreads();
   for (int e = t; e < m * qcap; e += blockDim.x) {

@@ -23,7 +23,9 @@
 #include <vector>
 
 #include "../../include/paraexp.h"
+#include "../../include/paraexp_policy.h"
 #include "kernels.h"
+#include "policy.h"
 
 struct pe_ctx {
   int device = 0;
@@ -102,7 +104,13 @@ void prof_collect(pe_ctx* ctx) {
 
 constexpr double kTaylorTheta = 0.78;  // ||A||_1 bound for the degree-16 Taylor polynomial
 constexpr int kMaxTrials = 6;
-constexpr double kSigmaFloor = 1e-12;  // relative singular values treated as zero
+// truncation floor: singular values at or below kSigmaFloor sigma_1 are never kept
+constexpr double kSigmaFloor = 1e-14;
+// dependence tolerances of the block QR: the compression resolves the sample matrix to
+// an absolute ~1e-14 of its column norms (below the truncation floor's reach); the
+// Arnoldi process deflates remainders below 1e-12 of the pre-projection norm
+constexpr double kDepTolCompress = 1e-14;
+constexpr double kDepTolArnoldi = 1e-12;
 constexpr int kRowsU = 64;
 
 // bound on the re-expansion growth of the Chebyshev source basis over one step
@@ -489,6 +497,7 @@ pe_status compress_one(pe_ctx* ctx, const pe_problem& p, double* U, int64_t ldU,
   d.l = nblk;
   d.active = 1;
   d.ldH = S_;
+  d.dep_tol = kDepTolCompress;
   set_geometry(d, n, bwc);
   if (!geometry_fits(d, caps, nblk)) return pe_fail(ctx, PE_ERR_UNSUPPORTED, "compression geometry exceeds workspace");
   ProbDev* dd = (ProbDev*)(base + o_desc);
@@ -503,30 +512,16 @@ pe_status compress_one(pe_ctx* ctx, const pe_problem& p, double* U, int64_t ldU,
   }
   // significant rows of R
   double* R = d.H;
-  if (const char* dump = std::getenv("PARAEXP_DUMP")) {  // debugging aid: R and Q as raw doubles
-    HCK(hipStreamSynchronize(st));
-    std::vector<double> hR((size_t)S_ * S_), hQ((size_t)nblk * n * bwc);
-    HCK(hipMemcpy(hR.data(), R, sizeof(double) * hR.size(), hipMemcpyDeviceToHost));
-    HCK(hipMemcpy(hQ.data(), d.V, sizeof(double) * hQ.size(), hipMemcpyDeviceToHost));
-    std::string base_path(dump);
-    if (FILE* f = std::fopen((base_path + "_R.bin").c_str(), "wb")) {
-      std::fwrite(hR.data(), sizeof(double), hR.size(), f);
-      std::fclose(f);
-    }
-    if (FILE* f = std::fopen((base_path + "_Q.bin").c_str(), "wb")) {
-      std::fwrite(hQ.data(), sizeof(double), hQ.size(), f);
-      std::fclose(f);
-    }
-  }
   pe::launch_row_norms(R, S_, S_, s, (double*)(base + o_rn), st);
   HCK(hipMemcpyAsync(hp, base + o_rn, sizeof(double) * S_, hipMemcpyDeviceToHost, st));
   HCK(hipStreamSynchronize(st));
   double fro2 = 0.0;
   for (int i = 0; i < S_; ++i) fro2 += hp[i] * hp[i];
   const double fro = std::sqrt(fro2);
+  // the rows of R that the QR did not deflate (a deflated column leaves a zero row)
   std::vector<int> sel;
   for (int i = 0; i < S_; ++i)
-    if (hp[i] > kSigmaFloor * fro) sel.push_back(i);
+    if (hp[i] > 1e-300 && hp[i] > 1e-17 * fro) sel.push_back(i);
   res.sigma.assign(s, 0.0);
   res.m = 0;
   if (fro == 0.0 || sel.empty() || p.rank_max == 0) {
@@ -547,10 +542,10 @@ pe_status compress_one(pe_ctx* ctx, const pe_problem& p, double* U, int64_t ldU,
   HCK(hipStreamSynchronize(st));
   std::vector<double> sig(r);
   for (int i = 0; i < r; ++i) sig[i] = hp[perm[i]];
-  // truncation: smallest m with dropped energy <= svd_tol |G^|_F, never keeping
-  // sigma <= kSigmaFloor sigma_1 (the resolution of the block QR, whose dependence test
-  // drops chunk remainders below 1e-12 of a column), keeping clusters whole, capped at
-  // rank_max
+  // truncation (the energy rule of the truncated SVD, Sec. 2.1 eq. 2.3): the smallest m
+  // with dropped energy <= svd_tol |G^|_F; singular values <= kSigmaFloor sigma_1 are
+  // never kept; a cut inside a cluster (|sigma_m - sigma_{m+1}| <= 1e-12 sigma_1) keeps
+  // the cluster whole; m is capped at rank_max
   double sfro2 = 0.0;
   for (double v : sig) sfro2 += v * v;
   const double gfro = std::sqrt(sfro2);
@@ -601,6 +596,7 @@ struct HostState {
   double target = 0.0, dtry = 0.0, nrm = 0.0;
   int bw = 1, N = 0;
   bool pending = false, accepted = false;
+  bool stop = false;  // the march cannot continue (non-finite projected matrix or estimate)
   int level = 0;
   double rho = 1.0;
   double pexp = 0.0;  // local order of the error estimate in the step (0: unknown)
@@ -682,6 +678,7 @@ pe_status march_batch(pe_ctx* ctx, const pe_problem* probs, const int* idx, int 
     d.coef = p.op.per_point ? p.op.coeffs : nullptr;
     bind_block(d, base, bo[ii], mixed, p.krylov_steps + 1);
     d.U = Ul[ii];
+    d.dep_tol = kDepTolArnoldi;
     d.xstate = (double*)(base + o_x[ii]);
     d.x = d.xstate;
     HostState& h = hs[ii];
@@ -840,6 +837,13 @@ pe_status march_batch(pe_ctx* ctx, const pe_problem* probs, const int* idx, int 
       hs[ii].nrm = hp[ii];
       hs[ii].pending = hd[ii].active != 0;
       hs[ii].accepted = false;
+      hs[ii].stop = false;
+      // a non-finite projected matrix: no step can be taken
+      if (hs[ii].pending && !std::isfinite(hp[ii])) {
+        hs[ii].pending = false;
+        hs[ii].stop = true;
+        hs[ii].flags |= PE_FLAG_NOT_CONVERGED;
+      }
     }
     const int tiles = (mb_N + 31) / 32;
     // Each trial evaluates the step at every squaring level: after k squarings the
@@ -887,54 +891,38 @@ pe_status march_batch(pe_ctx* ctx, const pe_problem* probs, const int* idx, int 
         const pe_problem& p = probs[idx[ii]];
         const double* ho = hp + 2 * (PE_MAX_LEVELS + 1) * ii;
         const int ns = he[ii].nsq;
-        const double dmin = 1e-13 * h.Tspan;
-        int best = -1;
-        double best_err = 0.0, best_lim = 1.0;
-        for (int k = ns; k >= 0; --k) {
-          const double err = ho[2 * k], yn = ho[2 * k + 1];
-          const double lim = p.tol * std::max(h.ref, yn) / h.Tspan;
-          if (trace)
+        if (trace)
+          for (int k = ns; k >= 0; --k)
             fprintf(stderr, "[paraexp] prob %d cycle %d trial %d level %d tau %.6e d %.3e N %d bw %d |H|1 %.3e "
-                    "err %.3e lim %.3e |y| %.3e\n", idx[ii], guard, trial, k, h.tau, std::ldexp(he[ii].alpha, k),
-                    h.N, h.bw, h.nrm, err, lim, yn);
-          if (std::isfinite(err) && err <= lim) {
-            best = k;
-            best_err = err;
-            best_lim = lim;
-            break;
-          }
-        }
-        const double d0 = he[ii].alpha;  // the level-0 step
-        if (best < 0 && d0 <= dmin) {
-          best = 0;
-          best_err = ho[0];
-          h.flags |= PE_FLAG_NOT_CONVERGED;
-        }
-        if (best >= 0) {
-          // a residual block that vanished exactly: the Krylov space is invariant
-          if (ho[2 * ns] == 0.0 && ho[2 * ns + 1] > 0.0) h.flags |= PE_FLAG_BREAKDOWN;
-          // local order p of the estimate, err ~ delta^p, from two squaring levels
-          // (their steps differ by 2); only where both are well above rounding
-          const int lo = best < ns ? best : best - 1;
-          if (lo >= 0) {
-            const double e_lo = ho[2 * lo], e_hi = ho[2 * (lo + 1)];
-            if (std::isfinite(e_hi) && e_lo > 1e-6 * best_lim && e_hi > 2.0 * e_lo)
-              h.pexp = std::min(40.0, std::max(2.0, std::log2(e_hi / e_lo)));
-          }
+                    "err %.3e |y| %.3e\n", idx[ii], guard, trial, k, h.tau, std::ldexp(he[ii].alpha, k), h.N, h.bw,
+                    h.nrm, ho[2 * k], ho[2 * k + 1]);
+        pe::StepIn in{};
+        in.nsq = ns;
+        in.est = ho;
+        in.alpha = he[ii].alpha;
+        in.tol = p.tol;
+        in.ref = h.ref;
+        in.tspan = h.Tspan;
+        in.dmin = 1e-13 * h.Tspan;
+        in.krylov_steps = p.krylov_steps;
+        in.pexp = h.pexp;
+        const pe::StepOut o = pe::step_decide(in);
+        h.flags |= o.flags;
+        h.pexp = o.pexp;
+        if (o.action == pe::kStepAccept) {
           h.accepted = true;
           h.pending = false;
-          h.level = best;
-          h.rho = best_lim > 0 ? best_err / best_lim : 0.0;
-          h.dtry = (best == ns) ? h.dtry : std::ldexp(he[ii].alpha, best);
-          h.resid = std::max(h.resid, best_err * h.dtry);
-          if (best < ns) h.rejected += 1;
-        } else {
+          h.level = o.level;
+          h.rho = o.rho;
+          h.dtry = o.step;
+          h.resid = std::max(h.resid, o.err * h.dtry);
+          if (o.level < ns) h.rejected += 1;
+        } else if (o.action == pe::kStepReject) {
           ++h.rejected;
-          const double err = ho[0], yn = ho[1];
-          const double lim = p.tol * std::max(h.ref, yn) / h.Tspan;
-          const double rho = std::isfinite(err) ? err / lim : 1e30;
-          const double ex = 1.0 / std::max(2.0, probs[idx[ii]].krylov_steps / 3.0);
-          h.dtry = d0 * std::min(0.5, std::max(0.05, 0.9 * std::pow(rho, -ex)));
+          h.dtry = o.step;
+        } else {
+          h.pending = false;
+          h.stop = true;
         }
       }
     }
@@ -948,6 +936,13 @@ pe_status march_batch(pe_ctx* ctx, const pe_problem* probs, const int* idx, int 
       d.outcol = nullptr;
       if (!d.active) continue;
       h.steps += d.l;
+      if (h.stop) {
+        // the march of this problem ends here: outputs not reached are NaN
+        for (; h.k < p.n_out; ++h.k)
+          pe::launch_fill(p.out + (int64_t)h.k * p.ldOut, p.op.n, 1, p.op.n, std::nan(""), st);
+        h.done = true;
+        continue;
+      }
       if (!h.accepted) {
         h.dlast = h.dtry;  // retry the cycle with the reduced step
         continue;
@@ -973,12 +968,7 @@ pe_status march_batch(pe_ctx* ctx, const pe_problem* probs, const int* idx, int 
       h.tau = landed ? h.target : h.tau + h.dtry;
       // a step clipped at an output time does not limit the next one
       if (!landed || h.dtry >= h.dlast) h.dlast = h.dtry;
-      {
-        // next step from the error model err ~ delta^p of this step (aiming at 0.95 of
-        // the limit); without an estimate of p, the order of a Krylov space of l steps
-        const double ex = h.pexp > 0.0 ? 1.0 / h.pexp : 1.0 / std::max(2.0, p.krylov_steps / 3.0);
-        h.dgrow = std::min(4.0, std::max(0.5, 0.95 * std::pow(std::max(h.rho, 1e-30), -ex)));
-      }
+      h.dgrow = pe::step_growth(h.rho, h.pexp, p.krylov_steps);
       h.xzero = false;
       ++h.cycles;
       if (d.outcol) {
@@ -1473,6 +1463,40 @@ pe_status pe_superpose(pe_ctx* ctx, const double* u0, const double* const* v, in
   HCK(hipGetLastError());
   HCK(hipStreamSynchronize(st));
   return PE_OK;
+}
+
+// ---- host-only decision rules (paraexp_policy.h) -----------------------------------
+void pe_policy_step(const pe_step_trial* t, pe_step_decision* out) {
+  if (!t || !out || !t->est || t->nsq < 0) return;
+  pe::StepIn in{};
+  in.nsq = t->nsq;
+  in.est = t->est;
+  in.alpha = t->alpha;
+  in.tol = t->tol;
+  in.ref = t->ref;
+  in.tspan = t->tspan;
+  in.dmin = t->dmin;
+  in.krylov_steps = t->krylov_steps;
+  in.pexp = t->pexp;
+  const pe::StepOut o = pe::step_decide(in);
+  out->action = o.action;
+  out->level = o.level;
+  out->flags = o.flags;
+  out->step = o.step;
+  out->rho = o.rho;
+  out->pexp = o.pexp;
+  out->err = o.err;
+}
+
+double pe_policy_step_growth(double rho, double pexp, int32_t krylov_steps) {
+  return pe::step_growth(rho, pexp, krylov_steps);
+}
+
+int32_t pe_policy_reorth_skip(const double* R, const double* Rn, int32_t bw, double kappa) {
+  if (!R || !Rn || bw < 1 || bw > 32) return 0;
+  for (int b = 0; b < bw; ++b)
+    if (!pe::reorth_column_ok(R, Rn, bw, b, kappa)) return 0;
+  return 1;
 }
 
 }  // extern "C"

@@ -163,7 +163,7 @@ def config_c1(n: int = 256) -> Problem:
     G = np.outer(np.sin(2 * np.pi * x), np.cos(4 * np.pi * ts))
     return Problem(n=n, coeffs=ade_coeffs(n, 1.0, 1e-2), u0=u0, t0=0.0, t1=1.0,
                    t_samples=ts, G=G, t_out=np.arange(1, 33) / 32.0, shift=True,
-                   krylov_steps=30, rank_max=8, q_max=32, tol=1e-12, svd_tol=1e-12,
+                   krylov_steps=30, rank_max=8, q_max=32, tol=1e-12, svd_tol=1e-13,
                    fit_tol=1e-13, name="c1_ade_n256")
 
 
@@ -178,7 +178,7 @@ def config_c2(n: int = 8192, seed: int = 2, krylov_steps: int = 60, s: int = 256
     return Problem(n=n, coeffs=ade_coeffs(n, 1.0, 1e-3), u0=u0, t0=0.0, t1=1.0,
                    t_samples=ts, G=g_at(ts), t_out=np.arange(1, n_out + 1) / n_out,
                    shift=True, krylov_steps=krylov_steps, rank_max=16, q_max=32, tol=tol,
-                   svd_tol=1e-12, fit_tol=1e-13, name=f"c2_ade_n{n}")
+                   svd_tol=1e-13, fit_tol=1e-13, name=f"c2_ade_n{n}")
 
 
 def c2_source(n: int = 8192, seed: int = 2):
@@ -220,7 +220,7 @@ def config_c4(count: int = 512, seed: int = 4, n_lo: int = 512, n_hi: int = 1638
                            u0=u0, t0=0.0, t1=1.0, t_samples=ts, G=g_at(ts),
                            t_out=np.arange(1, 33) / 32.0, shift=True,
                            krylov_steps=int(ls[i]), rank_max=16, q_max=32, tol=tol,
-                           svd_tol=1e-12, fit_tol=1e-13, name=f"c4_{i}"))
+                           svd_tol=1e-13, fit_tol=1e-13, name=f"c4_{i}"))
     return out
 
 
@@ -289,4 +289,4 @@ def random_ade_problem(seed: int, n: int, modes: int = 3, deg: int = 4, s: int =
     t_out = np.concatenate([t_out, [T]])
     return Problem(n=n, coeffs=coeffs, u0=u0, t0=0.0, t1=T, t_samples=ts, G=G, t_out=t_out,
                    shift=shift, krylov_steps=krylov_steps, rank_max=16, q_max=24, tol=tol,
-                   svd_tol=1e-12, fit_tol=1e-13, name=f"rand{seed}_n{n}")
+                   svd_tol=1e-13, fit_tol=1e-13, name=f"rand{seed}_n{n}")

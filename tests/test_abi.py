@@ -9,11 +9,18 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "paraexp.h")
+INCLUDE = os.path.join(ROOT, "include")
 
 
 def declared_functions():
-    text = open(HEADER).read()
-    return sorted(set(re.findall(r"^(?:pe_status|const char\*)\s+(pe_[a-z_]+)\s*\(", text, re.M)))
+    """Every function declared in include/*.h (return type at the start of the line)."""
+    names = set()
+    for f in sorted(os.listdir(INCLUDE)):
+        if f.endswith(".h"):
+            text = open(os.path.join(INCLUDE, f)).read()
+            names |= set(re.findall(r"^(?:pe_status|const char\*|void|double|int32_t)\s+(pe_[a-z_0-9]+)\s*\(",
+                                    text, re.M))
+    return sorted(names)
 
 
 def test_library_exports_every_declared_symbol():

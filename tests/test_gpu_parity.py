@@ -275,3 +275,61 @@ def test_smallest_grids_and_sample_counts(ctx, n, s):
     outs, reps = ctx.solve_batch([p])
     assert rel(gpu_out(outs[0]), ref) < FP64_TOL, reps[0]
     assert reps[0]["flags"] & 2, reps[0]  # the space is exhausted: PE_FLAG_BREAKDOWN
+
+
+# ------------------------------------------------------------------ truncation between the floors
+def test_compress_keeps_singular_values_between_the_floors(ctx):
+    """A sample matrix whose 4th and 5th singular values (5e-13, 2e-13 of sigma_1) lie
+    between the truncation floor (1e-14 sigma_1) and 1e-12 |G|_F: with svd_tol = 1e-13
+    the truncation rule (energy, floor, clusters; Sec. 2.1 eq. 2.3) keeps both, on the GPU
+    as in the oracle."""
+    rng = np.random.default_rng(17)
+    n, s = 1024, 40
+    sig = np.array([1.0, 0.3, 0.1, 5e-13, 2e-13])
+    Uq, _ = np.linalg.qr(rng.standard_normal((n, 5)))
+    ts = synth.chebyshev_lobatto(0.0, 0.5, s)
+    # time factors: orthonormalised smooth functions of t (so p(t) is fitted well)
+    Tm = np.stack([np.cos((k + 1) * ts) + 0.1 * k * ts for k in range(5)], axis=1)
+    Vq, _ = np.linalg.qr(Tm)
+    G = (Uq * sig) @ Vq.T
+    p = synth.Problem(n=n, coeffs=synth.ade_coeffs(n, 1.0, 1e-2), u0=np.zeros(n), t0=0.0, t1=0.5,
+                      t_samples=ts, G=G, t_out=np.array([0.5]), shift=False, krylov_steps=10,
+                      rank_max=16, q_max=32, tol=1e-10, svd_tol=1e-13, fit_tol=1e-10)
+    mdl = oracle.window_model(p)
+    assert mdl["m"] == 5
+    res = ctx.compress(p)
+    assert res["m"] == 5, res["sigma"][:8]
+    assert np.allclose(res["sigma"][:3], sig[:3], rtol=1e-12, atol=0)
+    assert np.allclose(res["sigma"][3:5], sig[3:5], rtol=1e-2, atol=0)
+    U = res["U"].cpu().numpy().T
+    assert np.max(np.abs(U.T @ U - np.eye(5))) < 1e-12
+    # the retained space is the oracle's (projector distance, well separated from sigma_6)
+    Po, Pg = mdl["U"] @ mdl["U"].T, U @ U.T
+    assert np.linalg.norm(Po - Pg, 2) < 1e-2
+
+
+# ------------------------------------------------------------------ failure handling
+def test_nonfinite_projection_stops_only_that_problem(ctx):
+    """One problem of a batch has stencil coefficients near the top of the double range:
+    its Krylov block norms overflow and the projected matrix is not finite.  Its march
+    stops at once (PE_FLAG_NOT_CONVERGED, outputs NaN), and the other problem of the same
+    batch is solved as usual."""
+    a = synth.random_ade_problem(41, 120, n_out=4)
+    b = synth.random_ade_problem(42, 96, n_out=3, shift=False)
+    b.coeffs = b.coeffs * 1e290
+    mdl = oracle.window_model(a)
+    ref, _ = oracle.solve_window(a, "dense", model=mdl)
+    outs, reps = ctx.expaction_batch([a, b], [mdl["U"].T, np.zeros((0, b.n))], [mdl["Pi"], np.zeros((0, 0))])
+    assert rel(gpu_out(outs[0]), ref) < FP64_TOL, reps[0]
+    assert not reps[0]["flags"] & 1
+    assert reps[1]["flags"] & 1, reps[1]
+    assert np.all(np.isnan(gpu_out(outs[1])))
+    assert reps[1]["cycles"] <= 1
+
+
+def test_repeated_solve_is_bitwise_identical(ctx):
+    p = synth.config_c1()
+    o1, r1 = ctx.solve_batch([p])
+    o2, r2 = ctx.solve_batch([p])
+    assert r1 == r2
+    assert np.array_equal(gpu_out(o1[0]), gpu_out(o2[0]))

@@ -295,8 +295,13 @@ def test_wr_burgers_converges_to_rk4_solution(jacobian, P):
                                         fit_tol=1e-12)
     U, hist = oracle.wr_burgers(bp, "dense", return_history=True)
     h = 1.0 / n
-    A = synth.burgers_diffusion_coeffs(n, bp.nu)
-    f = lambda uu: oracle.apply_stencil(A, uu) + oracle.burgers_nonlinear(uu, h)
+
+    def f(uu):
+        # right-hand side of the semi-discrete Burgers system written out here, not taken
+        # from the oracle: nu (u_{i+1} - 2 u_i + u_{i-1}) / h^2 - u_i (u_{i+1} - u_{i-1}) / (2h)
+        up, um = np.concatenate([uu[1:], uu[:1]]), np.concatenate([uu[-1:], uu[:-1]])
+        return bp.nu * (up - 2.0 * uu + um) / h**2 - uu * (up - um) / (2.0 * h)
+
     u = bp.u0.copy()
     dt = 1e-5
     for _ in range(int(round(bp.T / dt))):
@@ -314,3 +319,132 @@ def test_wr_spectral_picard_matches_dense():
     a = oracle.wr_burgers(bp, "dense")
     b = oracle.wr_burgers(bp, "spectral")
     assert rel(a, b) < 1e-11
+
+
+# ---------------------------------------------------------------- Burgers nonlinearity and Jacobian
+@pytest.mark.parametrize("n", [16, 64, 256, 1000])
+def test_burgers_nonlinear_closed_form_on_a_sine(n):
+    """N(u)_i = -u_i (u_{i+1} - u_{i-1}) / (2h) on u = sin(2 pi x): the central difference of
+    a sine is exact up to the factor sin(2 pi h) / (2 pi h), so
+    N_i = -sin(2 pi x_i) cos(2 pi x_i) sin(2 pi h) / h (Sec. 4.1, eq. burgersEq discretised)."""
+    h = 1.0 / n
+    x = np.arange(n) / n
+    got = oracle.burgers_nonlinear(np.sin(2 * np.pi * x), h)
+    want = -np.sin(2 * np.pi * x) * np.cos(2 * np.pi * x) * np.sin(2 * np.pi * h) / h
+    assert np.max(np.abs(got - want)) <= 1e-12 * np.max(np.abs(want))
+    # block input: column by column, a phase-shifted sine in the second column
+    U = np.stack([np.sin(2 * np.pi * x), np.sin(2 * np.pi * x + 0.7)], axis=1)
+    G = oracle.burgers_nonlinear(U, h)
+    want2 = -np.sin(2 * np.pi * x + 0.7) * np.cos(2 * np.pi * x + 0.7) * np.sin(2 * np.pi * h) / h
+    assert np.max(np.abs(G[:, 0] - want)) <= 1e-12 * np.max(np.abs(want))
+    assert np.max(np.abs(G[:, 1] - want2)) <= 1e-12 * np.max(np.abs(want2))
+
+
+def _sawtooth(xi, eps=0.1, kmax=100):
+    """Smoothed sawtooth of Sec. 4.1 (eq. modifiedSawtooth) and its exact derivative:
+    u = 1/2 - sum_k sin(2 pi k xi) Phi_k / (pi k), Phi_k = (pi k eps/2) / sinh(pi k eps/2)."""
+    k = np.arange(1, kmax + 1)[:, None]
+    a = np.pi * k * eps / 2
+    phi = a / np.sinh(a)
+    u = 0.5 - np.sum(np.sin(2 * np.pi * k * xi) * phi / (np.pi * k), axis=0)
+    ux = -np.sum(2 * np.cos(2 * np.pi * k * xi) * phi, axis=0)
+    return u, ux
+
+
+def test_burgers_nonlinear_second_order_on_the_smoothed_sawtooth():
+    """The advective discretisation is consistent with -u u_x to second order: on the
+    paper's manufactured solution (Sec. 4.1, at t = 0.3) halving h cuts the error by 4."""
+    errs = []
+    for n in (256, 512, 1024, 2048):
+        x = np.arange(n) / n
+        u, ux = _sawtooth(x - 0.5 * 0.3 + 0.5)
+        errs.append(np.max(np.abs(oracle.burgers_nonlinear(u, 1.0 / n) - (-u * ux))))
+    ratios = np.array(errs[:-1]) / np.array(errs[1:])
+    assert np.all(np.abs(ratios - 4.0) < 0.1), ratios
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_burgers_jacobian_is_the_derivative_of_the_nonlinearity(seed):
+    """J(u) v = (N(u + e v) - N(u - e v)) / (2e) for every direction v.  N is quadratic, so
+    the central difference is exact apart from rounding (Sec. 2.3, eq. jacobian).  The
+    product J v is formed here from the three stencil rows by explicit indexing."""
+    rng = np.random.default_rng(seed)
+    n = 96
+    h = 1.0 / n
+    u = rng.standard_normal(n)
+    J = oracle.burgers_jacobian(u, h)
+    assert J.shape == (3, n)
+    for _ in range(3):
+        v = rng.standard_normal(n)
+        Jv = np.array([J[0, i] * v[i - 1] + J[1, i] * v[i] + J[2, i] * v[(i + 1) % n] for i in range(n)])
+        e = 1e-3
+        fd = (oracle.burgers_nonlinear(u + e * v, h) - oracle.burgers_nonlinear(u - e * v, h)) / (2 * e)
+        assert rel(Jv, fd) < 1e-10
+    # the dense Jacobian built entry by entry from partial derivatives of N_i
+    D = np.zeros((n, n))
+    for i in range(n):
+        for j in range(n):
+            ej = np.zeros(n)
+            ej[j] = 1.0
+            D[i, j] = (oracle.burgers_nonlinear(u + ej, h)[i] - oracle.burgers_nonlinear(u - ej, h)[i]) / 2.0
+    assert rel(oracle.dense_operator(n, J), D) < 1e-12
+
+
+# ---------------------------------------------------------------- truncation rule (reading #8)
+def _matrix_with_spectrum(sig, n=200, s=40, seed=3):
+    rng = np.random.default_rng(seed)
+    Uq, _ = np.linalg.qr(rng.standard_normal((n, len(sig))))
+    Vq, _ = np.linalg.qr(rng.standard_normal((s, len(sig))))
+    return (Uq * np.asarray(sig)) @ Vq.T
+
+
+def _rank_by_eckart_young(sig, svd_tol):
+    """Brute force: the smallest r whose best rank-r approximation (Eckart-Young) leaves
+    a Frobenius error <= svd_tol ||G||_F, from the singular values by direct summation."""
+    fro = math.sqrt(sum(v * v for v in sig))
+    for r in range(len(sig) + 1):
+        if math.sqrt(sum(v * v for v in sig[r:])) <= svd_tol * fro:
+            return r
+    return len(sig)
+
+
+@pytest.mark.parametrize("svd_tol", [0.3, 3e-2, 1e-3, 1e-6, 1e-9])
+def test_truncation_energy_rule_is_eckart_young(svd_tol):
+    sig = [3.0, 1.0, 0.4, 1e-2, 3e-4, 1e-5, 2e-7, 5e-9, 1e-10]
+    G = _matrix_with_spectrum(sig)
+    m, U, C, got_sig, tail, flags = oracle.compress(G, svd_tol, 30)
+    assert m == _rank_by_eckart_young(sig, svd_tol)
+    # the reported tail is the relative Frobenius error of the kept factorisation
+    assert abs(np.linalg.norm(G - U @ C) / np.linalg.norm(G) - tail) < 1e-13
+
+
+def test_truncation_keeps_a_cluster_whole():
+    """sigma_3 and sigma_4 differ by 4e-13 sigma_1: a cut between them by the energy rule
+    alone (m = 3) is widened to keep both (reading #8)."""
+    sig = [1.0, 0.5, 0.1, 0.1 - 4e-13, 1e-6, 1e-7]
+    G = _matrix_with_spectrum(sig)
+    fro = math.sqrt(sum(v * v for v in sig))
+    svd_tol = 0.09                                  # tail after 3 is 0.0887 ||G||_F
+    assert _rank_by_eckart_young(sig, svd_tol) == 3
+    m, *_ = oracle.compress(G, svd_tol, 30)
+    assert m == 4
+    # a gap of 1e-9 sigma_1 is not a cluster
+    sig2 = [1.0, 0.5, 0.1, 0.1 - 1e-9, 1e-6, 1e-7]
+    m2, *_ = oracle.compress(_matrix_with_spectrum(sig2), svd_tol, 30)
+    assert m2 == 3
+    assert fro > 0
+
+
+def test_truncation_floor_and_cap():
+    """Singular values at or below 1e-14 sigma_1 are never kept, whatever svd_tol asks;
+    values just above it are; rank_max caps m and sets the flag."""
+    sig = [1.0, 0.3, 5e-13, 2e-13, 5e-15]
+    G = _matrix_with_spectrum(sig)
+    m, *_ = oracle.compress(G, 0.0, 30)
+    assert m == 4
+    m, *_rest, flags = oracle.compress(G, 0.0, 2)
+    assert m == 2 and flags & 4
+    # svd_tol = 1e-13 of ||G||_F (~1.04): both 5e-13 and 2e-13 are needed
+    assert _rank_by_eckart_young(sig, 1e-13) == 4
+    m, *_ = oracle.compress(G, 1e-13, 30)
+    assert m == 4
