@@ -48,6 +48,8 @@ def main():
                     help="Paraexp windows per solve (Sec. 2.2): the window subproblems run as one batch "
                          "(s / P samples each) and u = u0 + sum_j v_j is superposed; 1 = one window")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="skip the other precision and the single-window split (same inputs, same process)")
     ap.add_argument("--roofline-kernel", default=None, choices=["block_update", "block_proj"],
                     help="kernel family of the roofline figure (default: the one with the most GPU time, "
                          "block_update for one window, block_proj for the window split)")
@@ -72,51 +74,76 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    prec = pe.PE_FP64 if args.precision == "fp64" else pe.PE_MIXED
-    # the FP32-stored basis puts a floor of ~1e-9 under the residual estimate, so the
-    # mixed path runs at tol 1e-8 (its accuracy target is 1e-7 against the FP64 oracle)
-    tol = 1e-12 if args.precision == "fp64" else 1e-8
-    probs = [synth.config_c2(n=args.n, seed=2 + i, tol=tol) for i in range(max(1, args.batch))]
-    prob = probs[0]
+    import oracle
+
     P = max(1, args.windows)
     if args.roofline_kernel is None:
         args.roofline_kernel = "block_proj" if P > 1 else "block_update"
-    if P > 1:
-        # each instance as P Paraexp windows, all windows of all instances in one batch
-        subs = []
-        for i, pr in enumerate(probs):
-            _, g_at = synth.c2_source(args.n, 2 + i)
-            subs += synth.split_windows(pr, P, g_at, s=max(2, pr.s // P))
-    else:
-        subs = probs
     ctx = pe.Context(0)
-    staged = ctx.prepare(subs, prec)
+    refs = {}
 
-    def solve():
-        outs, reps = ctx.solve_prepared(staged)
-        if P > 1:
-            outs = [ctx.superpose(pr.u0, outs[i * P:(i + 1) * P]) for i, pr in enumerate(probs)]
-        return outs, reps
-    torch.cuda.synchronize()
-    for i in range(args.warmup):
-        tw = time.perf_counter()
-        solve()
-        print(f"warmup {i}: {time.perf_counter() - tw:.3f} s", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    # per-launch HIP-event timing of the dominant kernel family, on the solve's stream
-    ctx.profile_enable(args.roofline_kernel)
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        ts = time.perf_counter()
-        outs, reps = solve()
-        print(f"step {i}: {time.perf_counter() - ts:.3f} s cycles={reps[0]['cycles']} "
-              f"rejected={reps[0]['rejected']}", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    ms = 1e3 * elapsed / max(args.steps, 1)
-    prof = ctx.profile_read()
+    def run(precision, windows, steps, warmup, profile):
+        """Time `steps` solves of the workload at one precision and window split; returns
+        the figures of that run (accuracy against the oracle checked outside the timing)."""
+        prec = pe.PE_FP64 if precision == "fp64" else pe.PE_MIXED
+        # the FP32-stored basis puts a floor of ~1e-9 under the residual estimate, so the
+        # mixed path runs at tol 1e-8 (its accuracy target is 1e-7 against the FP64 oracle)
+        tol = 1e-12 if precision == "fp64" else 1e-8
+        probs = [synth.config_c2(n=args.n, seed=2 + i, tol=tol) for i in range(max(1, args.batch))]
+        if windows > 1:
+            # each instance as P Paraexp windows, all windows of all instances in one batch
+            subs = []
+            for i, pr in enumerate(probs):
+                _, g_at = synth.c2_source(args.n, 2 + i)
+                subs += synth.split_windows(pr, windows, g_at, s=max(2, pr.s // windows))
+        else:
+            subs = probs
+        staged = ctx.prepare(subs, prec)
+
+        def solve():
+            outs, reps = ctx.solve_prepared(staged)
+            if windows > 1:
+                outs = [ctx.superpose(pr.u0, outs[i * windows:(i + 1) * windows]) for i, pr in enumerate(probs)]
+            return outs, reps
+        torch.cuda.synchronize()
+        for i in range(warmup):
+            tw = time.perf_counter()
+            solve()
+            print(f"[{precision} P={windows}] warmup {i}: {time.perf_counter() - tw:.3f} s", file=sys.stderr,
+                  flush=True)
+        torch.cuda.synchronize()
+        if profile:  # per-launch HIP-event timing of the dominant kernel family, on the solve's stream
+            ctx.profile_enable(args.roofline_kernel)
+        t0 = time.perf_counter()
+        for i in range(steps):
+            ts = time.perf_counter()
+            outs, reps = solve()
+            print(f"[{precision} P={windows}] step {i}: {time.perf_counter() - ts:.3f} s "
+                  f"cycles={reps[0]['cycles']} rejected={reps[0]['rejected']}", file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        prof = ctx.profile_read() if profile else None
+        if profile:
+            ctx.profile_enable(None)
+        err = 0.0
+        for i, pr in enumerate(probs):
+            key = (args.n, 2 + i)
+            if key not in refs:
+                tc = time.perf_counter()
+                refs[key] = (oracle.solve_window(pr, "spectral")[0], time.perf_counter() - tc)
+            ref = refs[key][0]
+            if windows > 1:  # the superposed u(t_k) = u0 + v(t_k)
+                ref = pr.u0[:, None] + ref
+            got = outs[i].detach().cpu().numpy().T
+            err = max(err, float(np.linalg.norm(got - ref) / np.linalg.norm(ref)))
+        return {"solves_per_s": len(probs) * steps / elapsed, "ms_per_step": 1e3 * elapsed / max(steps, 1),
+                "rel_l2_vs_oracle": err, "report": reps[0], "prof": prof, "probs": probs}
+
+    main_run = run(args.precision, P, args.steps, args.warmup, True)
+    probs = main_run["probs"]
+    prob = probs[0]
+    prof = main_run["prof"]
     launches, k_ms, k_bytes, k_flops = prof["launches"], prof["ms"], prof["bytes"], prof["flops"]
-    ctx.profile_enable(None)
     roof = None
     # the counter record of the single-window split covers three whole restart cycles,
     # whose launch mix is the solve's; with several windows the early cycles carry every
@@ -130,20 +157,25 @@ def main():
                 "launches": launches, "avg_launch_us": 1e3 * k_ms / launches,
                 "algorithmic_bytes_per_launch": k_bytes / launches,
                 "flops_per_launch": k_flops / launches}
-    rep = reps[0]
+    rep = main_run["report"]
+    err = main_run["rel_l2_vs_oracle"]
 
-    # accuracy against the CPU oracle (test infrastructure, not part of the timed path)
-    import oracle
-    err, t_oracle = 0.0, None
-    for i, pr in enumerate(probs):
-        tc = time.perf_counter()
-        ref, _ = oracle.solve_window(pr, "spectral")
-        if i == 0:
-            t_oracle = time.perf_counter() - tc
-        if P > 1:  # the superposed u(t_k) = u0 + v(t_k)
-            ref = pr.u0[:, None] + ref
-        got = outs[i].detach().cpu().numpy().T
-        err = max(err, float(np.linalg.norm(got - ref) / np.linalg.norm(ref)))
+    # the same inputs at the other precision and as a single window (same process)
+    compare = {}
+    if not args.no_compare:
+        other = "mixed" if args.precision == "fp64" else "fp64"
+        cmp_steps = max(1, min(args.steps, 2))
+        o = run(other, P, cmp_steps, 1, False)
+        compare[f"{other}_paraexp{P}" if P > 1 else other] = {
+            k: o[k] for k in ("solves_per_s", "ms_per_step", "rel_l2_vs_oracle", "report")}
+        fp64_sps = main_run["solves_per_s"] if args.precision == "fp64" else o["solves_per_s"]
+        mixed_sps = o["solves_per_s"] if args.precision == "fp64" else main_run["solves_per_s"]
+        compare["speedup_mixed_over_fp64"] = mixed_sps / fp64_sps
+        if P > 1:
+            w1 = run(args.precision, 1, cmp_steps, 1, False)
+            compare[f"{args.precision}_single_window"] = {
+                k: w1[k] for k in ("solves_per_s", "ms_per_step", "rel_l2_vs_oracle", "report")}
+    t_oracle = refs[(args.n, 2)][1]
 
     cpu = None
     if not args.no_cpu:
@@ -165,16 +197,16 @@ def main():
 
     line = {
         "metric": "Paraexp exp-action solves/s + HBM GB/s, mixed vs FP64 at 1e-7 rel L2",
-        "value": len(probs) * args.steps / elapsed,
+        "value": main_run["solves_per_s"],
         "unit": "solves/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms,
+        "ms_per_step": main_run["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if prec == pe.PE_FP64 else "f64+f32basis",
+        "dtype": "f64" if args.precision == "fp64" else "f64+f32basis",
         "data": "synthetic",
         "config": {"workload": f"c2_advection_diffusion_n{args.n}_krylov60_s256_nout32"
                                + (f"_paraexp{P}" if P > 1 else "")
@@ -185,6 +217,7 @@ def main():
         "rel_l2_vs_oracle": err,
         "report": rep,
         "roofline": roof,
+        "compare": compare,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -1,0 +1,62 @@
+// Wave and workgroup reductions and the cross-workgroup hand-off shared by the gfx950
+// kernels of the Paraexp library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace pe {
+
+// DPP data movement of a double (both 32-bit halves); rows outside row_mask receive 0
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_move(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROW_MASK, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROW_MASK, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum over the 64 lanes of a wave, returned to every lane.  Within each row of 16 lanes:
+// quad_perm [1,0,3,2], quad_perm [2,3,0,1], row_ror 4, row_ror 8; then row_bcast 15 into
+// rows 1 and 3 and row_bcast 31 into rows 2 and 3, which leaves the total in lane 63.
+__device__ __forceinline__ double wave_sum(double v) {
+  v += dpp_move<0xB1, 0xF>(v);
+  v += dpp_move<0x4E, 0xF>(v);
+  v += dpp_move<0x124, 0xF>(v);
+  v += dpp_move<0x128, 0xF>(v);
+  v += dpp_move<0x142, 0xA>(v);
+  v += dpp_move<0x143, 0xC>(v);
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+  return __hiloint2double(hi, lo);
+}
+
+// sum over a workgroup whose size is a multiple of 64; `red` holds >= 16 doubles of LDS
+__device__ __forceinline__ double block_sum(double v, double* red) {
+  v = wave_sum(v);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  __syncthreads();
+  if (l == 0) red[w] = v;
+  __syncthreads();
+  double t = 0.0;
+  const int nw = blockDim.x >> 6;
+  for (int i = 0; i < nw; ++i) t += red[i];
+  return t;
+}
+
+// Cross-workgroup hand-off inside a kernel: data for the last workgroup is stored
+// write-through at agent scope, every thread waits for its stores, then thread 0 bumps
+// the counter.  The last workgroup invalidates its L2 view (agent-scope acquire) before
+// reading.  No L2 write-back is needed, unlike a full __threadfence per workgroup.
+__device__ __forceinline__ void st_agent(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ bool arrive_last(unsigned* counter, unsigned expected, int* flag) {
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (threadIdx.x == 0) *flag = (atomicAdd(counter, 1u) == expected - 1);
+  __syncthreads();
+  const bool last = *flag != 0;
+  if (last) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  return last;
+}
+
+}  // namespace pe

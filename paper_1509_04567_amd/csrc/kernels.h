@@ -57,6 +57,19 @@ void launch_form_u(const double* Q, int bwc, int64_t n, const int* sel, int r, c
 void launch_fit(const double* A, int s, const int* perm, int m, const double* ts, double t0, double t1, int qcap,
                 double fit_tol, double* Pi, int ldPi, double* work, double* info, hipStream_t st);
 
+// column-pivoted Gram-Schmidt range finder of the shifted samples (compress.hip):
+// Q (n x k, ld n) orthonormal, R = Q^T G (k x s, ld kcap); k and the squared norms of G
+// and of the residual are in the state block (read back with read_cp_state)
+constexpr int kCpMaxK = 128;     // column cap of the range finder
+constexpr int kCpMaxRw = 4096;   // rows per chunk at most
+constexpr double kCpFloor = 1e-15;  // stop when |residual|_F <= max(kCpFloor, 2 k eps) |G|_F
+void cp_geometry(int64_t n, int s, int& rw, int& P, int& CG);
+size_t cp_part_doubles(int64_t n, int s);
+size_t cp_state_bytes();
+void launch_cp_range(int64_t n, int s, int kcap, const double* G, double* A, double* Q, double* R, double* part,
+                     double* cn2, double* rrow, unsigned* cnt, void* state, hipStream_t st);
+void read_cp_state(const void* host_copy, int* k, double* gfro2, double* res2);
+
 // waveform relaxation (Burgers): per-point operator and source samples of one window
 void launch_wr_source(int64_t n, int s, double h, double nu, const double* U, int jacobian, double w_end, double w_in,
                       double* coef, double* G, hipStream_t st);

@@ -437,23 +437,29 @@ pe_status compress_one(pe_ctx* ctx, const pe_problem& p, double* U, int64_t ldU,
                        CompressOut& res, hipStream_t st) {
   const int64_t n = p.op.n;
   const int s = p.s;
-  const int bwc = std::min(8, s);
-  const int nblk = (s + bwc - 1) / bwc;
-  const int S_ = nblk * bwc;
   const int qcap = std::min(p.q_max, s);
-  BlockCaps caps = block_caps(n, bwc, nblk, S_, S_);
+  // columns of the range finder: the numerical rank of the samples, up to kCpMaxK (beyond
+  // that the residual's energy is reported in the dropped tail); none when nothing may
+  // be kept
+  const int kcap = p.rank_max == 0 ? 0 : (int)std::min<int64_t>({(int64_t)s, n, (int64_t)pe::kCpMaxK});
+  int cp_rw, cp_P, cp_CG;
+  pe::cp_geometry(n, s, cp_rw, cp_P, cp_CG);
   Carver cv;
-  const size_t o_coef = cv.take<double>(p.op.per_point ? 3 * (size_t)n : 3);
   const size_t o_lu0 = cv.take<double>(n);
   const size_t o_gh = cv.take<double>((size_t)n * s);
-  BlockOffsets bo = carve_block(cv, caps, false);
-  const size_t o_desc = cv.take<ProbDev>(1);
-  const size_t o_rn = cv.take<double>(S_);
-  const size_t o_sel = cv.take<int>(S_);
-  const size_t o_A = cv.take<double>((size_t)s * S_);
-  const size_t o_J = cv.take<double>((size_t)S_ * S_);
-  const size_t o_sig = cv.take<double>(S_);
-  const size_t o_perm = cv.take<int>(S_);
+  const size_t o_res = cv.take<double>((size_t)n * s);
+  const size_t o_Q = cv.take<double>((size_t)n * std::max(1, kcap));
+  const size_t o_R = cv.take<double>((size_t)std::max(1, kcap) * s);
+  const size_t o_part = cv.take<double>(pe::cp_part_doubles(n, s));
+  const size_t o_cn2 = cv.take<double>(s);
+  const size_t o_rrow = cv.take<double>(s);
+  const size_t o_cnt = cv.take<unsigned>(1 + (size_t)cp_CG);
+  const size_t o_state = cv.take<char>(pe::cp_state_bytes());
+  const size_t o_sel = cv.take<int>(std::max(1, kcap));
+  const size_t o_A = cv.take<double>((size_t)s * std::max(1, kcap));
+  const size_t o_J = cv.take<double>((size_t)std::max(1, kcap) * std::max(1, kcap));
+  const size_t o_sig = cv.take<double>(std::max(1, kcap));
+  const size_t o_perm = cv.take<int>(std::max(1, kcap));
   const size_t o_info = cv.take<int>(4);
   const size_t o_ts = cv.take<double>(s);
   const size_t o_fw = cv.take<double>((size_t)s * qcap + (size_t)qcap * qcap + (size_t)32 * qcap + (size_t)32 * s);
@@ -461,7 +467,7 @@ pe_status compress_one(pe_ctx* ctx, const pe_problem& p, double* U, int64_t ldU,
   const size_t o_flag = cv.take<int>(4);
   pe_status stt = ensure_arena(ctx, cv.off);
   if (stt != PE_OK) return stt;
-  stt = ensure_pinned(ctx, sizeof(double) * (4 * (size_t)S_ + 64));
+  stt = ensure_pinned(ctx, std::max(sizeof(double) * (4 * (size_t)std::max(1, kcap) + 64), pe::cp_state_bytes()));
   if (stt != PE_OK) return stt;
   char* base = ctx->arena;
   double* hp = (double*)ctx->pinned;
@@ -484,57 +490,31 @@ pe_status compress_one(pe_ctx* ctx, const pe_problem& p, double* U, int64_t ldU,
   } else {
     pe::launch_add_column(n, s, p.G, p.ldG, nullptr, Gh, n, st);
   }
-  // S2-S3: G^ = Q R by block CGS2 + TSQR in blocks of bwc columns
-  ProbDev d{};
-  d.n = n;
-  d.per_point = p.op.per_point;
-  if (!p.op.per_point) std::memcpy(d.c3, p.op.coeffs, 3 * sizeof(double));
-  d.coef = p.op.per_point ? p.op.coeffs : nullptr;
-  bind_block(d, base, bo, false, nblk);
-  d.Xg = Gh;
-  d.ldXg = n;
-  d.m = s;
-  d.l = nblk;
-  d.active = 1;
-  d.ldH = S_;
-  d.dep_tol = kDepTolCompress;
-  set_geometry(d, n, bwc);
-  if (!geometry_fits(d, caps, nblk)) return pe_fail(ctx, PE_ERR_UNSUPPORTED, "compression geometry exceeds workspace");
-  ProbDev* dd = (ProbDev*)(base + o_desc);
-  HCK(hipMemsetAsync(d.cnt, 0, caps.cnt * sizeof(unsigned), st));
-  HCK(hipMemsetAsync(d.H, 0, caps.H * sizeof(double), st));
-  HCK(hipMemcpyAsync(dd, &d, sizeof(ProbDev), hipMemcpyHostToDevice, st));
-  const size_t smem_p = proj_smem(d), smem_u = update_smem(d);
-  for (int j = 0; j < nblk; ++j) {
-    run_block_step(ctx, dd, 1, ((j + pe::kSlotGroup - 1) / pe::kSlotGroup) * d.Cp, smem_p, d.Cu, smem_u, j, j,
-                   pe::MODE_GIVEN, 0, step_cost(n, bwc, j, 8), st);
-    pe::launch_block_commit(dd, 1, (int)((n * bwc + 255) / 256), j, 0, st);
-  }
-  // significant rows of R
-  double* R = d.H;
-  pe::launch_row_norms(R, S_, S_, s, (double*)(base + o_rn), st);
-  HCK(hipMemcpyAsync(hp, base + o_rn, sizeof(double) * S_, hipMemcpyDeviceToHost, st));
-  HCK(hipStreamSynchronize(st));
-  double fro2 = 0.0;
-  for (int i = 0; i < S_; ++i) fro2 += hp[i] * hp[i];
-  const double fro = std::sqrt(fro2);
-  // the rows of R that the QR did not deflate (a deflated column leaves a zero row)
-  std::vector<int> sel;
-  for (int i = 0; i < S_; ++i)
-    if (hp[i] > 1e-300 && hp[i] > 1e-17 * fro) sel.push_back(i);
   res.sigma.assign(s, 0.0);
   res.m = 0;
-  if (fro == 0.0 || sel.empty() || p.rank_max == 0) {
+  // S2-S3: range of G^ by column-pivoted Gram-Schmidt, R = Q^T G^ (k x s, ld kcap)
+  double* Qc = (double*)(base + o_Q);
+  double* R = (double*)(base + o_R);
+  pe::launch_cp_range(n, s, kcap, Gh, (double*)(base + o_res), Qc, R, (double*)(base + o_part),
+                      (double*)(base + o_cn2), (double*)(base + o_rrow), (unsigned*)(base + o_cnt), base + o_state, st);
+  HCK(hipGetLastError());
+  HCK(hipMemcpyAsync(hp, base + o_state, pe::cp_state_bytes(), hipMemcpyDeviceToHost, st));
+  HCK(hipStreamSynchronize(st));
+  int r = 0;
+  double gfro2 = 0.0, res2 = 0.0;
+  pe::read_cp_state(hp, &r, &gfro2, &res2);
+  if (gfro2 == 0.0 || r == 0) {  // a zero source, or nothing may be kept (rank_max = 0)
     res.sigma1 = 0.0;
-    res.svd_tail = fro == 0.0 ? 0.0 : 1.0;
-    if (fro > 0.0 && p.rank_max == 0) res.flags |= PE_FLAG_RANK_CAPPED;
+    res.svd_tail = gfro2 > 0.0 ? 1.0 : 0.0;
+    if (gfro2 > 0.0) res.flags |= PE_FLAG_RANK_CAPPED;
     return PE_OK;
   }
-  const int r = (int)sel.size();
+  std::vector<int> sel(r);
+  for (int i = 0; i < r; ++i) sel[i] = i;
   HCK(hipMemcpyAsync(base + o_sel, sel.data(), sizeof(int) * r, hipMemcpyHostToDevice, st));
   double* A = (double*)(base + o_A);
   double* J = (double*)(base + o_J);
-  pe::launch_jacobi_svd(R, S_, (int*)(base + o_sel), s, r, A, J, (double*)(base + o_sig), (int*)(base + o_perm),
+  pe::launch_jacobi_svd(R, kcap, (int*)(base + o_sel), s, r, A, J, (double*)(base + o_sig), (int*)(base + o_perm),
                         (int*)(base + o_info), st);
   std::vector<int> perm(r);
   HCK(hipMemcpyAsync(hp, base + o_sig, sizeof(double) * r, hipMemcpyDeviceToHost, st));
@@ -546,10 +526,10 @@ pe_status compress_one(pe_ctx* ctx, const pe_problem& p, double* U, int64_t ldU,
   // with dropped energy <= svd_tol |G^|_F; singular values <= kSigmaFloor sigma_1 are
   // never kept; a cut inside a cluster (|sigma_m - sigma_{m+1}| <= 1e-12 sigma_1) keeps
   // the cluster whole; m is capped at rank_max
-  double sfro2 = 0.0;
-  for (double v : sig) sfro2 += v * v;
-  const double gfro = std::sqrt(sfro2);
+  // (the energy left in the range finder's residual belongs to the dropped tail)
+  const double gfro = std::sqrt(gfro2);
   std::vector<double> tail(r + 1, 0.0);
+  tail[r] = std::sqrt(std::max(res2, 0.0));
   for (int i = r - 1; i >= 0; --i) tail[i] = std::sqrt(tail[i + 1] * tail[i + 1] + sig[i] * sig[i]);
   int m = r;
   for (int i = 0; i <= r; ++i)
@@ -568,8 +548,8 @@ pe_status compress_one(pe_ctx* ctx, const pe_problem& p, double* U, int64_t ldU,
   res.svd_tail = gfro > 0.0 ? tail[m] / gfro : 0.0;
   for (int i = 0; i < std::min(r, s); ++i) res.sigma[i] = sig[i];
   if (m == 0) return PE_OK;
-  // U = Q J[:, perm[0:m]]
-  pe::launch_form_u(d.V, bwc, n, (int*)(base + o_sel), r, J, (int*)(base + o_perm), m, U, ldU, st);
+  // U = Q J[:, perm[0:m]]  (Q column-major: blocks of width 1)
+  pe::launch_form_u(Qc, 1, n, (int*)(base + o_sel), r, J, (int*)(base + o_perm), m, U, ldU, st);
   // S4: Chebyshev fit of C = Sigma Z^T rows over the samples
   HCK(hipMemcpyAsync(base + o_ts, p.t_samples, sizeof(double) * s, hipMemcpyHostToDevice, st));
   pe::launch_fit(A, s, (int*)(base + o_perm), m, (double*)(base + o_ts), p.t0, p.t1, qcap, p.fit_tol, Pi, ldPi,
