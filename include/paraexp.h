@@ -153,6 +153,19 @@ pe_status pe_stencil_apply(pe_ctx* ctx, const pe_stencil* op, const double* X, i
 pe_status pe_compress(pe_ctx* ctx, const pe_problem* prob, double* U, double* Pi, int32_t* m,
                       int32_t* q, double* sigma, pe_report* report, void* stream);
 
+/* pe_compress without any allocation, for callers that cannot allocate device memory
+ * (code under stream capture, tight serving loops, harnesses that forbid hipMalloc).
+ * Same arguments, results and errors as pe_compress; the device workspace is instead a
+ * fixed 64 MiB array of the library on each GPU (held until the process ends) and the
+ * host read-back buffer lives in the context, so the call makes no hipMalloc, hipFree,
+ * hipHostMalloc or other allocating call.  A problem whose compression needs more than
+ * 64 MiB of workspace (two n x s copies of the samples, up to n x 128 range vectors and
+ * partial sums: n = 8192 with s = 256 needs 48 MiB) is rejected with PE_ERR_UNSUPPORTED
+ * before any device work.  Every call on one GPU
+ * shares that array: calls that overlap on one GPU (several streams or threads) race. */
+pe_status pe_compress_noalloc(pe_ctx* ctx, const pe_problem* prob, double* U, double* Pi, int32_t* m, int32_t* q,
+                              double* sigma, pe_report* report, void* stream);
+
 /* Steps S5-S8 (Sec. 2.1, eq. 2.4: the block Krylov space of [x | U] and the exponential
  * of the projected source-augmented matrix; Sec. 2.2 for the window subproblem) for
  * nprob independent problems with a given compressed source

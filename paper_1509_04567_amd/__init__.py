@@ -11,6 +11,12 @@ from .binding import (  # noqa: F401
     EXPORTED,
     PE_FP64,
     PE_MIXED,
+    PE_OK,
+    PE_ERR_ARG,
+    PE_ERR_NONFINITE,
+    PE_ERR_DEVICE,
+    PE_ERR_OOM,
+    PE_ERR_UNSUPPORTED,
     FLAG_NOT_CONVERGED,
     FLAG_BREAKDOWN,
     FLAG_RANK_CAPPED,

@@ -34,6 +34,7 @@ FLAG_RANK_CAPPED = 4
 FLAG_FIT_CAPPED = 8
 
 EXPORTED = ["pe_create", "pe_destroy", "pe_last_error", "pe_version", "pe_stencil_apply", "pe_compress",
+            "pe_compress_noalloc",
             "pe_expaction_batch", "pe_solve_batch", "pe_workspace_query", "pe_superpose", "pe_wr_burgers",
             "pe_profile_enable", "pe_profile_read",
             # host-only decision rules (include/paraexp_policy.h)
@@ -159,6 +160,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.pe_stencil_apply.argtypes = [vp, ctypes.POINTER(PeStencil), vp, i64, vp, i64, i32, vp]
     lib.pe_compress.argtypes = [vp, ctypes.POINTER(PeProblem), vp, vp, ctypes.POINTER(i32), ctypes.POINTER(i32),
                                 ctypes.POINTER(ctypes.c_double), ctypes.POINTER(PeReport), vp]
+    lib.pe_compress_noalloc.argtypes = lib.pe_compress.argtypes
     lib.pe_expaction_batch.argtypes = [vp, ctypes.POINTER(PeProblem), ctypes.POINTER(vp), ctypes.POINTER(vp),
                                        ctypes.POINTER(i32), ctypes.POINTER(i32), i32, ctypes.POINTER(PeReport), vp]
     lib.pe_solve_batch.argtypes = [vp, ctypes.POINTER(PeProblem), i32, ctypes.POINTER(PeReport), vp]
@@ -175,7 +177,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.pe_policy_step_growth.restype = ctypes.c_double
     lib.pe_policy_reorth_skip.argtypes = [vp, vp, i32, ctypes.c_double]
     lib.pe_policy_reorth_skip.restype = i32
-    for name in ["pe_create", "pe_destroy", "pe_stencil_apply", "pe_compress", "pe_expaction_batch",
+    for name in ["pe_create", "pe_destroy", "pe_stencil_apply", "pe_compress", "pe_compress_noalloc",
+                 "pe_expaction_batch",
                  "pe_solve_batch", "pe_superpose", "pe_wr_burgers", "pe_profile_enable", "pe_profile_read"]:
         getattr(lib, name).restype = ctypes.c_int
     _LIB = lib
@@ -369,7 +372,9 @@ class Context:
         return Y
 
     # -- S1-S4
-    def compress(self, src, precision: int = PE_FP64):
+    def compress(self, src, precision: int = PE_FP64, noalloc: bool = False):
+        """Compression of one problem; noalloc=True calls pe_compress_noalloc (the
+        library's fixed device scratch instead of its growable workspace)."""
         torch = _torch()
         dp = make_problem(src, self.device, precision)
         n, rmax, qmax = int(src.n), int(src.rank_max), int(src.q_max)
@@ -378,9 +383,10 @@ class Context:
         m, q = ctypes.c_int32(), ctypes.c_int32()
         sig = (ctypes.c_double * max(dp.struct.s, 1))()
         rep = PeReport()
-        self._check(self.lib.pe_compress(self.h, ctypes.byref(dp.struct), ctypes.c_void_p(U.data_ptr()),
-                                         ctypes.c_void_p(Pi.data_ptr()), ctypes.byref(m), ctypes.byref(q), sig,
-                                         ctypes.byref(rep), _stream_ptr()))
+        fn = self.lib.pe_compress_noalloc if noalloc else self.lib.pe_compress
+        self._check(fn(self.h, ctypes.byref(dp.struct), ctypes.c_void_p(U.data_ptr()),
+                       ctypes.c_void_p(Pi.data_ptr()), ctypes.byref(m), ctypes.byref(q), sig,
+                       ctypes.byref(rep), _stream_ptr()))
         mm, qq = m.value, q.value
         # U rows 0..m-1 are the retained columns; Pi is (rank_max x q_max) column-major
         return dict(U=U[:mm], Pi=Pi[:qq, :mm].T.contiguous() if mm else Pi[:0, :0], m=mm, q=qq,

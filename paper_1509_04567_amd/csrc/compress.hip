@@ -147,6 +147,19 @@ __device__ void pick_pivot(const CpArgs& a, bool first) {
   }
 }
 
+// zero counters, fresh state
+__global__ void k_cp_reset(CpArgs a, int kcap) {
+  for (int i = threadIdx.x; i < 1 + a.CG; i += blockDim.x) a.cnt[i] = 0u;
+  if (threadIdx.x == 0) {
+    CpState& S = *a.st;
+    S.k = 0;
+    S.done = 0;
+    S.piv = 0;
+    S.kcap = kcap;
+    S.gfro2 = S.thr2 = S.qnorm = S.res2 = 0.0;
+  }
+}
+
 // A = G^ and its squared column norms; first pivot
 __global__ __launch_bounds__(256) void k_cp_init(CpArgs a) {
   __shared__ int flag;
@@ -361,10 +374,8 @@ void launch_cp_range(int64_t n, int s, int kcap, const double* G, double* A, dou
   a.rrow = rrow;
   a.cnt = cnt;
   a.st = (CpState*)state;
-  CpState init{};
-  init.kcap = kcap;
-  (void)hipMemcpyAsync(state, &init, sizeof(CpState), hipMemcpyHostToDevice, st);
-  (void)hipMemsetAsync(cnt, 0, sizeof(unsigned) * (1 + a.CG), st);
+  // counters and state are set by a kernel (no memset or host copy in the launch sequence)
+  hipLaunchKernelGGL(k_cp_reset, dim3(1), dim3(256), 0, st, a, kcap);
   const dim3 g2((unsigned)a.P, (unsigned)a.CG), g1((unsigned)a.P);
   hipLaunchKernelGGL(k_cp_init, g2, dim3(256), 0, st, a);
   for (int it = 0; it < kcap; ++it) {

@@ -79,6 +79,7 @@ void launch_diff_norms(const double* a, const double* b, int64_t cnt, double* pa
 void launch_superpose(const double* u0, const double* const* v, int P, int64_t n, int n_out, int64_t ldv,
                       double* u, int64_t ldu, hipStream_t st);
 void launch_check_finite(const double* x, int64_t n, int cols, int64_t ld, int* flag, hipStream_t st);
+void launch_zero_u32(unsigned* x, int64_t n, hipStream_t st);
 void launch_fill(double* x, int64_t n, int cols, int64_t ld, double v, hipStream_t st);
 void launch_copy(const double* a, double* b, int64_t n, hipStream_t st);
 

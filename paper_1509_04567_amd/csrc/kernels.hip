@@ -1637,6 +1637,15 @@ void launch_check_finite(const double* x, int64_t n, int cols, int64_t ld, int* 
   hipLaunchKernelGGL(k_check_finite, grid, dim3(256), 0, st, x, n, ld, flag);
 }
 
+__global__ void k_zero_u32(unsigned* x, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = 0u;
+}
+
+void launch_zero_u32(unsigned* x, int64_t n, hipStream_t st) {
+  if (n > 0) hipLaunchKernelGGL(k_zero_u32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, x, n);
+}
+
 __global__ void k_fill(double* x, int64_t n, int64_t ld, double v) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int c = blockIdx.y;

@@ -19,6 +19,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -26,6 +27,22 @@
 #include "../../include/paraexp_policy.h"
 #include "kernels.h"
 #include "policy.h"
+
+// ---- fixed device scratch of the no-allocation entry point (pe_compress_noalloc) ----
+// One file-scope device array per GPU, alive until the process ends.  In host code the
+// array's name is only a stand-in: its device address, on each device, comes from
+// hipGetSymbolAddress (taken once per device, with that device current, by pe_create)
+// and only that address is ever handed to kernels or copies.  Calls that overlap on one
+// GPU share the array and race.
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) char scratch[kScratchBytes];
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static char* g_scratch_ptr[kMaxDevices] = {};
+static hipError_t g_scratch_err[kMaxDevices] = {};
+// host buffer of the no-allocation entry point: read-backs of the range finder's state,
+// singular values, permutation and fit summary (kept in the context, sized at creation)
+constexpr size_t kScratchHostDoubles = 1024;
 
 struct pe_ctx {
   int device = 0;
@@ -49,6 +66,9 @@ struct pe_ctx {
   // workspace query: ensure_arena records the size and stops the call there
   bool query = false;
   size_t query_bytes = 0;
+  // no-allocation entry point: device address of this device's scratch array, host buffer
+  char* scratch_dev = nullptr;
+  double scratch_host[kScratchHostDoubles];
 };
 
 static pe_status pe_fail(pe_ctx* ctx, pe_status st, const std::string& msg, hipError_t e = hipSuccess) {
@@ -384,7 +404,7 @@ pe_status validate_problem(pe_ctx* ctx, const pe_problem& p, bool need_samples) 
 // ---- device finiteness check of caller arrays -------------------------------------
 pe_status check_finite_dev(pe_ctx* ctx, const double* x, int64_t n, int cols, int64_t ld, int* dflag, int* hflag,
                            hipStream_t st, const char* what) {
-  HCK(hipMemsetAsync(dflag, 0, sizeof(int), st));
+  pe::launch_zero_u32((unsigned*)dflag, 1, st);
   pe::launch_check_finite(x, n, cols, ld, dflag, st);
   HCK(hipMemcpyAsync(hflag, dflag, sizeof(int), hipMemcpyDeviceToHost, st));
   HCK(hipStreamSynchronize(st));
@@ -430,11 +450,21 @@ StepCost step_cost(int64_t n, int bw, int nb, int beta) {
 struct CompressOut {
   int m = 0, q = 0, flags = 0;
   double fit_resid = 0.0, svd_tail = 0.0, sigma1 = 0.0;
-  std::vector<double> sigma;
+  int nsig = 0;                  // singular values resolved (the rest are zero)
+  double sigma[pe::kCpMaxK] = {};
+};
+
+// Workspace of a call: the context arena (grown on demand) and its pinned host buffer, or
+// a fixed device region and host buffer given by the caller (no allocation at all).
+struct FixedWs {
+  char* dev;
+  size_t dev_bytes;
+  double* host;
+  size_t host_bytes;
 };
 
 pe_status compress_one(pe_ctx* ctx, const pe_problem& p, double* U, int64_t ldU, double* Pi, int ldPi,
-                       CompressOut& res, hipStream_t st) {
+                       CompressOut& res, hipStream_t st, const FixedWs* fx = nullptr) {
   const int64_t n = p.op.n;
   const int s = p.s;
   const int qcap = std::min(p.q_max, s);
@@ -465,12 +495,25 @@ pe_status compress_one(pe_ctx* ctx, const pe_problem& p, double* U, int64_t ldU,
   const size_t o_fw = cv.take<double>((size_t)s * qcap + (size_t)qcap * qcap + (size_t)32 * qcap + (size_t)32 * s);
   const size_t o_fi = cv.take<double>(4);
   const size_t o_flag = cv.take<int>(4);
-  pe_status stt = ensure_arena(ctx, cv.off);
-  if (stt != PE_OK) return stt;
-  stt = ensure_pinned(ctx, std::max(sizeof(double) * (4 * (size_t)std::max(1, kcap) + 64), pe::cp_state_bytes()));
-  if (stt != PE_OK) return stt;
-  char* base = ctx->arena;
-  double* hp = (double*)ctx->pinned;
+  const size_t host_need = std::max(sizeof(double) * (4 * (size_t)std::max(1, kcap) + 64), pe::cp_state_bytes());
+  char* base;
+  double* hp;
+  pe_status stt;
+  if (fx) {
+    if (cv.off > fx->dev_bytes || host_need > fx->host_bytes)
+      return pe_fail(ctx, PE_ERR_UNSUPPORTED, "problem needs " + std::to_string(cv.off) +
+                                                  " bytes of device scratch, more than the fixed " +
+                                                  std::to_string(fx->dev_bytes));
+    base = fx->dev;
+    hp = fx->host;
+  } else {
+    stt = ensure_arena(ctx, cv.off);
+    if (stt != PE_OK) return stt;
+    stt = ensure_pinned(ctx, host_need);
+    if (stt != PE_OK) return stt;
+    base = ctx->arena;
+    hp = (double*)ctx->pinned;
+  }
 
   // non-finite inputs
   stt = check_finite_dev(ctx, p.u0, n, 1, n, (int*)(base + o_flag), (int*)hp, st, "u0");
@@ -490,7 +533,7 @@ pe_status compress_one(pe_ctx* ctx, const pe_problem& p, double* U, int64_t ldU,
   } else {
     pe::launch_add_column(n, s, p.G, p.ldG, nullptr, Gh, n, st);
   }
-  res.sigma.assign(s, 0.0);
+  res.nsig = 0;
   res.m = 0;
   // S2-S3: range of G^ by column-pivoted Gram-Schmidt, R = Q^T G^ (k x s, ld kcap)
   double* Qc = (double*)(base + o_Q);
@@ -509,18 +552,18 @@ pe_status compress_one(pe_ctx* ctx, const pe_problem& p, double* U, int64_t ldU,
     if (gfro2 > 0.0) res.flags |= PE_FLAG_RANK_CAPPED;
     return PE_OK;
   }
-  std::vector<int> sel(r);
+  int sel[pe::kCpMaxK], perm[pe::kCpMaxK];
+  double sig[pe::kCpMaxK], tail[pe::kCpMaxK + 1];
   for (int i = 0; i < r; ++i) sel[i] = i;
-  HCK(hipMemcpyAsync(base + o_sel, sel.data(), sizeof(int) * r, hipMemcpyHostToDevice, st));
+  HCK(hipMemcpyAsync(base + o_sel, sel, sizeof(int) * r, hipMemcpyHostToDevice, st));
   double* A = (double*)(base + o_A);
   double* J = (double*)(base + o_J);
   pe::launch_jacobi_svd(R, kcap, (int*)(base + o_sel), s, r, A, J, (double*)(base + o_sig), (int*)(base + o_perm),
                         (int*)(base + o_info), st);
-  std::vector<int> perm(r);
   HCK(hipMemcpyAsync(hp, base + o_sig, sizeof(double) * r, hipMemcpyDeviceToHost, st));
-  HCK(hipMemcpyAsync(perm.data(), base + o_perm, sizeof(int) * r, hipMemcpyDeviceToHost, st));
+  HCK(hipMemcpyAsync(hp + r, base + o_perm, sizeof(int) * r, hipMemcpyDeviceToHost, st));
   HCK(hipStreamSynchronize(st));
-  std::vector<double> sig(r);
+  std::memcpy(perm, hp + r, sizeof(int) * r);
   for (int i = 0; i < r; ++i) sig[i] = hp[perm[i]];
   // truncation (the energy rule of the truncated SVD, Sec. 2.1 eq. 2.3): the smallest m
   // with dropped energy <= svd_tol |G^|_F; singular values <= kSigmaFloor sigma_1 are
@@ -528,7 +571,6 @@ pe_status compress_one(pe_ctx* ctx, const pe_problem& p, double* U, int64_t ldU,
   // the cluster whole; m is capped at rank_max
   // (the energy left in the range finder's residual belongs to the dropped tail)
   const double gfro = std::sqrt(gfro2);
-  std::vector<double> tail(r + 1, 0.0);
   tail[r] = std::sqrt(std::max(res2, 0.0));
   for (int i = r - 1; i >= 0; --i) tail[i] = std::sqrt(tail[i + 1] * tail[i + 1] + sig[i] * sig[i]);
   int m = r;
@@ -546,7 +588,8 @@ pe_status compress_one(pe_ctx* ctx, const pe_problem& p, double* U, int64_t ldU,
   res.m = m;
   res.sigma1 = sig[0];
   res.svd_tail = gfro > 0.0 ? tail[m] / gfro : 0.0;
-  for (int i = 0; i < std::min(r, s); ++i) res.sigma[i] = sig[i];
+  res.nsig = std::min(r, s);
+  for (int i = 0; i < res.nsig; ++i) res.sigma[i] = sig[i];
   if (m == 0) return PE_OK;
   // U = Q J[:, perm[0:m]]  (Q column-major: blocks of width 1)
   pe::launch_form_u(Qc, 1, n, (int*)(base + o_sel), r, J, (int*)(base + o_perm), m, U, ldU, st);
@@ -1018,6 +1061,16 @@ pe_status pe_create(pe_ctx** ctx_out, int device) {
   if (hipSetDevice(device) != hipSuccess) return PE_ERR_DEVICE;
   pe_ctx* ctx = new pe_ctx();
   ctx->device = device;
+  if (device < kMaxDevices) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[device] && g_scratch_err[device] == hipSuccess) {
+      void* ptr = nullptr;
+      const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+      if (e == hipSuccess && ptr) g_scratch_ptr[device] = (char*)ptr;
+      else g_scratch_err[device] = e != hipSuccess ? e : hipErrorInvalidSymbol;
+    }
+    ctx->scratch_dev = g_scratch_ptr[device];
+  }
   *ctx_out = ctx;
   return PE_OK;
 }
@@ -1068,7 +1121,41 @@ pe_status pe_compress(pe_ctx* ctx, const pe_problem* prob, double* U, double* Pi
   *m = co.m;
   *q = co.q;
   if (sigma)
-    for (int i = 0; i < prob->s; ++i) sigma[i] = co.sigma[i];
+    for (int i = 0; i < prob->s; ++i) sigma[i] = i < co.nsig ? co.sigma[i] : 0.0;
+  if (report) {
+    std::memset(report, 0, sizeof(pe_report));
+    report->rank = co.m;
+    report->q = co.q;
+    report->flags = co.flags;
+    report->fit_resid = co.fit_resid;
+    report->svd_tail = co.svd_tail;
+    report->sigma1 = co.sigma1;
+  }
+  return PE_OK;
+}
+
+pe_status pe_compress_noalloc(pe_ctx* ctx, const pe_problem* prob, double* U, double* Pi, int32_t* m, int32_t* q,
+                      double* sigma, pe_report* report, void* stream) {
+  if (!ctx) return PE_ERR_ARG;
+  if (!prob || !U || !Pi || !m || !q) return pe_fail(ctx, PE_ERR_ARG, "pe_compress_noalloc: null argument");
+  pe_status s = validate_problem(ctx, *prob, true);
+  if (s != PE_OK) return s;
+  HCK(hipSetDevice(ctx->device));
+  hipStream_t st = (hipStream_t)stream;
+  if (!ctx->scratch_dev) {
+    const hipError_t e = ctx->device < kMaxDevices ? g_scratch_err[ctx->device] : hipErrorInvalidDevice;
+    return pe_fail(ctx, PE_ERR_DEVICE, "pe_compress_noalloc: no device scratch on this device", e);
+  }
+  const FixedWs fx{ctx->scratch_dev, kScratchBytes, ctx->scratch_host, sizeof(ctx->scratch_host)};
+  CompressOut co;
+  s = compress_one(ctx, *prob, U, prob->op.n, Pi, std::max(1, prob->rank_max), co, st, &fx);
+  if (s != PE_OK) return s;
+  HCK(hipGetLastError());
+  HCK(hipStreamSynchronize(st));
+  *m = co.m;
+  *q = co.q;
+  if (sigma)
+    for (int i = 0; i < prob->s; ++i) sigma[i] = i < co.nsig ? co.sigma[i] : 0.0;
   if (report) {
     std::memset(report, 0, sizeof(pe_report));
     report->rank = co.m;
