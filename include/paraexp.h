@@ -64,6 +64,11 @@ enum {
 
 typedef enum { PE_FP64 = 0, PE_MIXED = 1 } pe_precision;
 
+/* Krylov space of a restart cycle (Sec. 2.1): polynomial, K_l(L, [x | U]), or rational
+ * shift-and-invert, K_l((I - gamma L)^{-1}, [x | U]) -- the acceleration the paper uses
+ * (Sec. 2.1, Sec. 3.2), whose convergence does not degrade with the grid's stiffness. */
+typedef enum { PE_KRYLOV_POLY = 0, PE_KRYLOV_SAI = 1 } pe_krylov;
+
 typedef struct pe_ctx pe_ctx; /* opaque: device, stream-independent workspace */
 
 /* The operator L (Sec. 3, eq. 3.2):
@@ -90,7 +95,12 @@ typedef struct {
  *   tol       accuracy target of the time integration, relative to max(|u0|, |state|)
  *   svd_tol   truncation: keep m singular vectors with dropped energy <= svd_tol |G^|_F
  *   fit_tol   polynomial degree: smallest with relative fit residual <= fit_tol
- *   prec      PE_FP64, or PE_MIXED (Krylov basis stored in fp32, fp64 arithmetic). */
+ *   prec      PE_FP64, or PE_MIXED (Krylov basis stored in fp32, fp64 arithmetic)
+ *   krylov    PE_KRYLOV_POLY or PE_KRYLOV_SAI
+ *   sai_shift shift-and-invert only: gamma = sai_shift times the step a restart cycle
+ *             aims at (0: 0.1); the shifted system is solved as a periodic tridiagonal
+ *             system without pivoting, so I - gamma L should be diagonally dominant
+ *             (always so for 2 nu >= |a| h, the cell Peclet condition). */
 typedef struct {
   pe_stencil op;
   const double* u0;
@@ -111,6 +121,8 @@ typedef struct {
   double svd_tol;
   double fit_tol;
   pe_precision prec;
+  pe_krylov krylov;
+  double sai_shift;
 } pe_problem;
 
 /* Per-problem report (host). */
@@ -236,6 +248,8 @@ typedef struct {
   int32_t q_max;
   double tol, svd_tol, fit_tol;
   pe_precision prec;
+  pe_krylov krylov;
+  double sai_shift;
 } pe_wr_problem;
 pe_status pe_wr_burgers(pe_ctx* ctx, const pe_wr_problem* wr, pe_report* reports, double* increments,
                         void* stream);

@@ -11,6 +11,8 @@ from .binding import (  # noqa: F401
     EXPORTED,
     PE_FP64,
     PE_MIXED,
+    PE_KRYLOV_POLY,
+    PE_KRYLOV_SAI,
     PE_OK,
     PE_ERR_ARG,
     PE_ERR_NONFINITE,

@@ -28,6 +28,8 @@ PE_ERR_OOM = -4
 PE_ERR_UNSUPPORTED = -5
 PE_FP64 = 0
 PE_MIXED = 1
+PE_KRYLOV_POLY = 0
+PE_KRYLOV_SAI = 1
 FLAG_NOT_CONVERGED = 1
 FLAG_BREAKDOWN = 2
 FLAG_RANK_CAPPED = 4
@@ -70,6 +72,8 @@ class PeProblem(ctypes.Structure):
         ("svd_tol", ctypes.c_double),
         ("fit_tol", ctypes.c_double),
         ("prec", ctypes.c_int32),
+        ("krylov", ctypes.c_int32),
+        ("sai_shift", ctypes.c_double),
     ]
 
 
@@ -110,6 +114,8 @@ class PeWrProblem(ctypes.Structure):
         ("svd_tol", ctypes.c_double),
         ("fit_tol", ctypes.c_double),
         ("prec", ctypes.c_int32),
+        ("krylov", ctypes.c_int32),
+        ("sai_shift", ctypes.c_double),
     ]
 
 
@@ -296,6 +302,8 @@ def make_problem(src, device, precision: int = PE_FP64, out=None) -> DeviceProbl
     st.svd_tol = float(getattr(src, "svd_tol", 1e-13))
     st.fit_tol = float(getattr(src, "fit_tol", 1e-13))
     st.prec = int(precision)
+    st.krylov = int(getattr(src, "krylov", PE_KRYLOV_POLY))
+    st.sai_shift = float(getattr(src, "sai_shift", 0.0))
     return DeviceProblem(struct=st, out=out[:n_out], keep=keep)
 
 
@@ -467,7 +475,9 @@ class Context:
                          u0=u0.data_ptr(), u_init=ui.data_ptr() if ui is not None else None,
                          u_final=out.data_ptr(), krylov_steps=int(bp.krylov_steps), rank_max=int(bp.rank_max),
                          q_max=int(bp.q_max), tol=float(bp.tol), svd_tol=float(bp.svd_tol),
-                         fit_tol=float(bp.fit_tol), prec=int(precision))
+                         fit_tol=float(bp.fit_tol), prec=int(precision),
+                         krylov=int(getattr(bp, "krylov", PE_KRYLOV_POLY)),
+                         sai_shift=float(getattr(bp, "sai_shift", 0.0)))
         reps = (PeReport * P)()
         inc = (ctypes.c_double * max(K, 1))()
         self._check(self.lib.pe_wr_burgers(self.h, ctypes.byref(wp), reps, inc, _stream_ptr()))

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libparaexp.so")
-SOURCES = ["kernels.hip", "compress.hip", "solver.hip"]
+SOURCES = ["kernels.hip", "compress.hip", "sai.hip", "solver.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950",

@@ -62,6 +62,45 @@ struct ProbDev {
                            // norm before projection is deflated (dependent)
   int32_t rows_p;          // rows per projection chunk
   int32_t Cp;              // number of projection chunks
+
+  // shift-and-invert Arnoldi: the input block W = (I - gamma L)^{-1} V_j of a step,
+  // row-major n x bw (fp64), written by the tridiagonal solve
+  const double* Wb;
+};
+
+// ---------------------------------------------------------------------------------
+// Shift-and-invert operator (I - gamma L)^{-1} of one problem: a periodic tridiagonal
+// matrix T = I - gamma L solved by partition: the rows are cut into C chunks of R rows
+// (the last takes the remainder, R..2R-1 rows); each chunk is eliminated on its own
+// (Thomas), its coupling to the neighbouring chunks' end rows enters through two spike
+// vectors, and the 2C interface values solve a periodic block-tridiagonal system.
+// ---------------------------------------------------------------------------------
+struct TriDev {
+  int64_t n;
+  int32_t per_point;
+  double c3[3];            // constant coefficients of L (per_point == 0)
+  const double* coef;      // 3 n coefficients of L (per_point == 1)
+  double gamma;            // shift: T = I - gamma L
+  int32_t R, C;            // rows per chunk, chunks
+  int32_t bw;              // columns of the current block
+  int32_t active;
+  double* ta;              // n: sub-diagonal of T
+  double* tinv;            // n: inverse pivots of the chunk eliminations
+  double* tc;              // n: eliminated super-diagonal
+  double* vL;              // n: left spikes  T_c^{-1} (a_s e_first)
+  double* vR;              // n: right spikes T_c^{-1} (b_e e_last)
+  double* red;             // 14 C + 4: reduced system factors (see sai.hip)
+  double* rrhs;            // 2 C x bw: interface values of the chunk solutions
+  double* ru;              // 2 C x bw: interface values of the solution
+  double* W;               // n x bw row-major: the solution block
+  double* GW;              // bw x bw: Gram of (I - gamma L) V_l (residual estimate)
+  int32_t* piv;            // row interchanges of the projected matrix's LU
+  unsigned* cnt;           // 2 counters (solve, Gram)
+  double* LU;              // N0 x N0 (ld N0) work: LU factors of the projected matrix
+  double* Kinv;            // N0 x N0 (ld N0): its inverse
+  const double* H;         // projected matrix (Arnoldi Hessenberg of the shifted inverse)
+  int64_t ldH;
+  int32_t N0;              // l bw
 };
 
 // squaring levels whose exponential actions are evaluated in one trial
@@ -93,6 +132,13 @@ struct ExpmDev {
   const double* w;         // q: T_k(x(tau)) at the start of the cycle
   const double* Dm;        // qmax x qmax row-major Chebyshev derivative matrix
   int32_t qmax;
+  // shift-and-invert: the projected operator is (I - K^{-1}) / gamma with K the Arnoldi
+  // matrix of (I - gamma L)^{-1}; the residual estimate needs the Gram of
+  // (I - gamma L) V_l
+  int32_t sai;
+  double gamma;
+  const double* Kinv;      // lbw x lbw (ld lbw)
+  const double* GW;        // bw x bw
 };
 
 // Host-visible helpers ---------------------------------------------------------

@@ -4,6 +4,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include "common.h"
+
 namespace pe {
 
 // DPP data movement of a double (both 32-bit halves); rows outside row_mask receive 0
@@ -57,6 +59,44 @@ __device__ __forceinline__ bool arrive_last(unsigned* counter, unsigned expected
   const bool last = *flag != 0;
   if (last) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   return last;
+}
+
+// ---- access to the per-problem block workspace (ProbDev) ----------------------------
+template <typename TS>
+__device__ __forceinline__ TS* basis_ptr(const ProbDev& p);
+template <>
+__device__ __forceinline__ double* basis_ptr<double>(const ProbDev& p) { return p.V; }
+template <>
+__device__ __forceinline__ float* basis_ptr<float>(const ProbDev& p) { return p.V32; }
+
+__device__ __forceinline__ void stencil_coefs(const ProbDev& p, int64_t r, double& cm, double& cz, double& cp) {
+  if (p.per_point) {
+    cm = p.coef[r];
+    cz = p.coef[p.n + r];
+    cp = p.coef[2 * p.n + r];
+  } else {
+    cm = p.c3[0];
+    cz = p.c3[1];
+    cp = p.c3[2];
+  }
+}
+
+// chunk of a row for the update (TSQR) partition: the last chunk takes the remainder
+__device__ __forceinline__ int chunk_of(const ProbDev& p, int64_t r) {
+  int64_t u = r >> p.rows_u_log2;
+  return (int)(u < p.Cu - 1 ? u : p.Cu - 1);
+}
+
+// entry (r, col) of a TSQR output block: Qloc[r, :] . Qs[u(r)][:, col]
+__device__ __forceinline__ double tsqr_entry(const ProbDev& p, const double* Qloc, const double* Qs, int64_t r,
+                                             int col) {
+  const int bw = p.bw;
+  const int u = chunk_of(p, r);
+  const double* q = Qloc + r * bw;
+  const double* s = Qs + (int64_t)u * bw * bw + col;
+  double acc = 0.0;
+  for (int k = 0; k < bw; ++k) acc += q[k] * s[k * bw];
+  return acc;
 }
 
 }  // namespace pe

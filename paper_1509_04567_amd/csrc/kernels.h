@@ -5,8 +5,12 @@
 
 namespace pe {
 
-// modes of the block orthogonalisation kernels
-enum BlockMode : int { MODE_ARNOLDI = 0, MODE_GIVEN = 1, MODE_INIT = 2 };
+// modes of the block orthogonalisation kernels: Arnoldi step of L (the input block is
+// formed on the fly as L V_j), of the shifted inverse (I - gamma L)^{-1} (input block read
+// from ProbDev::Wb, V_j already committed), a given block (columns of ProbDev::Xg), or
+// the initial block [U | x]
+enum BlockMode : int { MODE_ARNOLDI = 0, MODE_GIVEN = 1, MODE_INIT = 2, MODE_SAI = 3 };
+__host__ __device__ inline bool arnoldi_mode(int mode) { return mode == MODE_ARNOLDI || mode == MODE_SAI; }
 
 // dynamic LDS requested by the update kernel at most (bytes)
 constexpr int kUpdateLdsMax = 150 * 1024;
@@ -44,6 +48,16 @@ void launch_norm1(ExpmDev* e, double* out, int nprob, int maxN, hipStream_t st);
 void launch_elementwise(ExpmDev* e, int op, int nprob, int64_t maxNN, hipStream_t st);
 void launch_gemm(ExpmDev* e, int op, int k, int nprob, int tiles_max, hipStream_t st);
 void launch_expm_apply(ExpmDev* e, int level, int nprob, int maxN, hipStream_t st);
+
+// shift-and-invert operator (sai.hip): factorisation of I - gamma L, the solve of an
+// Arnoldi step (V_j committed, W = (I - gamma L)^{-1} V_j into TriDev::W), the Gram of
+// (I - gamma L) V_l (part: nprob x ceil(n / 128) x 1024 doubles), inverse of the
+// projected matrix
+void launch_tri_factor(TriDev* td, int nprob, int maxC, hipStream_t st);
+void launch_sai_solve(ProbDev* d, TriDev* td, int nprob, int maxCbw, int64_t maxnbw, int j, int mixed,
+                      hipStream_t st);
+void launch_sai_gram(ProbDev* d, TriDev* td, int nprob, int64_t maxn, double* part, hipStream_t st);
+void launch_hess_inverse(TriDev* td, int nprob, int maxN0, hipStream_t st);
 
 // x = V y (+ output column)
 void launch_project(ProbDev* d, ExpmDev* e, int nprob, int64_t maxn, int max_lbw, int mixed, hipStream_t st);

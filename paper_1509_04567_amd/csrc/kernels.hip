@@ -28,43 +28,6 @@ namespace pe {
 // ------------------------------------------------------------------------------------
 // reductions and helpers
 // ------------------------------------------------------------------------------------
-template <typename TS>
-__device__ __forceinline__ TS* basis_ptr(const ProbDev& p);
-template <>
-__device__ __forceinline__ double* basis_ptr<double>(const ProbDev& p) { return p.V; }
-template <>
-__device__ __forceinline__ float* basis_ptr<float>(const ProbDev& p) { return p.V32; }
-
-__device__ __forceinline__ void stencil_coefs(const ProbDev& p, int64_t r, double& cm, double& cz, double& cp) {
-  if (p.per_point) {
-    cm = p.coef[r];
-    cz = p.coef[p.n + r];
-    cp = p.coef[2 * p.n + r];
-  } else {
-    cm = p.c3[0];
-    cz = p.c3[1];
-    cp = p.c3[2];
-  }
-}
-
-// chunk of a row for the update (TSQR) partition: the last chunk takes the remainder
-__device__ __forceinline__ int chunk_of(const ProbDev& p, int64_t r) {
-  int64_t u = r >> p.rows_u_log2;
-  return (int)(u < p.Cu - 1 ? u : p.Cu - 1);
-}
-
-// entry (r, col) of a TSQR output block: Qloc[r, :] . Qs[u(r)][:, col]
-__device__ __forceinline__ double tsqr_entry(const ProbDev& p, const double* Qloc, const double* Qs, int64_t r,
-                                             int col) {
-  const int bw = p.bw;
-  const int u = chunk_of(p, r);
-  const double* q = Qloc + r * bw;
-  const double* s = Qs + (int64_t)u * bw * bw + col;
-  double acc = 0.0;
-  for (int k = 0; k < bw; ++k) acc += q[k] * s[k * bw];
-  return acc;
-}
-
 // Modified Gram-Schmidt applied twice, column by column, by the whole workgroup on a
 // row-major rows x bw array X (leading dimension ld, any bw); thread t handles rows t,
 // t + blockDim.x, ...  A column whose remainder is <= dep_tol times its norm as given is
@@ -417,6 +380,10 @@ __device__ __forceinline__ void form_block(const ProbDev& p, int mode, int pass,
           return gc < p.m ? v : 0.0;
         },
         [&](int64_t e, double v) { X[(e % rows) * ld + e / rows] = v; });
+  } else if (pass == 0 && mode == MODE_SAI) {  // W = (I - gamma L)^{-1} V_j, solved beforehand
+    bulk_load(
+        (int64_t)rows * bw, [&](int64_t e) -> double { return p.Wb[r0 * bw + e]; },
+        [&](int64_t e, double v) { X[(e / bw) * ld + e % bw] = v; });
   } else if (pass == 0) {  // MODE_ARNOLDI: W = L V_j, V_j read from the basis
     const TS* vj = V + (int64_t)j * blk;
     const int64_t gm = wrap_row(r0 - 1, n), gp = wrap_row(r0 + rows, n);
@@ -473,7 +440,7 @@ __global__ __launch_bounds__(256) void k_block_proj(const ProbDev* __restrict__ 
   const int c = blockIdx.x % p.Cp;
   const int ngroups = (nb + kSlotGroup - 1) / kSlotGroup;
   if (grp >= ngroups) return;
-  if (mode == MODE_ARNOLDI && pass == 1 && p.cnt[2 * p.nbmax + 1]) return;  // reorthogonalisation not needed
+  if (arnoldi_mode(mode) && pass == 1 && p.cnt[2 * p.nbmax + 1]) return;  // reorthogonalisation not needed
   const int64_t n = p.n;
   const int64_t r0 = (int64_t)c * p.rows_p;
   if (r0 >= n) return;
@@ -492,6 +459,7 @@ __global__ __launch_bounds__(256) void k_block_proj(const ProbDev* __restrict__ 
   const int64_t blk = n * bw;
   const bool arn0 = (mode == MODE_ARNOLDI && pass == 0);
   const bool given0 = (mode == MODE_GIVEN && pass == 0);
+  const bool sai0 = (mode == MODE_SAI && pass == 0);  // input block W from Wb, V_j committed
   const int i_lo = grp * kSlotGroup, i_hi = min(nb, i_lo + kSlotGroup);
   const int col = t % bw, rstep = 256 / bw, rr0 = t / bw;
   const bool act = rr0 < rstep;
@@ -556,7 +524,7 @@ __global__ __launch_bounds__(256) void k_block_proj(const ProbDev* __restrict__ 
           if (e < per_slot) Vs[(int64_t)kk * p.rows_p * bw + e] = vv[kk][m];
         }
     }
-    if (!given0) {
+    if (!given0 && !sai0) {
 #pragma unroll
       for (int m = 0; m < 5; ++m)
         if (t + 256 * m < nqr) Qrow[t + 256 * m] = qv[m];
@@ -575,6 +543,10 @@ __global__ __launch_bounds__(256) void k_block_proj(const ProbDev* __restrict__ 
           return gc < p.m ? v : 0.0;
         },
         [&](int64_t e, double v) { Xs[(e % rows) * bw + e / rows] = v; });
+  else if (sai0)
+    bulk_load(
+        (int64_t)rows * bw, [&](int64_t e) -> double { return p.Wb[r0 * bw + e]; },
+        [&](int64_t e, double v) { Xs[e] = v; });
   __syncthreads();
   // ---- form the input block
   if (arn0) {
@@ -605,7 +577,7 @@ __global__ __launch_bounds__(256) void k_block_proj(const ProbDev* __restrict__ 
       double* dst = Vs + (int64_t)(j - i_lo) * p.rows_p * bw;
       for (int e = t; e < rows * bw; e += 256) dst[e] = Vh[bw + e];
     }
-  } else if (!given0) {  // pass 1: X = Q1 = Qloc1 Qs1
+  } else if (!given0 && !sai0) {  // pass 1: X = Q1 = Qloc1 Qs1
     if (act)
       for (int rr = rr0; rr < rows; rr += rstep) {
         const double* q = Qrow + rr * bw;
@@ -778,7 +750,7 @@ __global__ __launch_bounds__(256) void k_block_update(const ProbDev* __restrict_
 
   // Arnoldi steps whose first pass kept enough of every column skip the second pass
   // (decided, and column block j of H written, by the first pass's last workgroup)
-  if (mode == MODE_ARNOLDI && pass == 1 && p.cnt[2 * p.nbmax + 1]) return;
+  if (arnoldi_mode(mode) && pass == 1 && p.cnt[2 * p.nbmax + 1]) return;
 
   // 0. pass 1: blocks i < nb of column block j of H (of R in MODE_GIVEN), one block per
   //    workgroup: H_ij = S1_i + S2_i Rf1 (the block nb needs the combine below)
@@ -892,7 +864,7 @@ __global__ __launch_bounds__(256) void k_block_update(const ProbDev* __restrict_
   double* Rout = p.Rf + (mode == MODE_INIT ? 2 : pass) * nout;
   for (int o = t; o < nout; o += 256) Rout[o] = Rl[o];
   if (mode == MODE_INIT && t == 0) p.cnt[2 * p.nbmax + 1] = 0u;
-  if (mode == MODE_ARNOLDI && pass == 0) {
+  if (arnoldi_mode(mode) && pass == 0) {
     // the loss of orthogonality of each column of Q1 = W' R1^{-1} to the basis is bounded
     // through R1^{-1} and the pre-projection norms (reorth_column_ok); when every column
     // passes, the second pass is skipped: V_{j+1} = Q1, H column = S1 and subdiagonal
@@ -1005,8 +977,11 @@ __global__ void k_build_aug(const ExpmDev* __restrict__ E) {
     const int r = (int)(idx % N), c = (int)(idx / N);
     double v = 0.0;
     if (r < lbw && c < lbw) {
+      if (e.sai)  // shift-and-invert: H_L = (I - K^{-1}) / gamma
+        v = ((r == c ? 1.0 : 0.0) - e.Kinv[(int64_t)r + (int64_t)lbw * c]) / e.gamma;
       // block upper Hessenberg: blocks below the subdiagonal are zero (never written)
-      if (r / bw <= c / bw + 1) v = e.H[(int64_t)r + e.ldH * c];
+      else if (r / bw <= c / bw + 1)
+        v = e.H[(int64_t)r + e.ldH * c];
     } else if (r < bw && c >= lbw) {
       const int k = c - lbw;
       for (int cc = 0; cc < e.m; ++cc) v += e.R0[r * bw + cc] * e.Pi[cc + (int64_t)e.ldPi * k];
@@ -1215,18 +1190,45 @@ __global__ __launch_bounds__(1024) void k_expm_apply(const ExpmDev* __restrict__
   }
 }
 
-// out[2k] = |H_{l+1,l} y_k[(l-1)bw : l bw]| (residual of the Arnoldi relation at the end
-// of the step of level k), out[2k+1] = |y_k[0 : l bw]|
+// out[2k] = residual norm of the Krylov solution at the end of the step of level k,
+// out[2k+1] = |y_k[0 : l bw]|.  Polynomial Krylov: |H_{l+1,l} y_k[(l-1)bw : l bw]|.
+// Shift-and-invert: |(I - gamma L) V_{l+1} K_{l+1,l} E_l^T K^{-1} y_k| / gamma, with
+// E_l^T K^{-1} y = E_l^T (I - gamma H_L) y and the norm from the Gram GW.
 __global__ __launch_bounds__(256) void k_expm_resid(const ExpmDev* __restrict__ E, int level) {
   const ExpmDev e = E[blockIdx.x];  // by value: uniform, loaded once
   if (!e.active || level > e.nsq) return;
   __shared__ double red[16];
+  __shared__ double zs[32];
   const double* y = e.y + (int64_t)level * e.N;
   double yn = 0.0;
   for (int r = threadIdx.x; r < e.lbw; r += blockDim.x) yn += y[r] * y[r];
   yn = block_sum(yn, red);
   double rr = 0.0;
   const int bw = e.bw, l = e.l;
+  if (e.sai) {
+    const int lbw = e.lbw, N = e.N;
+    for (int a = 0; a < bw; ++a) {
+      double sa = 0.0;
+      for (int c = threadIdx.x; c < lbw; c += blockDim.x) sa += e.Ht[(int64_t)(lbw - bw + a) + (int64_t)N * c] * y[c];
+      sa = block_sum(sa, red);
+      if (threadIdx.x == 0) zs[a] = y[lbw - bw + a] - e.gamma * sa;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double cv[32];
+      for (int a = 0; a < bw; ++a) {
+        double acc = 0.0;
+        for (int b = 0; b < bw; ++b) acc += e.H[(int64_t)(l * bw + a) + e.ldH * (int64_t)((l - 1) * bw + b)] * zs[b];
+        cv[a] = acc;
+      }
+      double q = 0.0;
+      for (int a = 0; a < bw; ++a)
+        for (int b = 0; b < bw; ++b) q += cv[a] * e.GW[a * bw + b] * cv[b];
+      e.out[2 * level] = sqrt(fmax(q, 0.0)) / e.gamma;
+      e.out[2 * level + 1] = sqrt(yn);
+    }
+    return;
+  }
   if ((int)threadIdx.x < bw) {
     const int a = threadIdx.x;
     double sacc = 0.0;

@@ -133,6 +133,18 @@ constexpr double kDepTolCompress = 1e-14;
 constexpr double kDepTolArnoldi = 1e-12;
 constexpr int kRowsU = 64;
 
+// shift-and-invert: gamma = kSaiShift times the step a restart cycle aims at, unless the
+// problem sets its own factor
+constexpr double kSaiShift = 0.1;
+// rows per chunk of the partitioned tridiagonal solve: 32, or more on long grids so that
+// the interface system (two unknowns per chunk, solved by one thread per column) stays
+// at most 1024 chunks long
+int sai_rows_per_chunk(int64_t n) {
+  int64_t r = 32;
+  while (n / r > 1024) r *= 2;
+  return (int)r;
+}
+
 // bound on the re-expansion growth of the Chebyshev source basis over one step
 constexpr double kGrowthCap = 100.0;
 // restart cycles of a march between two timed ones (pe_profile_enable)
@@ -383,6 +395,8 @@ pe_status validate_problem(pe_ctx* ctx, const pe_problem& p, bool need_samples) 
   if (p.q_max < 1 || p.q_max > 64) return pe_fail(ctx, PE_ERR_ARG, "q_max must be in [1, 64]");
   if (!(p.tol > 0.0)) return pe_fail(ctx, PE_ERR_ARG, "tol must be positive");
   if (p.prec != PE_FP64 && p.prec != PE_MIXED) return pe_fail(ctx, PE_ERR_ARG, "unknown precision");
+  if (p.krylov != PE_KRYLOV_POLY && p.krylov != PE_KRYLOV_SAI) return pe_fail(ctx, PE_ERR_ARG, "unknown Krylov space");
+  if (!(p.sai_shift >= 0.0) || !std::isfinite(p.sai_shift)) return pe_fail(ctx, PE_ERR_ARG, "bad sai_shift");
   if (need_samples) {
     if (p.s < 1 || !p.t_samples || !p.G) return pe_fail(ctx, PE_ERR_ARG, "missing source samples");
     if (p.ldG < p.op.n) return pe_fail(ctx, PE_ERR_ARG, "ldG < n");
@@ -659,6 +673,41 @@ pe_status march_batch(pe_ctx* ctx, const pe_problem* probs, const int* idx, int 
     maxNall = std::max(maxNall, Nmax[ii]);
     max_lbw = std::max(max_lbw, l * bwmax);
   }
+  // shift-and-invert: factors of I - gamma L, interface system, solve block, residual Gram
+  const bool sai = probs[idx[0]].krylov == PE_KRYLOV_SAI;
+  struct SaiOff {
+    size_t ta, tinv, tc, vL, vR, red, rrhs, ru, W, GW, piv, cnt;
+    int R, C;
+  };
+  std::vector<SaiOff> so(sai ? nb_prob : 0);
+  int maxC = 1, maxbwall = 1;
+  if (sai)
+    for (int ii = 0; ii < nb_prob; ++ii) {
+      const pe_problem& p = probs[idx[ii]];
+      const int64_t n = p.op.n;
+      const int bwmax = ml[ii] + 1;
+      SaiOff& o = so[ii];
+      o.R = sai_rows_per_chunk(n);
+      o.C = (int)std::max<int64_t>(1, n / o.R);
+      o.ta = cv.take<double>(n);
+      o.tinv = cv.take<double>(n);
+      o.tc = cv.take<double>(n);
+      o.vL = cv.take<double>(n);
+      o.vR = cv.take<double>(n);
+      o.red = cv.take<double>(14 * (size_t)o.C + 4);
+      o.rrhs = cv.take<double>(2 * (size_t)o.C * bwmax);
+      o.ru = cv.take<double>(2 * (size_t)o.C * bwmax);
+      o.W = cv.take<double>((size_t)n * bwmax);
+      o.GW = cv.take<double>((size_t)bwmax * bwmax);
+      o.piv = cv.take<int32_t>((size_t)p.krylov_steps * bwmax);
+      o.cnt = cv.take<unsigned>(2);
+      maxC = std::max(maxC, o.C);
+      maxbwall = std::max(maxbwall, bwmax);
+    }
+  const size_t o_td = cv.take<TriDev>(sai ? nb_prob : 1);
+  int64_t maxn_all = 1;
+  for (int ii = 0; ii < nb_prob; ++ii) maxn_all = std::max<int64_t>(maxn_all, probs[idx[ii]].op.n);
+  const size_t o_gpart = cv.take<double>(sai ? (size_t)nb_prob * ((maxn_all + 127) / 128) * 1024 : 1);
   const size_t o_pd = cv.take<ProbDev>(nb_prob);
   const size_t o_ed = cv.take<ExpmDev>(nb_prob);
   const size_t o_Dm = cv.take<double>((size_t)qmax_all * qmax_all);
@@ -746,6 +795,40 @@ pe_status march_batch(pe_ctx* ctx, const pe_problem* probs, const int* idx, int 
     e.qmax = qmax_all;
     e.kscale = 2.0 / (p.t1 - p.t0);
   }
+  std::vector<TriDev> ht(sai ? nb_prob : 0);
+  TriDev* tdd = (TriDev*)(base + o_td);
+  for (int ii = 0; ii < (sai ? nb_prob : 0); ++ii) {
+    const pe_problem& p = probs[idx[ii]];
+    const SaiOff& o = so[ii];
+    TriDev& t = ht[ii];
+    t = TriDev{};
+    t.n = p.op.n;
+    t.per_point = p.op.per_point;
+    if (!p.op.per_point) std::memcpy(t.c3, p.op.coeffs, 3 * sizeof(double));
+    t.coef = p.op.per_point ? p.op.coeffs : nullptr;
+    t.R = o.R;
+    t.C = o.C;
+    t.ta = (double*)(base + o.ta);
+    t.tinv = (double*)(base + o.tinv);
+    t.tc = (double*)(base + o.tc);
+    t.vL = (double*)(base + o.vL);
+    t.vR = (double*)(base + o.vR);
+    t.red = (double*)(base + o.red);
+    t.rrhs = (double*)(base + o.rrhs);
+    t.ru = (double*)(base + o.ru);
+    t.W = (double*)(base + o.W);
+    t.GW = (double*)(base + o.GW);
+    t.piv = (int32_t*)(base + o.piv);
+    t.cnt = (unsigned*)(base + o.cnt);
+    t.LU = he[ii].A;      // the exponential's work matrices are free until the trials
+    t.Kinv = he[ii].A2;
+    t.H = hd[ii].H;
+    pe::launch_zero_u32(t.cnt, 2, st);
+    hd[ii].Wb = t.W;
+    he[ii].sai = 1;
+    he[ii].Kinv = t.Kinv;
+    he[ii].GW = t.GW;
+  }
   std::vector<std::vector<double>> wv(nb_prob, std::vector<double>(qmax_all + 1));
   int guard = 0;
   const int trace = env_int("PARAEXP_TRACE", 0);
@@ -815,6 +898,25 @@ pe_status march_batch(pe_ctx* ctx, const pe_problem* probs, const int* idx, int 
       }
     }
     if (nact == 0) break;
+    // shift-and-invert: gamma from the step each cycle aims at; factor I - gamma L
+    int maxN0 = 1;
+    if (sai) {
+      for (int ii = 0; ii < nb_prob; ++ii) {
+        const pe_problem& p = probs[idx[ii]];
+        TriDev& t = ht[ii];
+        const ProbDev& d = hd[ii];
+        t.active = d.active;
+        if (!d.active) continue;
+        t.gamma = (p.sai_shift > 0.0 ? p.sai_shift : kSaiShift) * hs[ii].dtry;
+        t.bw = d.bw;
+        t.N0 = d.l * d.bw;
+        t.ldH = d.ldH;
+        he[ii].gamma = t.gamma;
+        maxN0 = std::max(maxN0, t.N0);
+      }
+      HCK(hipMemcpyAsync(tdd, ht.data(), sizeof(TriDev) * nb_prob, hipMemcpyHostToDevice, st));
+      pe::launch_tri_factor(tdd, nb_prob, maxC, st);
+    }
     // event markers cost GPU time, so a march times every kProfEvery-th restart cycle
     // (all of its block steps, so the sample spans the same step mix)
     ctx->prof_sample = (guard % kProfEvery) == 0;
@@ -845,8 +947,18 @@ pe_status march_batch(pe_ctx* ctx, const pe_problem* probs, const int* idx, int 
           cost.upd_bytes += c.upd_bytes;
           cost.flops += c.flops;
         }
-      run_block_step(ctx, dd, nb_prob, gx_p * groups, smem_p, gx_u, smem_u, j, j + 1, pe::MODE_ARNOLDI, mixed, cost,
-                     st);
+      if (sai) {
+        pe::launch_sai_solve(dd, tdd, nb_prob, maxC * maxbwall, maxn_all * maxbwall, j, mixed, st);
+        run_block_step(ctx, dd, nb_prob, gx_p * groups, smem_p, gx_u, smem_u, j, j + 1, pe::MODE_SAI, mixed, cost,
+                       st);
+      } else {
+        run_block_step(ctx, dd, nb_prob, gx_p * groups, smem_p, gx_u, smem_u, j, j + 1, pe::MODE_ARNOLDI, mixed, cost,
+                       st);
+      }
+    }
+    if (sai) {  // residual Gram of the last block, then K^{-1} for the projected operator
+      pe::launch_sai_gram(dd, tdd, nb_prob, maxn_all, (double*)(base + o_gpart), st);
+      pe::launch_hess_inverse(tdd, nb_prob, maxN0, st);
     }
     // ---- S6: projected exponential with step-size trials
     for (int ii = 0; ii < nb_prob; ++ii) he[ii].active = hd[ii].active;
@@ -1022,12 +1134,13 @@ pe_status march_batch(pe_ctx* ctx, const pe_problem* probs, const int* idx, int 
 pe_status march_all(pe_ctx* ctx, const pe_problem* probs, int nprob, const double* const* Ul,
                     const double* const* Pil, const int* ldPil, const int* ml, const int* ql, pe_report* reports,
                     hipStream_t st) {
-  for (int prec = 0; prec < 2; ++prec) {
+  for (int grp = 0; grp < 4; ++grp) {
+    const int prec = grp & 1, kry = grp >> 1;
     std::vector<int> idx;
     std::vector<const double*> U, Pi;
     std::vector<int> ld, m, q;
     for (int i = 0; i < nprob; ++i)
-      if ((int)probs[i].prec == prec) {
+      if ((int)probs[i].prec == prec && (int)probs[i].krylov == kry) {
         idx.push_back(i);
         U.push_back(Ul[i]);
         Pi.push_back(Pil[i]);
@@ -1342,6 +1455,8 @@ pe_status pe_wr_burgers(pe_ctx* ctx, const pe_wr_problem* wr, pe_report* reports
         q.svd_tol = w.svd_tol;
         q.fit_tol = w.fit_tol;
         q.prec = w.prec;
+        q.krylov = w.krylov;
+        q.sai_shift = w.sai_shift;
       }
       {
         const pe_status sb = pe_solve_batch(ctx, pr.data(), P, reports, stream);
@@ -1375,6 +1490,8 @@ pe_status pe_wr_burgers(pe_ctx* ctx, const pe_wr_problem* wr, pe_report* reports
         q.q_max = w.q_max;
         q.tol = w.tol;
         q.prec = w.prec;
+        q.krylov = w.krylov;
+        q.sai_shift = w.sai_shift;
         const double* nullp = nullptr;
         const int32_t zero = 0;
         pe_report rep;

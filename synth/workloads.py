@@ -46,6 +46,8 @@ class Problem:
     svd_tol: float = 1e-13
     fit_tol: float = 1e-13
     name: str = ""
+    krylov: int = 0             # 0: polynomial Krylov space, 1: shift-and-invert
+    sai_shift: float = 0.0      # shift-and-invert: gamma / cycle step (0: default)
 
     @property
     def s(self) -> int:
@@ -77,6 +79,8 @@ class BurgersProblem:
     svd_tol: float = 1e-10
     fit_tol: float = 1e-11
     name: str = ""
+    krylov: int = 0
+    sai_shift: float = 0.0
 
     def window_times(self, j: int) -> np.ndarray:
         t0 = self.T * j / self.P

@@ -1,0 +1,143 @@
+"""Shift-and-invert block Krylov (Sec. 2.1; Sec. 3.2) on the GPU through the C ABI,
+against the CPU oracle.  The oracle computes the exact solution of the semi-discrete
+problem with the compressed source, whatever Krylov space the solver uses, so the bars
+are those of the polynomial path: 1e-10 relative L2 (FP64), 1e-7 (FP32-stored basis)."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-10
+MIXED_TOL = 1e-7
+SAI = 1
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1509_04567_amd as pe
+    c = pe.Context(0)
+    yield c
+    c.close()
+
+
+def gpu_out(t):
+    return t.detach().cpu().numpy().T
+
+
+def sai(p, shift=0.0):
+    p.krylov = SAI
+    p.sai_shift = shift
+    return p
+
+
+@pytest.mark.parametrize("name", ["c1", "rand_shift", "rand_noshift", "rand_perpoint", "one_chunk"])
+def test_sai_expaction_stage_parity(ctx, name):
+    """Identical compressed source on both sides; only the time integration differs.
+    n = 200, 157, 190 cut into 32-row chunks with a longer last chunk; n = 45 is a single
+    chunk whose ends couple to each other."""
+    if name == "c1":
+        p = synth.config_c1()
+    elif name == "rand_shift":
+        p = synth.random_ade_problem(11, 200, n_out=6)
+    elif name == "rand_noshift":
+        p = synth.random_ade_problem(12, 157, n_out=4, shift=False)
+    elif name == "rand_perpoint":
+        p = synth.random_ade_problem(13, 190, per_point=True, n_out=4)
+    else:
+        p = synth.random_ade_problem(14, 45, n_out=3)
+    sai(p)
+    mdl = oracle.window_model(p)
+    ref, _ = oracle.solve_window(p, "dense", model=mdl)
+    outs, reps = ctx.expaction_batch([p], [mdl["U"].T], [mdl["Pi"]])
+    assert rel(gpu_out(outs[0]), ref) < FP64_TOL, reps[0]
+    assert not reps[0]["flags"] & 1
+
+
+def test_sai_c2_full_size_fp64(ctx):
+    """The benchmark workload (n = 8192, rank-7 source, l = 60) end to end: the shifted
+    inverse needs a few dozen restart cycles where the polynomial space needs ~750."""
+    p = sai(synth.config_c2())
+    ref, _ = oracle.solve_window(p, "spectral")
+    outs, reps = ctx.solve_batch([p])
+    assert rel(gpu_out(outs[0]), ref) < FP64_TOL, reps[0]
+    assert reps[0]["cycles"] <= 100, reps[0]
+    per_t = np.linalg.norm(gpu_out(outs[0]) - ref, axis=0) / np.linalg.norm(ref, axis=0)
+    assert per_t.max() < 10 * FP64_TOL
+
+
+def test_sai_c2_full_size_mixed(ctx):
+    import paper_1509_04567_amd as pe
+    p = sai(synth.config_c2(tol=1e-8))
+    ref, _ = oracle.solve_window(p, "spectral")
+    outs, reps = ctx.solve_batch([p], precision=pe.PE_MIXED)
+    assert rel(gpu_out(outs[0]), ref) < MIXED_TOL, reps[0]
+
+
+def test_sai_paraexp_windows_and_mixed_batch(ctx):
+    """Four Paraexp windows (eqs. 2.7-2.9) solved with the shifted inverse, plus one
+    polynomial-Krylov problem in the same call (the batch splits by Krylov space)."""
+    p = synth.config_c2(n=1024)
+    _, g_at = synth.c2_source(1024, 2)
+    wins = [sai(w) for w in synth.split_windows(p, 4, g_at, s=64)]
+    extra = synth.random_ade_problem(21, 130, n_out=3)
+    outs, reps = ctx.solve_batch(wins + [extra])
+    u = ctx.superpose(p.u0, outs[:4]).cpu().numpy().T
+    ref = oracle.solve_sequential(wins, "spectral")
+    assert rel(u, ref) < FP64_TOL, reps
+    ref_x, _ = oracle.solve_window(extra, "dense")
+    assert rel(gpu_out(outs[4]), ref_x) < FP64_TOL, reps[4]
+
+
+@pytest.mark.parametrize("n,s", [(4, 2), (5, 3)])
+def test_sai_smallest_grids(ctx, n, s):
+    x = synth.grid(n)
+    ts = synth.chebyshev_lobatto(0.0, 0.2, s)
+    G = np.outer(np.cos(2 * np.pi * x), 1.0 + ts)
+    p = synth.Problem(n=n, coeffs=synth.ade_coeffs(n, 1.0, 1e-2), u0=1.0 + np.sin(2 * np.pi * x), t0=0.0,
+                      t1=0.2, t_samples=ts, G=G, t_out=np.array([0.1, 0.2, 0.3]), shift=True, krylov_steps=3,
+                      rank_max=2, q_max=4, tol=1e-12, svd_tol=1e-13, fit_tol=1e-13, krylov=SAI)
+    ref, _ = oracle.solve_window(p, "dense")
+    outs, reps = ctx.solve_batch([p])
+    assert rel(gpu_out(outs[0]), ref) < FP64_TOL, reps[0]
+
+
+def test_sai_wide_blocks(ctx):
+    """Block width 32 (rank 31 plus the state) on 160 points with 6 steps: later blocks
+    exhaust the space and deflate, which leaves zero rows and columns in the projected
+    matrix that its inverse must step over."""
+    rng = np.random.default_rng(7)
+    n, s = 160, 48
+    x = synth.grid(n)
+    ts = synth.chebyshev_lobatto(0.0, 0.1, s)
+    G = sum(np.outer(np.sin(2 * np.pi * k * x + rng.uniform(0, 6.3)), np.cos(k * ts * 20.0 + k))
+            for k in range(1, 41))
+    p = synth.Problem(n=n, coeffs=synth.ade_coeffs(n, 1.0, 1e-2), u0=np.sin(2 * np.pi * x), t0=0.0, t1=0.1,
+                      t_samples=ts, G=G, t_out=np.array([0.05, 0.1]), shift=True, krylov_steps=6,
+                      rank_max=31, q_max=32, tol=1e-12, svd_tol=1e-14, fit_tol=1e-13, krylov=SAI)
+    mdl = oracle.window_model(p)
+    ref, _ = oracle.solve_window(p, "dense", model=mdl)
+    outs, reps = ctx.solve_batch([p])
+    assert reps[0]["rank"] == 31
+    assert not reps[0]["flags"] & 1, reps[0]
+    assert rel(gpu_out(outs[0]), ref) < FP64_TOL, reps[0]
+
+
+def test_sai_shift_choice_does_not_change_the_result(ctx):
+    """gamma only shapes the Krylov space: three shifts give the same solution."""
+    base = synth.random_ade_problem(31, 300, n_out=5)
+    ref, _ = oracle.solve_window(base, "dense")
+    for f in (0.03, 0.1, 0.5):
+        p = synth.random_ade_problem(31, 300, n_out=5)
+        sai(p, f)
+        outs, reps = ctx.solve_batch([p])
+        assert rel(gpu_out(outs[0]), ref) < FP64_TOL, (f, reps[0])
