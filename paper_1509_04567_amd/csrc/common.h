@@ -71,9 +71,10 @@ struct ProbDev {
 // ---------------------------------------------------------------------------------
 // Shift-and-invert operator (I - gamma L)^{-1} of one problem: a periodic tridiagonal
 // matrix T = I - gamma L solved by partition: the rows are cut into C chunks of R rows
-// (the last takes the remainder, R..2R-1 rows); each chunk is eliminated on its own
-// (Thomas), its coupling to the neighbouring chunks' end rows enters through two spike
-// vectors, and the 2C interface values solve a periodic block-tridiagonal system.
+// (C a power of two; the last chunk takes the remainder, R..2R-1 rows); each chunk is
+// eliminated on its own (Thomas), its coupling to the neighbouring chunks' end rows
+// enters through two spike vectors, and the 2C interface values solve a periodic
+// block-tridiagonal system by cyclic reduction.
 // ---------------------------------------------------------------------------------
 struct TriDev {
   int64_t n;
@@ -89,7 +90,7 @@ struct TriDev {
   double* tc;              // n: eliminated super-diagonal
   double* vL;              // n: left spikes  T_c^{-1} (a_s e_first)
   double* vR;              // n: right spikes T_c^{-1} (b_e e_last)
-  double* red;             // 14 C + 4: reduced system factors (see sai.hip)
+  double* red;             // cyclic-reduction coefficients of the interface system (sai.hip)
   double* rrhs;            // 2 C x bw: interface values of the chunk solutions
   double* ru;              // 2 C x bw: interface values of the solution
   double* W;               // n x bw row-major: the solution block

@@ -61,6 +61,37 @@ __device__ __forceinline__ bool arrive_last(unsigned* counter, unsigned expected
   return last;
 }
 
+// Bulk copy: element e of [0, cnt) is read with src(e) and stored with put(e, v); each
+// thread keeps kBulkDepth loads in flight (clamped addresses, unconditional loads)
+constexpr int kBulkDepth = 8;
+template <int D = kBulkDepth, typename Src, typename Put>
+__device__ __forceinline__ void bulk_load(int64_t cnt, Src src, Put put) {
+  const int T = blockDim.x;
+  for (int64_t e0 = threadIdx.x; e0 < cnt; e0 += D * (int64_t)T) {
+    double v[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      const int64_t e = e0 + (int64_t)k * T;
+      const double x = src(e < cnt ? e : cnt - 1);  // clamped, unconditional: loads stay in flight
+      v[k] = e < cnt ? x : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      const int64_t e = e0 + (int64_t)k * T;
+      if (e < cnt) put(e, v[k]);
+    }
+  }
+}
+
+// Workgroup barrier that orders LDS accesses only: outstanding global loads and stores
+// stay in flight across it (a __syncthreads waits for them as well)
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+
 // ---- access to the per-problem block workspace (ProbDev) ----------------------------
 template <typename TS>
 __device__ __forceinline__ TS* basis_ptr(const ProbDev& p);

@@ -53,11 +53,24 @@ void launch_expm_apply(ExpmDev* e, int level, int nprob, int maxN, hipStream_t s
 // Arnoldi step (V_j committed, W = (I - gamma L)^{-1} V_j into TriDev::W), the Gram of
 // (I - gamma L) V_l (part: nprob x ceil(n / 128) x 1024 doubles), inverse of the
 // projected matrix
+// LDS of the solve kernel (doubles, within gfx950's 160 KiB per workgroup); chunks per
+// workgroup of the solve and whether their rows are staged in LDS
+constexpr int kSaiLdsDoubles = 20000;
+__host__ __device__ inline int sai_chunks_per_group(int R, int bw) {
+  const int by_threads = 256 / bw, by_lds = kSaiLdsDoubles / ((R + 2) * (bw + 3)) - 1;
+  const int c = by_threads < by_lds ? by_threads : by_lds;
+  return c < 1 ? 1 : c;
+}
+// staged: the group's rows of V_j and the three elimination coefficients per row
+__host__ __device__ inline bool sai_stage_in_lds(int R, int bw) {
+  return (int64_t)(sai_chunks_per_group(R, bw) + 1) * (R + 2) * (bw + 3) <= kSaiLdsDoubles;
+}
+int sai_solve_groups(int C, int R, int bw);
 void launch_tri_factor(TriDev* td, int nprob, int maxC, hipStream_t st);
-void launch_sai_solve(ProbDev* d, TriDev* td, int nprob, int maxCbw, int64_t maxnbw, int j, int mixed,
+void launch_sai_solve(ProbDev* d, TriDev* td, int nprob, int groups, int64_t maxnbw, int j, int mixed,
                       hipStream_t st);
 void launch_sai_gram(ProbDev* d, TriDev* td, int nprob, int64_t maxn, double* part, hipStream_t st);
-void launch_hess_inverse(TriDev* td, int nprob, int maxN0, hipStream_t st);
+void launch_hess_inverse(TriDev* td, int nprob, int maxN0, int maxbw, hipStream_t st);
 
 // x = V y (+ output column)
 void launch_project(ProbDev* d, ExpmDev* e, int nprob, int64_t maxn, int max_lbw, int mixed, hipStream_t st);

@@ -325,26 +325,6 @@ void launch_add_column(int64_t n, int s, const double* G, int64_t ldG, const dou
 // put(e, v).  Each thread keeps kBulkDepth loads in flight, so a phase costs one or two
 // memory round trips however many elements a thread handles (data written by other
 // workgroups comes from other XCDs with microsecond latency).
-constexpr int kBulkDepth = 8;
-template <typename Src, typename Put>
-__device__ __forceinline__ void bulk_load(int64_t cnt, Src src, Put put) {
-  const int T = blockDim.x;
-  for (int64_t e0 = threadIdx.x; e0 < cnt; e0 += kBulkDepth * (int64_t)T) {
-    double v[kBulkDepth];
-#pragma unroll
-    for (int k = 0; k < kBulkDepth; ++k) {
-      const int64_t e = e0 + (int64_t)k * T;
-      const double x = src(e < cnt ? e : cnt - 1);  // clamped, unconditional (see cgs2_team)
-      v[k] = e < cnt ? x : 0.0;
-    }
-#pragma unroll
-    for (int k = 0; k < kBulkDepth; ++k) {
-      const int64_t e = e0 + (int64_t)k * T;
-      if (e < cnt) put(e, v[k]);
-    }
-  }
-}
-
 __device__ __forceinline__ int64_t wrap_row(int64_t g, int64_t n) { return g < 0 ? g + n : (g >= n ? g - n : g); }
 
 // Input block X (rows x bw, leading dimension ld, LDS) of the update kernel's chunk

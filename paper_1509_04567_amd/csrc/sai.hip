@@ -58,13 +58,20 @@ __device__ __forceinline__ void inv2(const double* m, double* o) {
   o[3] = m[0] * id;
 }
 
-// reduced-system layout inside TriDev::red (per chunk c, then 4 trailing doubles):
-//   Dinv[4c..4c+4)          inverse of the eliminated diagonal block
-//   Lm  [4C + 4c ..)        forward multiplier A_c Dinv_{c-1}
-//   Cc  [8C + 2c ..)        (vR_c[first], vR_c[last]): the coupling to F_{c+1}
-//   Z   [10C + 4c ..)       rows 2c, 2c+1 of Z = M0^{-1} P (two columns, row-major pairs)
-//   Sinv[14C ..14C+4)       (I + Q^T Z)^{-1}
-// For C = 1 the whole 2 x 2 system's inverse sits in Sinv.
+// The interface system (two unknowns per chunk: F_c, the first row, and G_c, the last)
+//   A_c u_{c-1} + u_c + C_c u_{c+1} = f_c,   u_c = (F_c, G_c), indices mod C,
+//   A_c = [[0, vL_c(first)], [0, vL_c(last)]],   C_c = [[vR_c(first), 0], [vR_c(last), 0]],
+// is solved by parallel cyclic reduction: C is a power of two, and level k (stride
+// s = 2^k) replaces row c by row c minus alpha_c row (c - s) minus beta_c row (c + s),
+// alpha_c = A_c D_{c-s}^{-1}, beta_c = C_c D_{c+s}^{-1}, which couples it to rows c -+ 2s;
+// after log2(C) levels both couplings land on row c itself and u_c = E_c f_c with
+// E_c = (A_c + D_c + C_c)^{-1}.  TriDev::red holds, per level, alpha_c and beta_c
+// (8 doubles per chunk), then E_c (4 per chunk).
+__device__ __forceinline__ int sai_levels(int C) {
+  int k = 0;
+  while ((1 << k) < C) ++k;
+  return k;
+}
 
 }  // namespace
 
@@ -108,186 +115,292 @@ __global__ __launch_bounds__(256) void k_tri_factor(const TriDev* __restrict__ t
   }
 }
 
-// one thread per problem: block elimination of the periodic interface system
-//   F_c + vL_c[0] G_{c-1} + vR_c[0] F_{c+1} = y_c[0],  G_c + vL_c[e] G_{c-1} + vR_c[e] F_{c+1} = y_c[e]
-// (chunk indices mod C): block tridiagonal M0 plus the two wrap-around couplings, which
-// enter by the Sherman-Morrison-Woodbury formula
-__global__ void k_tri_reduce_factor(const TriDev* __restrict__ tds) {
+// one workgroup per problem: the cyclic-reduction coefficients of the interface system,
+// one thread per chunk, the blocks of the current level in LDS
+__device__ __forceinline__ void mul2(const double* a, const double* b, double* o) {
+  o[0] = a[0] * b[0] + a[1] * b[2];
+  o[1] = a[0] * b[1] + a[1] * b[3];
+  o[2] = a[2] * b[0] + a[3] * b[2];
+  o[3] = a[2] * b[1] + a[3] * b[3];
+}
+__global__ __launch_bounds__(256) void k_tri_reduce_factor(const TriDev* __restrict__ tds) {
   const TriDev t = tds[blockIdx.x];
-  if (!t.active || threadIdx.x != 0) return;
-  const int C = t.C;
-  double* Dinv = t.red;
-  double* Lm = t.red + 4 * (int64_t)C;
-  double* Cc = t.red + 8 * (int64_t)C;
-  double* Z = t.red + 10 * (int64_t)C;
-  double* Sinv = t.red + 14 * (int64_t)C;
-  auto vLf = [&](int c) { return t.vL[chunk_start(t, c)]; };
-  auto vLe = [&](int c) { return t.vL[chunk_end(t, c) - 1]; };
-  auto vRf = [&](int c) { return t.vR[chunk_start(t, c)]; };
-  auto vRe = [&](int c) { return t.vR[chunk_end(t, c) - 1]; };
-  if (C == 1) {
-    // F = x_0, G = x_{n-1}: x_{s-1} = G and x_e = F within the single chunk
-    const double m[4] = {1.0 + vRf(0), vLf(0), vRe(0), 1.0 + vLe(0)};
-    inv2(m, Sinv);
-    return;
+  if (!t.active) return;
+  __shared__ double sA[4 * 256], sC[4 * 256], sD[4 * 256];
+  const int C = t.C, c = threadIdx.x;
+  const int nlev = sai_levels(C);
+  double A[4] = {0, 0, 0, 0}, Cm[4] = {0, 0, 0, 0}, D[4] = {1, 0, 0, 1};
+  if (c < C) {
+    A[1] = t.vL[chunk_start(t, c)];
+    A[3] = t.vL[chunk_end(t, c) - 1];
+    Cm[0] = t.vR[chunk_start(t, c)];
+    Cm[2] = t.vR[chunk_end(t, c) - 1];
   }
-  for (int c = 0; c < C; ++c) {
-    Cc[2 * c] = vRf(c);
-    Cc[2 * c + 1] = vRe(c);
-  }
-  // M0: D_0 = I; D_c = I - A_c Dinv_{c-1} C_{c-1}, with A_c = [[0, vLf],[0, vLe]] and
-  // C_c = [[vRf, 0],[vRe, 0]]
-  Dinv[0] = 1.0;
-  Dinv[1] = 0.0;
-  Dinv[2] = 0.0;
-  Dinv[3] = 1.0;
-  Lm[0] = Lm[1] = Lm[2] = Lm[3] = 0.0;
-  for (int c = 1; c < C; ++c) {
-    const double* Dp = Dinv + 4 * (c - 1);
-    // A_c Dp: A_c has only its second column (vLf(c), vLe(c))
-    const double l0 = vLf(c), l1 = vLe(c);
-    double L4[4] = {l0 * Dp[2], l0 * Dp[3], l1 * Dp[2], l1 * Dp[3]};
-    for (int k = 0; k < 4; ++k) Lm[4 * c + k] = L4[k];
-    // D = I - L4 C_{c-1}, C_{c-1} has only its first column (Cc[2(c-1)], Cc[2(c-1)+1])
-    const double c0 = Cc[2 * (c - 1)], c1 = Cc[2 * (c - 1) + 1];
-    const double D[4] = {1.0 - (L4[0] * c0 + L4[1] * c1), 0.0, -(L4[2] * c0 + L4[3] * c1), 1.0};
-    inv2(D, Dinv + 4 * c);
-  }
-  // Z = M0^{-1} P: P's columns are the wrap-around couplings, (vLf(0), vLe(0)) in block
-  // row 0 (coefficient of G_{C-1}) and (vRf(C-1), vRe(C-1)) in block row C-1
-  // (coefficient of F_0); forward sweep then back sweep, both columns at once
-  for (int col = 0; col < 2; ++col) {
-    // g_c = p_c - Lm_c g_{c-1}, stored in Z temporarily
-    for (int c = 0; c < C; ++c) {
-      double p0 = 0.0, p1 = 0.0;
-      if (col == 0 && c == 0) {
-        p0 = vLf(0);
-        p1 = vLe(0);
+  for (int lev = 0; lev < nlev; ++lev) {
+    const int s = 1 << lev;
+    if (c < C)
+      for (int k = 0; k < 4; ++k) {
+        sA[4 * c + k] = A[k];
+        sC[4 * c + k] = Cm[k];
+        sD[4 * c + k] = D[k];
       }
-      if (col == 1 && c == C - 1) {
-        p0 = vRf(C - 1);
-        p1 = vRe(C - 1);
+    __syncthreads();
+    if (c < C) {
+      const int m = (c - s + C) % C, p = (c + s) % C;
+      double Dm[4], Dp[4], al[4], be[4], t1[4], t2[4];
+      inv2(sD + 4 * m, Dm);
+      inv2(sD + 4 * p, Dp);
+      mul2(A, Dm, al);
+      mul2(Cm, Dp, be);
+      double* out = t.red + ((int64_t)lev * C + c) * 8;
+      for (int k = 0; k < 4; ++k) {
+        out[k] = al[k];
+        out[4 + k] = be[k];
       }
-      if (c > 0) {
-        const double* L4 = Lm + 4 * c;
-        const double g0 = Z[4 * (c - 1) + col], g1 = Z[4 * (c - 1) + 2 + col];
-        p0 -= L4[0] * g0 + L4[1] * g1;
-        p1 -= L4[2] * g0 + L4[3] * g1;
+      // D' = D - al C_{c-s} - be A_{c+s};  A' = -al A_{c-s};  C' = -be C_{c+s}
+      mul2(al, sC + 4 * m, t1);
+      mul2(be, sA + 4 * p, t2);
+      for (int k = 0; k < 4; ++k) D[k] -= t1[k] + t2[k];
+      mul2(al, sA + 4 * m, t1);
+      mul2(be, sC + 4 * p, t2);
+      for (int k = 0; k < 4; ++k) {
+        A[k] = -t1[k];
+        Cm[k] = -t2[k];
       }
-      Z[4 * c + col] = p0;
-      Z[4 * c + 2 + col] = p1;
     }
-    for (int c = C - 1; c >= 0; --c) {
-      double g0 = Z[4 * c + col], g1 = Z[4 * c + 2 + col];
-      if (c < C - 1) {  // g -= C_c y_{c+1}: C_c picks F_{c+1}
-        const double f1 = Z[4 * (c + 1) + col];
-        g0 -= Cc[2 * c] * f1;
-        g1 -= Cc[2 * c + 1] * f1;
-      }
-      const double* Di = Dinv + 4 * c;
-      Z[4 * c + col] = Di[0] * g0 + Di[1] * g1;
-      Z[4 * c + 2 + col] = Di[2] * g0 + Di[3] * g1;
-    }
+    __syncthreads();
   }
-  // S = I + Q^T Z, Q^T picks the entries G_{C-1} (row 2C-1) and F_0 (row 0)
-  const double S[4] = {1.0 + Z[4 * (C - 1) + 2 + 0], Z[4 * (C - 1) + 2 + 1], Z[0], 1.0 + Z[1]};
-  inv2(S, Sinv);
+  if (c < C) {
+    // after the last level both couplings refer to row c itself
+    const double S[4] = {A[0] + D[0] + Cm[0], A[1] + D[1] + Cm[1], A[2] + D[2] + Cm[2], A[3] + D[3] + Cm[3]};
+    inv2(S, t.red + ((int64_t)nlev * C) * 8 + 4 * (int64_t)c);
+  }
 }
 
 // ---- the solve of one Arnoldi step ----------------------------------------------------
-// W = T^{-1} V_j.  One thread per (chunk, column): V_j's rows of the chunk are formed from
-// the step's TSQR factors (first-pass factors when the previous step skipped its second
-// pass) and committed to basis block j in the storage precision; the chunk solution y is
-// written to W and its end values to rrhs.  The last workgroup of the problem solves the
-// interface system, one thread per column.
+// V_j = Qloc Qs (the step's TSQR factors; first-pass factors when the previous step
+// skipped its second pass), committed to basis block j in the storage precision (and in
+// fp64 for block 0 of an fp32 basis).  One thread per entry.
+template <typename TS>
+__global__ __launch_bounds__(256) void k_sai_commit(const ProbDev* __restrict__ pds, int j) {
+  const ProbDev p = pds[blockIdx.y];
+  if (!p.active || j >= p.l) return;
+  const int bw = p.bw;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= p.n * bw) return;
+  const bool first = p.cnt[2 * p.nbmax + 1] != 0;
+  const int64_t r = e / bw;
+  const int col = (int)(e - r * bw);
+  const double v = tsqr_entry(p, first ? p.Qloc1 : p.Qloc2, first ? p.Qs1 : p.Qs2, r, col);
+  basis_ptr<TS>(p)[(int64_t)j * p.n * bw + e] = (TS)v;
+  if (!std::is_same<TS, double>::value && j == 0) p.V[e] = v;
+}
+
+// The interface system by cyclic reduction (the last workgroup of the solve): f, g are
+// ping-pong buffers of bw interface vectors, column-major (entry (2c + k) of column col at
+// col 2C + 2c + k: F_c for k = 0, G_c for k = 1; consecutive chunks are consecutive in
+// memory, so a wave's accesses spread over the LDS banks); the result goes to u (same
+// layout).  Thread c < C takes chunk c for every column; a level's coefficients are
+// fetched one level ahead, so their latency hides behind the current level.  The
+// workgroup barrier orders the levels.
+template <bool kLdsBuf>
+__device__ void pcr_solve(int C, int bw, const double* __restrict__ red, double* f, double* g, double* u) {
+  const int nlev = sai_levels(C);
+  const int c = threadIdx.x;
+  const bool act = c < C;
+  const int64_t ld = 2 * (int64_t)C;
+  double ab[8], nx[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) ab[k] = (act && nlev > 0) ? red[(int64_t)c * 8 + k] : 0.0;
+  for (int lev = 0; lev < nlev; ++lev) {
+    const int s = 1 << lev;
+    if (lev + 1 < nlev) {
+#pragma unroll
+      for (int k = 0; k < 8; ++k) nx[k] = act ? red[((int64_t)(lev + 1) * C + c) * 8 + k] : 0.0;
+    } else {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) nx[k] = act ? red[((int64_t)nlev * C) * 8 + 4 * (int64_t)c + k] : 0.0;
+    }
+    if (act) {
+      const int m = (c - s + C) % C, p = (c + s) % C;
+#pragma unroll 4
+      for (int col = 0; col < bw; ++col) {
+        const double* fc = f + col * ld;
+        const double f0 = fc[2 * c], f1 = fc[2 * c + 1];
+        const double m0 = fc[2 * m], m1 = fc[2 * m + 1];
+        const double p0 = fc[2 * p], p1 = fc[2 * p + 1];
+        g[col * ld + 2 * c] = f0 - (ab[0] * m0 + ab[1] * m1) - (ab[4] * p0 + ab[5] * p1);
+        g[col * ld + 2 * c + 1] = f1 - (ab[2] * m0 + ab[3] * m1) - (ab[6] * p0 + ab[7] * p1);
+      }
+    }
+    // LDS buffers: the barrier leaves the coefficient fetch of the next level in flight
+    if (kLdsBuf)
+      lds_barrier();
+    else
+      __syncthreads();
+    double* tmp = f;
+    f = g;
+    g = tmp;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) ab[k] = nx[k];
+  }
+  if (nlev == 0) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) ab[k] = act ? red[4 * (int64_t)c + k] : 0.0;
+  }
+  if (act)
+    for (int col = 0; col < bw; ++col) {  // u_c = E_c f_c, E_c now in ab[0..3]
+      const double f0 = f[col * ld + 2 * c], f1 = f[col * ld + 2 * c + 1];
+      u[col * ld + 2 * c] = ab[0] * f0 + ab[1] * f1;
+      u[col * ld + 2 * c + 1] = ab[2] * f0 + ab[3] * f1;
+    }
+}
+
+// W = T^{-1} V_j (V_j committed): a workgroup takes cpw consecutive chunks (cpw bw <= 256
+// threads); when their rows of V_j fit in LDS they are staged there -- each chunk in its
+// own region, padded by two doubles so that the chunks a wave works on start in different
+// LDS banks -- and thread (chunk, column) eliminates its chunk in LDS, otherwise it works
+// on W in global memory.  The chunk solutions y go to W and their end values to rrhs
+// (column-major interface vectors, see pcr_solve).  The last workgroup of the problem
+// solves the interface system.
 template <typename TS>
 __global__ __launch_bounds__(256) void k_sai_solve(const ProbDev* __restrict__ pds, const TriDev* __restrict__ tds,
                                                    int j) {
   const ProbDev p = pds[blockIdx.y];
   const TriDev t = tds[blockIdx.y];
   if (!p.active || !t.active || j >= p.l) return;
+  extern __shared__ double xs[];
   __shared__ int flag;
-  const int bw = p.bw;
-  const int g = blockIdx.x * blockDim.x + threadIdx.x;
-  const bool first = p.cnt[2 * p.nbmax + 1] != 0;
-  const double* Ql = first ? p.Qloc1 : p.Qloc2;
-  const double* Qs = first ? p.Qs1 : p.Qs2;
-  TS* V = basis_ptr<TS>(p);
-  const int64_t blk = p.n * bw;
-  if (g < t.C * bw) {
-    const int c = g / bw, col = g % bw;
-    const int64_t s = chunk_start(t, c), e = chunk_end(t, c);
-    double y = 0.0;
-    for (int64_t i = s; i < e; ++i) {
-      const double v = tsqr_entry(p, Ql, Qs, i, col);
-      const TS vs = (TS)v;
-      V[(int64_t)j * blk + i * bw + col] = vs;
-      if (!std::is_same<TS, double>::value && j == 0) p.V[i * bw + col] = v;
-      const double f = (double)vs;
-      y = (i == s) ? f * t.tinv[i] : (f - t.ta[i] * y) * t.tinv[i];
-      t.W[i * bw + col] = y;
+  const int bw = p.bw, tid = threadIdx.x, R = t.R;
+  const int cpw = sai_chunks_per_group(R, bw);
+  const bool lds = sai_stage_in_lds(R, bw);
+  const int c0 = blockIdx.x * cpw;
+  const int64_t ld = 2 * (int64_t)t.C;
+  const TS* V = basis_ptr<TS>(p) + (int64_t)j * p.n * bw;
+  if (c0 < t.C) {
+    const int c1 = min(t.C, c0 + cpw);
+    const int cl = tid / bw, col = tid - (tid / bw) * bw;
+    const int c = c0 + cl;
+    const bool mine = cl < cpw && c < c1;
+    if (lds) {
+      // chunk k of the group: values at xv(k) (rows x bw), coefficients at xa(k), xi(k),
+      // xc(k) (rows each); regions padded by 2 doubles, the group's last chunk may be long
+      const int xstr = R * bw + 2, cstr = R + 2;
+      const int rows_last = (int)(chunk_end(t, c1 - 1) - chunk_start(t, c1 - 1));
+      double* xv0 = xs;
+      double* xa0 = xs + (int64_t)(c1 - c0 - 1) * xstr + rows_last * bw + 2;
+      const int cspan = (c1 - c0 - 1) * cstr + rows_last + 2;
+      double* xi0 = xa0 + cspan;
+      double* xc0 = xi0 + cspan;
+      // one bulk phase for all of the group's values and coefficients; chunk k of the
+      // group is min(row / R, nch - 1) (its last chunk may be long)
+      const int nch = c1 - c0;
+      const int64_t rs = chunk_start(t, c0);
+      const int nrows = (int)(chunk_end(t, c1 - 1) - rs);
+      const int rbw = R * bw;
+      bulk_load<16>(
+          (int64_t)nrows * bw, [&](int64_t q) -> double { return (double)V[rs * bw + q]; },
+          [&](int64_t q, double v) {
+            const int k = min((int)q / rbw, nch - 1);
+            xv0[q + 2 * k] = v;
+          });
+      bulk_load<16>(
+          3 * (int64_t)nrows,
+          [&](int64_t q) -> double {
+            const int a = (int)q / nrows, r = (int)q - a * nrows;
+            const double* src = a == 0 ? t.ta : (a == 1 ? t.tinv : t.tc);
+            return src[rs + r];
+          },
+          [&](int64_t q, double v) {
+            const int a = (int)q / nrows, r = (int)q - a * nrows;
+            const int k = min(r / R, nch - 1);
+            double* dst = a == 0 ? xa0 : (a == 1 ? xi0 : xc0);
+            dst[r + 2 * k] = v;
+          });
+      lds_barrier();
+      if (mine) {
+        const int e0 = (int)(chunk_end(t, c) - chunk_start(t, c));
+        double* __restrict__ x = xv0 + (int64_t)cl * xstr + col;
+        const double* __restrict__ cta_ = xa0 + (int64_t)cl * cstr;
+        const double* __restrict__ cti_ = xi0 + (int64_t)cl * cstr;
+        const double* __restrict__ ctc_ = xc0 + (int64_t)cl * cstr;
+        // both sweeps in batches of 8 rows: the batch's operands are read before any
+        // of its results is written, so the loads overlap and only the recurrence waits
+        constexpr int B = 8;
+        double y = 0.0;
+        for (int i0 = 0; i0 < e0; i0 += B) {
+          double xq[B], av[B], iv[B];
+#pragma unroll
+          for (int q = 0; q < B; ++q) {
+            const int i = i0 + q < e0 ? i0 + q : e0 - 1;
+            xq[q] = x[i * bw];
+            av[q] = cta_[i];
+            iv[q] = cti_[i];
+          }
+#pragma unroll
+          for (int q = 0; q < B; ++q) {
+            if (i0 + q >= e0) break;
+            y = (i0 + q == 0) ? xq[q] * iv[q] : (xq[q] - av[q] * y) * iv[q];
+            xq[q] = y;
+          }
+#pragma unroll
+          for (int q = 0; q < B; ++q)
+            if (i0 + q < e0) x[(i0 + q) * bw] = xq[q];
+        }
+        st_agent(t.rrhs + col * ld + 2 * c + 1, y);
+        for (int i1 = e0 - 2; i1 >= 0; i1 -= B) {  // rows i1, i1 - 1, ..., down to 0
+          double xq[B], cv[B];
+#pragma unroll
+          for (int q = 0; q < B; ++q) {
+            const int i = i1 - q >= 0 ? i1 - q : 0;
+            xq[q] = x[i * bw];
+            cv[q] = ctc_[i];
+          }
+#pragma unroll
+          for (int q = 0; q < B; ++q) {
+            if (i1 - q < 0) break;
+            y = xq[q] - cv[q] * y;
+            xq[q] = y;
+          }
+#pragma unroll
+          for (int q = 0; q < B; ++q)
+            if (i1 - q >= 0) x[(i1 - q) * bw] = xq[q];
+        }
+        st_agent(t.rrhs + col * ld + 2 * c, y);
+      }
+      lds_barrier();  // the interface values' stores stay in flight
+      for (int q = tid; q < nrows * bw; q += 256) t.W[rs * bw + q] = xv0[q + 2 * min(q / rbw, nch - 1)];
+    } else if (mine) {
+      const int64_t s = chunk_start(t, c), e = chunk_end(t, c);
+      double* x = t.W + s * bw + col;
+      const TS* v = V + s * bw + col;
+      double y = 0.0;
+      for (int64_t i = s; i < e; ++i) {
+        const double f = (double)v[(i - s) * bw];
+        y = (i == s) ? f * t.tinv[i] : (f - t.ta[i] * y) * t.tinv[i];
+        x[(i - s) * bw] = y;
+      }
+      st_agent(t.rrhs + col * ld + 2 * c + 1, y);
+      for (int64_t i = e - 2; i >= s; --i) {
+        y = x[(i - s) * bw] - t.tc[i] * y;
+        x[(i - s) * bw] = y;
+      }
+      st_agent(t.rrhs + col * ld + 2 * c, y);
     }
-    double x = y;
-    st_agent(t.rrhs + (int64_t)(2 * c + 1) * bw + col, x);
-    for (int64_t i = e - 2; i >= s; --i) {
-      x = t.W[i * bw + col] - t.tc[i] * x;
-      t.W[i * bw + col] = x;
-    }
-    st_agent(t.rrhs + (int64_t)(2 * c) * bw + col, x);
   }
   if (!arrive_last(t.cnt, gridDim.x, &flag)) return;
-  if (threadIdx.x == 0) atomicExch(t.cnt, 0u);
-  const int col = threadIdx.x;
-  if (col >= bw) return;
+  if (tid == 0) atomicExch(t.cnt, 0u);
   const int C = t.C;
-  const double* Dinv = t.red;
-  const double* Lm = t.red + 4 * (int64_t)C;
-  const double* Cc = t.red + 8 * (int64_t)C;
-  const double* Z = t.red + 10 * (int64_t)C;
-  const double* Sinv = t.red + 14 * (int64_t)C;
-  const double* f = t.rrhs;
-  double* u = t.ru;
-  auto F = [&](int c) -> double& { return u[(int64_t)(2 * c) * bw + col]; };
-  auto G = [&](int c) -> double& { return u[(int64_t)(2 * c + 1) * bw + col]; };
-  if (C == 1) {
-    const double f0 = f[col], f1 = f[bw + col];
-    F(0) = Sinv[0] * f0 + Sinv[1] * f1;
-    G(0) = Sinv[2] * f0 + Sinv[3] * f1;
-    return;
-  }
-  // y = M0^{-1} f (forward sweep into u, then back sweep)
-  double g0 = 0.0, g1 = 0.0;
-  for (int c = 0; c < C; ++c) {
-    double a0 = f[(int64_t)(2 * c) * bw + col], a1 = f[(int64_t)(2 * c + 1) * bw + col];
-    if (c > 0) {
-      const double* L4 = Lm + 4 * c;
-      a0 -= L4[0] * g0 + L4[1] * g1;
-      a1 -= L4[2] * g0 + L4[3] * g1;
-    }
-    F(c) = a0;
-    G(c) = a1;
-    g0 = a0;
-    g1 = a1;
-  }
-  double fnext = 0.0;
-  for (int c = C - 1; c >= 0; --c) {
-    double a0 = F(c), a1 = G(c);
-    if (c < C - 1) {
-      a0 -= Cc[2 * c] * fnext;
-      a1 -= Cc[2 * c + 1] * fnext;
-    }
-    const double* Di = Dinv + 4 * c;
-    const double y0 = Di[0] * a0 + Di[1] * a1, y1 = Di[2] * a0 + Di[3] * a1;
-    F(c) = y0;
-    G(c) = y1;
-    fnext = y0;
-  }
-  // Woodbury: u = y - Z Sinv (y[G_{C-1}], y[F_0])
-  const double q0 = G(C - 1), q1 = F(0);
-  const double w0 = Sinv[0] * q0 + Sinv[1] * q1, w1 = Sinv[2] * q0 + Sinv[3] * q1;
-  for (int c = 0; c < C; ++c) {
-    F(c) -= Z[4 * c] * w0 + Z[4 * c + 1] * w1;
-    G(c) -= Z[4 * c + 2] * w0 + Z[4 * c + 3] * w1;
+  const int64_t nf = 2 * (int64_t)C * bw;
+  __syncthreads();
+  if (2 * nf <= kSaiLdsDoubles) {
+    double* f = xs;
+    double* g = xs + nf;
+    bulk_load(nf, [&](int64_t e) -> double { return t.rrhs[e]; }, [&](int64_t e, double v) { f[e] = v; });
+    __syncthreads();
+    pcr_solve<true>(C, bw, t.red, f, g, t.ru);
+  } else {
+    pcr_solve<false>(C, bw, t.red, t.rrhs, t.ru, t.ru);  // ping-pong in global memory (wide blocks)
   }
 }
 
@@ -303,8 +416,8 @@ __global__ __launch_bounds__(256) void k_sai_recon(const TriDev* __restrict__ td
   const int col = (int)(g % bw);
   const int c = tri_chunk_of(t, r);
   const int cm = c == 0 ? t.C - 1 : c - 1, cp = c == t.C - 1 ? 0 : c + 1;
-  const double Gm = t.ru[(int64_t)(2 * cm + 1) * bw + col];
-  const double Fp = t.ru[(int64_t)(2 * cp) * bw + col];
+  const double Gm = t.ru[(int64_t)col * 2 * t.C + 2 * cm + 1];
+  const double Fp = t.ru[(int64_t)col * 2 * t.C + 2 * cp];
   t.W[g] -= Gm * t.vL[r] + Fp * t.vR[r];
 }
 
@@ -355,142 +468,326 @@ __global__ __launch_bounds__(kGramRows) void k_sai_gram(const ProbDev* __restric
 }
 
 // ---- inverse of the projected matrix --------------------------------------------------
-// LU with row interchanges of the block upper Hessenberg K (N0 = l bw, blocks of bw; the
-// blocks below the subdiagonal are zero and are never read from H).  Column k can only
-// have nonzeros down to row (k / bw + 2) bw - 1, so the pivot search and the elimination
-// stay in that band.  One workgroup per problem, factors in place in LU (ld N0).  A
-// deflated basis column gives a zero row and column and a unit pivot; any other zero
-// pivot makes the inverse NaN (the march then stops on the non-finite projected matrix).
+// K (N0 = l bw) is block upper Hessenberg with blocks of bw: column k has nonzeros down
+// to row pe(k) = min(N0, (k / bw + 2) bw) - 1 only.  LU with row interchanges, done one
+// block column (panel) at a time with the 2 bw band rows of the panel in LDS when they
+// fit (else in place in global memory):
+//   (a) one wave factors the panel: for each of its columns k the pivot is the largest
+//       entry of column k in rows [k, pe), rows k and pivot are exchanged in the panel
+//       columns >= k only (LINPACK storage: multipliers stay where they were computed),
+//       the multipliers are formed and the rest of the panel updated;
+//   (b) every thread takes trailing columns and applies the panel's interchanges and
+//       eliminations to them in order;
+//   (c) the finished rows (and the panel multipliers of the lower band rows) go back to
+//       global memory and the next block row of K comes in.
+// A deflated basis column (a zero vector) leaves row and column k of K zero: it gets a
+// unit pivot (K^{-1} = 1 there, the projected operator 0).  A zero pivot column with a
+// nonzero row (a singular K) makes the result NaN, and the march stops on the non-finite
+// projected matrix.
+__device__ __forceinline__ bool khess_in_block(int r, int c, int bw) { return r / bw <= c / bw + 1; }
+
+// the panel of a block column (rows [k0, pe), columns [k0, k1), BW >= k1 - k0): one
+// wave, lane q holds row k0 + q of the panel in registers; pivots by readlane
+template <int BW, typename At>
+__device__ __forceinline__ void lu_panel(At& at, int* pv, int* bad, int k0, int k1, int pe, int N0, int lane) {
+  const int nb = pe - k0, nc = k1 - k0;
+  double row[BW];
+#pragma unroll
+  for (int c = 0; c < BW; ++c) row[c] = (lane < nb && c < nc) ? at(k0 + lane, k0 + c) : 0.0;
+  auto bcast = [](double v, int src) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), src);
+    return __hiloint2double(hi, lo);
+  };
+#pragma unroll
+  for (int kq = 0; kq < BW; ++kq) {
+    if (kq >= nc) break;
+    // pivot: the largest |entry| of column kq in rows kq..nb-1 (smallest row among equals)
+    double best = -1.0;
+    int bi = kq;
+    for (int q = kq; q < nb; ++q) {
+      const double v = fabs(bcast(row[kq], q));
+      if (v > best) {
+        best = v;
+        bi = q;
+      }
+    }
+    if (!(best > 0.0)) {
+      // zero column: a deflated basis direction when row kq is zero as well
+      int nz = 0;
+#pragma unroll
+      for (int c = 0; c < BW; ++c)
+        if (c > kq && c < nc && lane == kq) nz |= (row[c] != 0.0);
+      for (int c = k1 + lane; c < N0; c += 64) nz |= (at(k0 + kq, c) != 0.0);
+      if (__any(nz) && lane == 0) *bad = 1;
+      if (lane == kq) row[kq] = 1.0;
+      if (lane == 0) pv[kq] = k0 + kq;
+      continue;
+    }
+    if (lane == 0) pv[kq] = k0 + bi;
+    if (bi != kq) {  // exchange rows kq and bi in panel columns >= kq
+#pragma unroll
+      for (int c = 0; c < BW; ++c) {
+        if (c < kq) continue;
+        const double vk = bcast(row[c], kq), vb = bcast(row[c], bi);
+        if (lane == kq) row[c] = vb;
+        if (lane == bi) row[c] = vk;
+      }
+    }
+    double prow[BW];  // the pivot row, read by every lane
+#pragma unroll
+    for (int c = 0; c < BW; ++c) prow[c] = c >= kq ? bcast(row[c], kq) : 0.0;
+    if (lane > kq && lane < nb) {
+      const double m = row[kq] / prow[kq];
+      row[kq] = m;
+#pragma unroll
+      for (int c = 0; c < BW; ++c)
+        if (c > kq) row[c] -= m * prow[c];
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < BW; ++c)
+    if (lane < nb && c < nc) at(k0 + lane, k0 + c) = row[c];
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+}
+
+// the trailing columns of a panel (rows [k0, pe), B2 >= pe - k0 compile-time slots):
+// interchanges and eliminations in order, the column in registers
+template <int B2, typename At>
+__device__ __forceinline__ void lu_trailing(At& at, const int* pv, int k0, int k1, int pe, int N0, int tid) {
+  const int nb = pe - k0;
+  for (int c = k1 + tid; c < N0; c += 256) {
+    double xr[B2];
+#pragma unroll
+    for (int q = 0; q < B2; ++q) xr[q] = q < nb ? at(k0 + q, c) : 0.0;
+#pragma unroll
+    for (int kq = 0; kq < B2 / 2; ++kq) {
+      if (k0 + kq >= k1) break;
+      const int pq = pv[kq] - k0;  // pivot row, relative to k0
+      double xk = 0.0, xo = 0.0;
+#pragma unroll
+      for (int q = 0; q < B2; ++q) {
+        if (q == pq) xk = xr[q];
+        if (q == kq) xo = xr[q];
+      }
+#pragma unroll
+      for (int q = 0; q < B2; ++q) {
+        if (q == pq) xr[q] = xo;
+        if (q == kq) xr[q] = xk;
+      }
+      if (xk != 0.0) {
+#pragma unroll
+        for (int q = kq + 1; q < B2; ++q)
+          if (q < nb) xr[q] -= at(k0 + q, k0 + kq) * xk;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < B2; ++q)
+      if (q < nb) at(k0 + q, c) = xr[q];
+  }
+}
+
+template <bool kLds>
 __global__ __launch_bounds__(256) void k_hess_lu(const TriDev* __restrict__ tds) {
   const TriDev t = tds[blockIdx.x];
   if (!t.active) return;
-  const int N0 = t.N0, bw = t.bw, tid = threadIdx.x;
-  double* A = t.LU;
-  __shared__ int piv_s;
+  extern __shared__ double band[];
+  __shared__ int pv[32];
   __shared__ int bad;
+  const int N0 = t.N0, bw = t.bw, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int l = N0 / bw;
+  double* A = t.LU;
+  // current panel: rows [k0, k0 + bw) sit in band slots hb0.., rows [k0 + bw, k0 + 2 bw)
+  // in slots hb1.. (the halves alternate from panel to panel)
+  int k0 = 0, hb0 = 0, hb1 = bw;
+  auto at = [&](int r, int c) -> double& {
+    if (kLds) {
+      const int rl = r - k0;
+      return band[(int64_t)(rl < bw ? hb0 + rl : hb1 + rl - bw) * N0 + c];
+    }
+    return A[(int64_t)r + (int64_t)N0 * c];
+  };
   if (tid == 0) bad = 0;
-  for (int64_t e = tid; e < (int64_t)N0 * N0; e += 256) {
-    const int r = (int)(e % N0), c = (int)(e / N0);
-    A[e] = (r / bw <= c / bw + 1) ? t.H[(int64_t)r + t.ldH * c] : 0.0;
+  if (kLds) {
+    // block rows 0 and 1 of K: every column may be nonzero
+    const int rows = min(N0, 2 * bw);
+    bulk_load(
+        (int64_t)rows * N0, [&](int64_t e) -> double { return t.H[(int64_t)(e % rows) + t.ldH * (e / rows)]; },
+        [&](int64_t e, double v) { band[(e % rows) * N0 + e / rows] = v; });
+  } else {
+    for (int64_t e = tid; e < (int64_t)N0 * N0; e += 256) {
+      const int r = (int)(e % N0), c = (int)(e / N0);
+      A[e] = c >= (r / bw - 1) * bw ? t.H[(int64_t)r + t.ldH * c] : 0.0;
+    }
   }
   __syncthreads();
-  for (int k = 0; k < N0; ++k) {
-    const int rlim = min(N0, (k / bw + 2) * bw);
-    if (tid < 64) {
-      double best = -1.0;
-      int bi = k;
-      for (int i = k + tid; i < rlim; i += 64) {
-        const double v = fabs(A[i + (int64_t)N0 * k]);
-        if (v > best) {
-          best = v;
-          bi = i;
-        }
-      }
-      // wave argmax (largest value, smallest row among equals)
-      for (int off = 32; off > 0; off >>= 1) {
-        const double ob = __shfl_down(best, off);
-        const int oi = __shfl_down(bi, off);
-        if (ob > best || (ob == best && oi < bi)) {
-          best = ob;
-          bi = oi;
-        }
-      }
-      if (tid == 0) {
-        piv_s = (best > 0.0) ? bi : -1;
-        t.piv[k] = (best > 0.0) ? bi : k;
-      }
+  for (int jb = 0; jb < l; ++jb) {
+    k0 = jb * bw;
+    hb0 = (jb & 1) * bw;
+    hb1 = bw - hb0;
+    const int k1 = k0 + bw, pe = min(N0, k1 + bw);
+    // (a) panel
+    if (w == 0) {
+      if (bw <= 8)
+        lu_panel<8>(at, pv, &bad, k0, k1, pe, N0, lane);
+      else if (bw <= 16)
+        lu_panel<16>(at, pv, &bad, k0, k1, pe, N0, lane);
+      else
+        lu_panel<32>(at, pv, &bad, k0, k1, pe, N0, lane);
     }
     __syncthreads();
-    if (piv_s < 0) {
-      // A zero column: the Arnoldi process deflated basis column k (a zero vector), which
-      // leaves row and column k of K zero.  That direction carries nothing, so it gets a
-      // unit pivot (K^{-1} = 1 there, the projected operator 0).  A zero column with a
-      // nonzero row would be a singular K: the inverse is then flagged NaN.
-      int nz = 0;
-      for (int c = k + 1 + tid; c < N0; c += 256) nz |= (A[k + (int64_t)N0 * c] != 0.0);
-      if (__syncthreads_or(nz)) {
-        if (tid == 0) bad = 1;
-      } else if (tid == 0) {
-        A[k + (int64_t)N0 * k] = 1.0;
+    // (b) trailing columns: the panel's interchanges and eliminations, in order, on the
+    // column's 2 bw band entries held in registers
+    if (bw <= 8)
+      lu_trailing<16>(at, pv, k0, k1, pe, N0, tid);
+    else if (bw <= 16)
+      lu_trailing<32>(at, pv, k0, k1, pe, N0, tid);
+    else
+      lu_trailing<64>(at, pv, k0, k1, pe, N0, tid);
+    if (tid == 0)
+      for (int k = k0; k < k1; ++k) t.piv[k] = pv[k - k0];
+    __syncthreads();
+    if (kLds) {
+      // (c) finished rows k0..k1-1 (columns >= k0) and the panel multipliers of the rows
+      // below; then block row jb + 2 of K (nonzero from column block jb + 1 on) enters
+      // the freed slots
+      for (int e = tid; e < bw * (N0 - k0); e += 256) {
+        const int r = k0 + e % bw, c = k0 + e / bw;
+        A[(int64_t)r + (int64_t)N0 * c] = at(r, c);
+      }
+      const int nlow = pe - k1;
+      for (int e = tid; e < nlow * bw; e += 256) {
+        const int r = k1 + e % nlow, c = k0 + e / nlow;
+        A[(int64_t)r + (int64_t)N0 * c] = at(r, c);
       }
       __syncthreads();
-      continue;
+      const int nr0 = k1 + bw, nr1 = min(N0, nr0 + bw), nnew = nr1 - nr0;
+      if (nnew > 0)
+        bulk_load(
+            (int64_t)nnew * (N0 - k1),
+            [&](int64_t e) -> double { return t.H[(int64_t)(nr0 + e % nnew) + t.ldH * (k1 + e / nnew)]; },
+            [&](int64_t e, double v) { band[(int64_t)(hb0 + e % nnew) * N0 + k1 + e / nnew] = v; });
+      __syncthreads();
     }
-    const int pr = piv_s;
-    if (pr != k)
-      for (int c = tid; c < N0; c += 256) {
-        const double x = A[k + (int64_t)N0 * c];
-        A[k + (int64_t)N0 * c] = A[pr + (int64_t)N0 * c];
-        A[pr + (int64_t)N0 * c] = x;
-      }
-    __syncthreads();
-    const double dinv = 1.0 / A[k + (int64_t)N0 * k];
-    for (int i = k + 1 + tid; i < rlim; i += 256) A[i + (int64_t)N0 * k] *= dinv;
-    __syncthreads();
-    const int nr = rlim - k - 1;
-    for (int e = tid; e < nr * (N0 - k - 1); e += 256) {
-      const int i = k + 1 + e % nr, c = k + 1 + e / nr;
-      A[i + (int64_t)N0 * c] -= A[i + (int64_t)N0 * k] * A[k + (int64_t)N0 * c];
-    }
-    __syncthreads();
   }
   if (bad && tid == 0) A[0] = __longlong_as_double(0x7ff8000000000000LL);
 }
 
-// Kinv = K^{-1}: one wave per column of the identity: row interchanges, unit lower
-// forward substitution, upper back substitution; the column lives in LDS
+// Kinv = K^{-1}: one wave per column of the identity, the column in LDS: forward sweep
+// with the interchanges and multipliers in the order they were made (LINPACK storage; the
+// multipliers of column k sit in rows (k, pe(k)) and are staged in LDS for the
+// workgroup when they fit), then back substitution with U, whose columns are staged in
+// LDS a block at a time by the whole workgroup.
+__device__ __forceinline__ void lds_order() {
+  __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): this wave's LDS operations are done
+  __builtin_amdgcn_wave_barrier();
+}
+template <bool kStageL>
 __global__ __launch_bounds__(256) void k_hess_inv(const TriDev* __restrict__ tds) {
   const TriDev t = tds[blockIdx.y];
   if (!t.active) return;
   extern __shared__ double xs[];
-  const int N0 = t.N0, lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int col = blockIdx.x * 4 + w;
-  if (col >= N0) return;
-  double* x = xs + (int64_t)w * N0;
+  const int N0 = t.N0, bw = t.bw, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  if (blockIdx.x * 4 >= N0) return;
   const double* A = t.LU;
+  const int col = blockIdx.x * 4 + w;
+  const bool act = col < N0;  // every wave stays for the workgroup barriers
+  double* x = xs + (int64_t)w * N0;
+  double* work = xs + 4 * (int64_t)N0;
+  // multipliers: Lb[k * 2bw + (i - k - 1)] = L[i][k], i in (k, pe(k))
+  const int lw = 2 * bw;
+  if (kStageL) {
+    bulk_load(
+        (int64_t)N0 * lw,
+        [&](int64_t e) -> double {
+          const int k = (int)(e / lw), i = k + 1 + (int)(e % lw);
+          return A[(i < N0 ? i : N0 - 1) + (int64_t)N0 * k];
+        },
+        [&](int64_t e, double v) {
+          const int k = (int)(e / lw), i = k + 1 + (int)(e % lw);
+          work[e] = (i < min(N0, (k / bw + 2) * bw)) ? v : 0.0;
+        });
+  }
   for (int i = lane; i < N0; i += 64) x[i] = (i == col) ? 1.0 : 0.0;
-  __builtin_amdgcn_wave_barrier();
-  if (lane == 0)
-    for (int k = 0; k < N0; ++k) {
-      const int p = t.piv[k];
-      if (p != k) {
-        const double v = x[k];
-        x[k] = x[p];
-        x[p] = v;
+  __syncthreads();
+  if (act)
+    for (int k = 0; k < N0 - 1; ++k) {
+      const int pr = t.piv[k];
+      const double xk = x[pr];
+      const double xkk = x[k];
+      lds_order();
+      if (lane == 0 && pr != k) {
+        x[pr] = xkk;
+        x[k] = xk;
       }
+      lds_order();
+      if (xk != 0.0 && lane < lw - 1) {
+        const int i = k + 1 + lane;
+        if (i < min(N0, (k / bw + 2) * bw)) x[i] -= (kStageL ? work[(int64_t)k * lw + lane] : A[i + (int64_t)N0 * k]) * xk;
+      }
+      lds_order();
     }
-  __builtin_amdgcn_wave_barrier();
-  for (int k = 0; k < N0 - 1; ++k) {
-    const double xk = x[k];
-    if (xk != 0.0)
-      for (int i = k + 1 + lane; i < N0; i += 64) x[i] -= A[i + (int64_t)N0 * k] * xk;
-    __builtin_amdgcn_wave_barrier();
+  // back substitution: columns [klo, khi] of U (rows 0..khi) staged per block
+  const int room = kSaiLdsDoubles - 4 * N0;
+  const int CB = max(1, min(64, room / N0));
+  for (int khi = N0 - 1; khi >= 0; khi -= CB) {
+    const int klo = max(0, khi - CB + 1), nr = khi + 1;
+    __syncthreads();
+    bulk_load(
+        (int64_t)(khi - klo + 1) * nr, [&](int64_t e) -> double { return A[(e % nr) + (int64_t)N0 * (klo + e / nr)]; },
+        [&](int64_t e, double v) { work[e] = v; });
+    __syncthreads();
+    if (act)
+      for (int k = khi; k >= klo; --k) {
+        const double* uc = work + (int64_t)(k - klo) * nr;
+        const double xk = x[k] / uc[k];
+        lds_order();
+        if (lane == 0) x[k] = xk;
+        if (xk != 0.0)
+          for (int i = lane; i < k; i += 64) x[i] -= uc[i] * xk;
+        lds_order();
+      }
   }
-  for (int k = N0 - 1; k >= 0; --k) {
-    const double xk = x[k] / A[k + (int64_t)N0 * k];
-    __builtin_amdgcn_wave_barrier();
-    if (lane == 0) x[k] = xk;
-    if (xk != 0.0)
-      for (int i = lane; i < k; i += 64) x[i] -= A[i + (int64_t)N0 * k] * xk;
-    __builtin_amdgcn_wave_barrier();
-  }
-  for (int i = lane; i < N0; i += 64) t.Kinv[i + (int64_t)N0 * col] = x[i];
+  __syncthreads();
+  if (act)
+    for (int i = lane; i < N0; i += 64) t.Kinv[i + (int64_t)N0 * col] = x[i];
 }
 
 // ---- launchers ----------------------------------------------------------------------------
 void launch_tri_factor(TriDev* td, int nprob, int maxC, hipStream_t st) {
   hipLaunchKernelGGL(k_tri_factor, dim3((unsigned)((maxC + 255) / 256), (unsigned)nprob), dim3(256), 0, st, td);
-  hipLaunchKernelGGL(k_tri_reduce_factor, dim3((unsigned)nprob), dim3(64), 0, st, td);
+  hipLaunchKernelGGL(k_tri_reduce_factor, dim3((unsigned)nprob), dim3(256), 0, st, td);
 }
 
-void launch_sai_solve(ProbDev* d, TriDev* td, int nprob, int maxCbw, int64_t maxnbw, int j, int mixed,
+// groups: workgroups per problem (the most that any problem's chunks need,
+// sai_solve_groups)
+void launch_sai_solve(ProbDev* d, TriDev* td, int nprob, int groups, int64_t maxnbw, int j, int mixed,
                       hipStream_t st) {
-  const dim3 gs((unsigned)((maxCbw + 255) / 256), (unsigned)nprob);
+  static bool attr = false;
+  if (!attr) {
+    const void* fns[2] = {(const void*)k_sai_solve<double>, (const void*)k_sai_solve<float>};
+    for (const void* f : fns)
+      if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, kSaiLdsDoubles * 8) != hipSuccess)
+        (void)hipGetLastError();
+    attr = true;
+  }
+  const dim3 ge((unsigned)((maxnbw + 255) / 256), (unsigned)nprob);
   if (mixed)
-    hipLaunchKernelGGL(k_sai_solve<float>, gs, dim3(256), 0, st, d, td, j);
+    hipLaunchKernelGGL(k_sai_commit<float>, ge, dim3(256), 0, st, d, j);
   else
-    hipLaunchKernelGGL(k_sai_solve<double>, gs, dim3(256), 0, st, d, td, j);
-  hipLaunchKernelGGL(k_sai_recon, dim3((unsigned)((maxnbw + 255) / 256), (unsigned)nprob), dim3(256), 0, st, td);
+    hipLaunchKernelGGL(k_sai_commit<double>, ge, dim3(256), 0, st, d, j);
+  const dim3 gs((unsigned)groups, (unsigned)nprob);
+  const size_t lds = sizeof(double) * kSaiLdsDoubles;
+  if (mixed)
+    hipLaunchKernelGGL(k_sai_solve<float>, gs, dim3(256), lds, st, d, td, j);
+  else
+    hipLaunchKernelGGL(k_sai_solve<double>, gs, dim3(256), lds, st, d, td, j);
+  hipLaunchKernelGGL(k_sai_recon, ge, dim3(256), 0, st, td);
+}
+
+int sai_solve_groups(int C, int R, int bw) {
+  const int cpw = sai_chunks_per_group(R, bw);
+  return (C + cpw - 1) / cpw;
 }
 
 void launch_sai_gram(ProbDev* d, TriDev* td, int nprob, int64_t maxn, double* part, hipStream_t st) {
@@ -498,17 +795,32 @@ void launch_sai_gram(ProbDev* d, TriDev* td, int nprob, int64_t maxn, double* pa
                      dim3(kGramRows), 0, st, d, td, part);
 }
 
-void launch_hess_inverse(TriDev* td, int nprob, int maxN0, hipStream_t st) {
-  hipLaunchKernelGGL(k_hess_lu, dim3((unsigned)nprob), dim3(256), 0, st, td);
-  const size_t lds = sizeof(double) * 4 * (size_t)maxN0;
+void launch_hess_inverse(TriDev* td, int nprob, int maxN0, int maxbw, hipStream_t st) {
   static bool attr = false;
   if (!attr) {
-    if (hipFuncSetAttribute((const void*)k_hess_inv, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024) !=
-        hipSuccess)
-      (void)hipGetLastError();
+    const void* fns[3] = {(const void*)k_hess_lu<true>, (const void*)k_hess_inv<true>,
+                          (const void*)k_hess_inv<false>};
+    for (const void* f : fns)
+      if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024) != hipSuccess)
+        (void)hipGetLastError();
     attr = true;
   }
-  hipLaunchKernelGGL(k_hess_inv, dim3((unsigned)((maxN0 + 3) / 4), (unsigned)nprob), dim3(256), lds, st, td);
+  // the band of 2 bw rows in LDS when it fits for every problem of the batch
+  const size_t band = sizeof(double) * 2 * (size_t)maxbw * maxN0;
+  if (band <= (size_t)kSaiLdsDoubles * sizeof(double))
+    hipLaunchKernelGGL(k_hess_lu<true>, dim3((unsigned)nprob), dim3(256), band, st, td);
+  else
+    hipLaunchKernelGGL(k_hess_lu<false>, dim3((unsigned)nprob), dim3(256), 0, st, td);
+  // four columns in LDS plus a work region (the staged multipliers, N0 x 2 bw, when they
+  // fit -- else read in place -- then blocks of U's columns)
+  const size_t ldsfull = sizeof(double) * kSaiLdsDoubles;
+  const bool stage = (size_t)4 * maxN0 + (size_t)2 * maxbw * maxN0 <= (size_t)kSaiLdsDoubles;
+  if (stage)
+    hipLaunchKernelGGL(k_hess_inv<true>, dim3((unsigned)((maxN0 + 3) / 4), (unsigned)nprob), dim3(256), ldsfull, st,
+                       td);
+  else
+    hipLaunchKernelGGL(k_hess_inv<false>, dim3((unsigned)((maxN0 + 3) / 4), (unsigned)nprob), dim3(256), ldsfull, st,
+                       td);
 }
 
 }  // namespace pe

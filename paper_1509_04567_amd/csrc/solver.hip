@@ -136,13 +136,21 @@ constexpr int kRowsU = 64;
 // shift-and-invert: gamma = kSaiShift times the step a restart cycle aims at, unless the
 // problem sets its own factor
 constexpr double kSaiShift = 0.1;
-// rows per chunk of the partitioned tridiagonal solve: 32, or more on long grids so that
-// the interface system (two unknowns per chunk, solved by one thread per column) stays
-// at most 1024 chunks long
-int sai_rows_per_chunk(int64_t n) {
-  int64_t r = 32;
-  while (n / r > 1024) r *= 2;
-  return (int)r;
+// largest projected dimension l bw of a shift-and-invert cycle (the inverse of the
+// projected matrix keeps four of its columns and one of U's in LDS)
+constexpr int kSaiMaxN0 = 4000;
+// chunks of the partitioned tridiagonal solve: a power of two (the interface system is
+// solved by cyclic reduction), at most 256 and with at least 16 rows each; the rows per
+// chunk follow (the last chunk takes the remainder)
+void sai_chunking(int64_t n, int& R, int& C) {
+  C = 1;
+  while (2 * C <= 256 && 2 * (int64_t)C * 16 <= n) C *= 2;
+  R = (int)(n / C);
+}
+int sai_red_doubles(int C) {
+  int lev = 0;
+  while ((1 << lev) < C) ++lev;
+  return 8 * C * lev + 4 * C + 4;
 }
 
 // bound on the re-expansion growth of the Chebyshev source basis over one step
@@ -680,21 +688,20 @@ pe_status march_batch(pe_ctx* ctx, const pe_problem* probs, const int* idx, int 
     int R, C;
   };
   std::vector<SaiOff> so(sai ? nb_prob : 0);
-  int maxC = 1, maxbwall = 1;
+  int maxC = 1, maxbwall = 1, sai_groups = 1;
   if (sai)
     for (int ii = 0; ii < nb_prob; ++ii) {
       const pe_problem& p = probs[idx[ii]];
       const int64_t n = p.op.n;
       const int bwmax = ml[ii] + 1;
       SaiOff& o = so[ii];
-      o.R = sai_rows_per_chunk(n);
-      o.C = (int)std::max<int64_t>(1, n / o.R);
+      sai_chunking(n, o.R, o.C);
       o.ta = cv.take<double>(n);
       o.tinv = cv.take<double>(n);
       o.tc = cv.take<double>(n);
       o.vL = cv.take<double>(n);
       o.vR = cv.take<double>(n);
-      o.red = cv.take<double>(14 * (size_t)o.C + 4);
+      o.red = cv.take<double>(sai_red_doubles(o.C));
       o.rrhs = cv.take<double>(2 * (size_t)o.C * bwmax);
       o.ru = cv.take<double>(2 * (size_t)o.C * bwmax);
       o.W = cv.take<double>((size_t)n * bwmax);
@@ -703,6 +710,7 @@ pe_status march_batch(pe_ctx* ctx, const pe_problem* probs, const int* idx, int 
       o.cnt = cv.take<unsigned>(2);
       maxC = std::max(maxC, o.C);
       maxbwall = std::max(maxbwall, bwmax);
+      for (int bw = 1; bw <= bwmax; ++bw) sai_groups = std::max(sai_groups, pe::sai_solve_groups(o.C, o.R, bw));
     }
   const size_t o_td = cv.take<TriDev>(sai ? nb_prob : 1);
   int64_t maxn_all = 1;
@@ -907,6 +915,8 @@ pe_status march_batch(pe_ctx* ctx, const pe_problem* probs, const int* idx, int 
         const ProbDev& d = hd[ii];
         t.active = d.active;
         if (!d.active) continue;
+        if (d.l * d.bw > kSaiMaxN0)
+          return pe_fail(ctx, PE_ERR_UNSUPPORTED, "shift-and-invert: krylov_steps x block width above 4000");
         t.gamma = (p.sai_shift > 0.0 ? p.sai_shift : kSaiShift) * hs[ii].dtry;
         t.bw = d.bw;
         t.N0 = d.l * d.bw;
@@ -948,7 +958,7 @@ pe_status march_batch(pe_ctx* ctx, const pe_problem* probs, const int* idx, int 
           cost.flops += c.flops;
         }
       if (sai) {
-        pe::launch_sai_solve(dd, tdd, nb_prob, maxC * maxbwall, maxn_all * maxbwall, j, mixed, st);
+        pe::launch_sai_solve(dd, tdd, nb_prob, sai_groups, maxn_all * maxbwall, j, mixed, st);
         run_block_step(ctx, dd, nb_prob, gx_p * groups, smem_p, gx_u, smem_u, j, j + 1, pe::MODE_SAI, mixed, cost,
                        st);
       } else {
@@ -958,7 +968,7 @@ pe_status march_batch(pe_ctx* ctx, const pe_problem* probs, const int* idx, int 
     }
     if (sai) {  // residual Gram of the last block, then K^{-1} for the projected operator
       pe::launch_sai_gram(dd, tdd, nb_prob, maxn_all, (double*)(base + o_gpart), st);
-      pe::launch_hess_inverse(tdd, nb_prob, maxN0, st);
+      pe::launch_hess_inverse(tdd, nb_prob, maxN0, maxbwall, st);
     }
     // ---- S6: projected exponential with step-size trials
     for (int ii = 0; ii < nb_prob; ++ii) he[ii].active = hd[ii].active;
