@@ -645,6 +645,12 @@ struct HostState {
   int level = 0;
   double rho = 1.0;
   double pexp = 0.0;  // local order of the error estimate in the step (0: unknown)
+  // dense output: after a step lands on an output time, the next output is tried from
+  // the same Krylov space (offsets measured from the cycle start tau_c); a new space is
+  // built only when that space cannot reach further than the state already has
+  double tau_c = 0.0;
+  bool reuse = false;      // the next plan tries the current space first
+  bool reuse_now = false;  // this pass evaluates the current space (no new Arnoldi)
 };
 
 pe_status march_batch(pe_ctx* ctx, const pe_problem* probs, const int* idx, int nb_prob, const double* const* Ul,
@@ -843,7 +849,7 @@ pe_status march_batch(pe_ctx* ctx, const pe_problem* probs, const int* idx, int 
   const int max_cycles = env_int("PARAEXP_MAX_CYCLES", 0);
   while (true) {
     // ---- plan the cycle
-    int nact = 0, lmax = 0, gx_p = 0, gx_u = 0, mb_N = 1;
+    int nact = 0, nreuse = 0, lmax = 0, gx_p = 0, gx_u = 0, mb_N = 1;
     size_t smem_p = 0, smem_u = 0;
     int64_t maxNN = 1;
     for (int ii = 0; ii < nb_prob; ++ii) {
@@ -853,6 +859,7 @@ pe_status march_batch(pe_ctx* ctx, const pe_problem* probs, const int* idx, int 
       d.active = 0;
       d.proj = 0;
       he[ii].active = 0;
+      h.reuse_now = false;
       if (h.done) continue;
       const int m = ml[ii];
       h.src = (m > 0) && (h.tau < p.t1);
@@ -862,16 +869,27 @@ pe_status march_batch(pe_ctx* ctx, const pe_problem* probs, const int* idx, int 
         continue;
       }
       h.target = h.src ? std::min(p.t_out[h.k], p.t1) : p.t_out[h.k];
-      const double rem = h.target - h.tau;
-      h.dtry = std::min(rem, h.dgrow * h.dlast);
-      if (h.src && ql[ii] > 0) {
-        // The exponential of the Chebyshev generator over a step re-expands the basis at
-        // a shift of c = 2 step / (t1 - t0) in x, with coefficients growing like
-        // (1 + sqrt(2c))^q; rounding in the projected exponential grows with them.  Steps
-        // are capped so that the growth stays below kGrowthCap.
-        const double g = std::pow(kGrowthCap, 1.0 / ql[ii]) - 1.0;
-        h.dtry = std::min(h.dtry, 0.25 * g * g * (p.t1 - p.t0));
+      // The exponential of the Chebyshev generator over a step re-expands the basis at a
+      // shift of c = 2 step / (t1 - t0) in x, with coefficients growing like
+      // (1 + sqrt(2c))^q; rounding in the projected exponential grows with them.  Steps
+      // (offsets from the cycle start) are capped so that the growth stays below kGrowthCap.
+      const double cap = (h.src && ql[ii] > 0)
+                             ? 0.25 * std::pow(std::pow(kGrowthCap, 1.0 / ql[ii]) - 1.0, 2) * (p.t1 - p.t0)
+                             : HUGE_VAL;
+      if (h.reuse) {
+        const double off = std::min(h.target - h.tau_c, cap);
+        if (off > h.tau - h.tau_c) {  // the same space, evaluated further out
+          h.dtry = off;
+          h.reuse_now = true;
+          ++nreuse;
+          mb_N = std::max(mb_N, h.N);
+          maxNN = std::max<int64_t>(maxNN, (int64_t)h.N * h.N);
+          continue;
+        }
+        h.reuse = false;
       }
+      h.tau_c = h.tau;
+      h.dtry = std::min(std::min(h.target - h.tau, h.dgrow * h.dlast), cap);
       h.bw = h.src ? (h.xzero ? m : m + 1) : 1;
       d.m = h.src ? m : 0;
       d.with_x = h.xzero ? 0 : 1;
@@ -905,10 +923,10 @@ pe_status march_batch(pe_ctx* ctx, const pe_problem* probs, const int* idx, int 
         HCK(hipMemcpyAsync((void*)e.w, wv[ii].data(), sizeof(double) * ql[ii], hipMemcpyHostToDevice, st));
       }
     }
-    if (nact == 0) break;
+    if (nact == 0 && nreuse == 0) break;
     // shift-and-invert: gamma from the step each cycle aims at; factor I - gamma L
     int maxN0 = 1;
-    if (sai) {
+    if (sai && nact > 0) {
       for (int ii = 0; ii < nb_prob; ++ii) {
         const pe_problem& p = probs[idx[ii]];
         TriDev& t = ht[ii];
@@ -930,7 +948,7 @@ pe_status march_batch(pe_ctx* ctx, const pe_problem* probs, const int* idx, int 
     // event markers cost GPU time, so a march times every kProfEvery-th restart cycle
     // (all of its block steps, so the sample spans the same step mix)
     ctx->prof_sample = (guard % kProfEvery) == 0;
-    if (++guard > (max_cycles > 0 ? max_cycles : kCycleCap)) {
+    if (nact > 0 && ++guard > (max_cycles > 0 ? max_cycles : kCycleCap)) {
       // out of cycles (a tolerance below the attainable accuracy crawls at the minimum
       // step): flag, and mark the outputs not reached with NaN
       for (int ii = 0; ii < nb_prob; ++ii) {
@@ -944,50 +962,56 @@ pe_status march_batch(pe_ctx* ctx, const pe_problem* probs, const int* idx, int 
       }
       break;
     }
-    HCK(hipMemcpyAsync(dd, hd.data(), sizeof(ProbDev) * nb_prob, hipMemcpyHostToDevice, st));
-    // ---- S5: initial block and block Arnoldi
-    pe::launch_block_update(dd, nb_prob, gx_u, smem_u, 0, 0, 1, pe::MODE_INIT, mixed, st);
-    for (int j = 0; j < lmax; ++j) {
-      const int groups = (j + 1 + pe::kSlotGroup - 1) / pe::kSlotGroup;
-      StepCost cost;
-      for (int ii = 0; ii < nb_prob; ++ii)
-        if (hd[ii].active && j < hd[ii].l) {
-          const StepCost c = step_cost(hd[ii].n, hd[ii].bw, j + 1, mixed ? 4 : 8);
-          cost.proj_bytes += c.proj_bytes;
-          cost.upd_bytes += c.upd_bytes;
-          cost.flops += c.flops;
+    // ---- S5: initial block and block Arnoldi (problems that start a new space)
+    if (nact > 0) {
+      HCK(hipMemcpyAsync(dd, hd.data(), sizeof(ProbDev) * nb_prob, hipMemcpyHostToDevice, st));
+      pe::launch_block_update(dd, nb_prob, gx_u, smem_u, 0, 0, 1, pe::MODE_INIT, mixed, st);
+      for (int j = 0; j < lmax; ++j) {
+        const int groups = (j + 1 + pe::kSlotGroup - 1) / pe::kSlotGroup;
+        StepCost cost;
+        for (int ii = 0; ii < nb_prob; ++ii)
+          if (hd[ii].active && j < hd[ii].l) {
+            const StepCost c = step_cost(hd[ii].n, hd[ii].bw, j + 1, mixed ? 4 : 8);
+            cost.proj_bytes += c.proj_bytes;
+            cost.upd_bytes += c.upd_bytes;
+            cost.flops += c.flops;
+          }
+        if (sai) {
+          pe::launch_sai_solve(dd, tdd, nb_prob, sai_groups, maxn_all * maxbwall, j, mixed, st);
+          run_block_step(ctx, dd, nb_prob, gx_p * groups, smem_p, gx_u, smem_u, j, j + 1, pe::MODE_SAI, mixed, cost,
+                         st);
+        } else {
+          run_block_step(ctx, dd, nb_prob, gx_p * groups, smem_p, gx_u, smem_u, j, j + 1, pe::MODE_ARNOLDI, mixed, cost,
+                         st);
         }
-      if (sai) {
-        pe::launch_sai_solve(dd, tdd, nb_prob, sai_groups, maxn_all * maxbwall, j, mixed, st);
-        run_block_step(ctx, dd, nb_prob, gx_p * groups, smem_p, gx_u, smem_u, j, j + 1, pe::MODE_SAI, mixed, cost,
-                       st);
-      } else {
-        run_block_step(ctx, dd, nb_prob, gx_p * groups, smem_p, gx_u, smem_u, j, j + 1, pe::MODE_ARNOLDI, mixed, cost,
-                       st);
+      }
+      if (sai) {  // residual Gram of the last block, then K^{-1} for the projected operator
+        pe::launch_sai_gram(dd, tdd, nb_prob, maxn_all, (double*)(base + o_gpart), st);
+        pe::launch_hess_inverse(tdd, nb_prob, maxN0, maxbwall, st);
       }
     }
-    if (sai) {  // residual Gram of the last block, then K^{-1} for the projected operator
-      pe::launch_sai_gram(dd, tdd, nb_prob, maxn_all, (double*)(base + o_gpart), st);
-      pe::launch_hess_inverse(tdd, nb_prob, maxN0, maxbwall, st);
+    // ---- S6: projected exponential with step-size trials (a reused space keeps its
+    // projected matrix, start vector and norm)
+    if (nact > 0) {
+      for (int ii = 0; ii < nb_prob; ++ii) he[ii].active = hd[ii].active;
+      HCK(hipMemcpyAsync(ed, he.data(), sizeof(ExpmDev) * nb_prob, hipMemcpyHostToDevice, st));
+      pe::launch_build_aug(ed, nb_prob, maxNN, st);
+      HCK(hipMemsetAsync(base + o_nrm, 0, sizeof(double) * nb_prob, st));
+      pe::launch_norm1(ed, (double*)(base + o_nrm), nb_prob, mb_N, st);
+      HCK(hipMemcpyAsync(hp, base + o_nrm, sizeof(double) * nb_prob, hipMemcpyDeviceToHost, st));
+      HCK(hipStreamSynchronize(st));
     }
-    // ---- S6: projected exponential with step-size trials
-    for (int ii = 0; ii < nb_prob; ++ii) he[ii].active = hd[ii].active;
-    HCK(hipMemcpyAsync(ed, he.data(), sizeof(ExpmDev) * nb_prob, hipMemcpyHostToDevice, st));
-    pe::launch_build_aug(ed, nb_prob, maxNN, st);
-    HCK(hipMemsetAsync(base + o_nrm, 0, sizeof(double) * nb_prob, st));
-    pe::launch_norm1(ed, (double*)(base + o_nrm), nb_prob, mb_N, st);
-    HCK(hipMemcpyAsync(hp, base + o_nrm, sizeof(double) * nb_prob, hipMemcpyDeviceToHost, st));
-    HCK(hipStreamSynchronize(st));
     for (int ii = 0; ii < nb_prob; ++ii) {
-      hs[ii].nrm = hp[ii];
-      hs[ii].pending = hd[ii].active != 0;
-      hs[ii].accepted = false;
-      hs[ii].stop = false;
+      HostState& h = hs[ii];
+      if (hd[ii].active) h.nrm = hp[ii];
+      h.pending = hd[ii].active != 0 || h.reuse_now;
+      h.accepted = false;
+      h.stop = false;
       // a non-finite projected matrix: no step can be taken
-      if (hs[ii].pending && !std::isfinite(hp[ii])) {
-        hs[ii].pending = false;
-        hs[ii].stop = true;
-        hs[ii].flags |= PE_FLAG_NOT_CONVERGED;
+      if (hd[ii].active && !std::isfinite(hp[ii])) {
+        h.pending = false;
+        h.stop = true;
+        h.flags |= PE_FLAG_NOT_CONVERGED;
       }
     }
     const int tiles = (mb_N + 31) / 32;
@@ -1052,6 +1076,10 @@ pe_status march_batch(pe_ctx* ctx, const pe_problem* probs, const int* idx, int 
         in.krylov_steps = p.krylov_steps;
         in.pexp = h.pexp;
         const pe::StepOut o = pe::step_decide(in);
+        if (h.reuse_now && o.action != pe::kStepAccept) {
+          h.pending = false;  // the space does not reach the next output: build a new one
+          continue;
+        }
         h.flags |= o.flags;
         h.pexp = o.pexp;
         if (o.action == pe::kStepAccept) {
@@ -1061,7 +1089,7 @@ pe_status march_batch(pe_ctx* ctx, const pe_problem* probs, const int* idx, int 
           h.rho = o.rho;
           h.dtry = o.step;
           h.resid = std::max(h.resid, o.err * h.dtry);
-          if (o.level < ns) h.rejected += 1;
+          if (o.level < ns && !h.reuse_now) h.rejected += 1;
         } else if (o.action == pe::kStepReject) {
           ++h.rejected;
           h.dtry = o.step;
@@ -1079,8 +1107,8 @@ pe_status march_batch(pe_ctx* ctx, const pe_problem* probs, const int* idx, int 
       const pe_problem& p = probs[idx[ii]];
       d.proj = 0;
       d.outcol = nullptr;
-      if (!d.active) continue;
-      h.steps += d.l;
+      if (!d.active && !h.reuse_now) continue;
+      if (d.active) h.steps += d.l;
       if (h.stop) {
         // the march of this problem ends here: outputs not reached are NaN
         for (; h.k < p.n_out; ++h.k)
@@ -1088,12 +1116,14 @@ pe_status march_batch(pe_ctx* ctx, const pe_problem* probs, const int* idx, int 
         h.done = true;
         continue;
       }
+      const bool landed = h.dtry >= h.target - h.tau_c;
+      if (h.reuse_now && h.accepted && !landed && !(h.tau_c + h.dtry > h.tau)) h.accepted = false;
       if (!h.accepted) {
-        h.dlast = h.dtry;  // retry the cycle with the reduced step
+        if (h.reuse_now) h.reuse = false;  // new space from the current state next pass
+        else h.dlast = h.dtry;             // retry the cycle with the reduced step
         continue;
       }
-      const double rem = h.target - h.tau;
-      const bool landed = h.dtry >= rem;
+      d.active = 1;  // the projection reads the space of a reused cycle too
       d.proj = 1;
       d.yacc = he[ii].y + (size_t)h.level * h.N;
       if (landed && h.target == p.t_out[h.k]) d.outcol = p.out + (int64_t)h.k * p.ldOut;
@@ -1108,14 +1138,17 @@ pe_status march_batch(pe_ctx* ctx, const pe_problem* probs, const int* idx, int 
       ProbDev& d = hd[ii];
       const pe_problem& p = probs[idx[ii]];
       if (!d.active || !h.accepted) continue;
-      const double rem = h.target - h.tau;
-      const bool landed = h.dtry >= rem;
-      h.tau = landed ? h.target : h.tau + h.dtry;
-      // a step clipped at an output time does not limit the next one
+      const bool landed = h.dtry >= h.target - h.tau_c;
+      h.tau = landed ? h.target : h.tau_c + h.dtry;
+      // offsets reached from one space set the next space's first step; an offset
+      // clipped at an output time does not limit it
       if (!landed || h.dtry >= h.dlast) h.dlast = h.dtry;
       h.dgrow = pe::step_growth(h.rho, h.pexp, p.krylov_steps);
       h.xzero = false;
-      ++h.cycles;
+      if (!h.reuse_now) ++h.cycles;
+      // landed on an output inside the source interval (or past it): try the next output
+      // from the same space
+      h.reuse = d.outcol != nullptr && !(h.src && h.target >= p.t1);
       if (d.outcol) {
         const double tk = p.t_out[h.k];
         ++h.k;
