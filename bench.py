@@ -1,11 +1,14 @@
 """Benchmark of the Paraexp exp-action path on one MI355X.
 
 One step = one complete solve of the 8192-point advection-diffusion workload on [0, 1]
-(shifted samples, truncated SVD, Chebyshev fit, restarted block Arnoldi with the
-projected exponential, outputs at 32 times), inputs already resident in device memory.
-By default the interval is split into 4 Paraexp windows (Sec. 2.2): the window
-subproblems, 64 samples each, run as one batch and u = u0 + sum_j v_j is superposed;
---windows 1 solves it as one window with 256 samples.
+(shifted samples, truncated SVD, Chebyshev fit, restarted block Krylov exp-action with
+60 block steps per restart and the projected exponential, outputs at 32 times), inputs
+already resident in device memory.  The Krylov space is by default the shift-and-invert
+one (Sec. 2.1, the remark on rational Krylov acceleration); --krylov poly uses the
+polynomial block Krylov space of eq. 2.4.  --windows P splits the interval into P
+Paraexp windows (Sec. 2.2) solved as one batch and superposed (u = u0 + sum_j v_j).
+Beside the timed configuration the same inputs are solved at the other precision, as
+P = 4 windows and with the polynomial Krylov space, in the same process.
 Prints one JSON line.  Only one GPU is used: --gpus above 1 exits with a message.
 """
 import argparse
@@ -19,12 +22,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 
-def measured_traffic(kernel, windows):
+def measured_traffic(kernel, windows, krylov):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary of
-    the same window split (FETCH_SIZE + WRITE_SIZE, scaled by a device copy of known
-    size), or None when the summary is missing or was taken on a different kernel source."""
+    the same window split and Krylov space (FETCH_SIZE + WRITE_SIZE, scaled by a device
+    copy of known size), or None when the summary is missing or was taken on a different
+    kernel source."""
     import hashlib
-    tag = f"_paraexp{windows}" if windows > 1 else ""
+    tag = (f"_paraexp{windows}" if windows > 1 else "") + ("_sai" if krylov == "sai" else "")
     path = os.path.join(ROOT, "profiles", f"pmc_{kernel}_c2_n8192{tag}.txt")
     src = os.path.join(ROOT, "paper_1509_04567_amd", "csrc", "kernels.hip")
     try:
@@ -44,15 +48,18 @@ def main():
     ap.add_argument("--n", type=int, default=8192)
     ap.add_argument("--batch", type=int, default=1,
                     help="independent windows solved together per step (seeds 2, 3, ...); 1 = the workload")
-    ap.add_argument("--windows", type=int, default=4,
+    ap.add_argument("--windows", type=int, default=1,
                     help="Paraexp windows per solve (Sec. 2.2): the window subproblems run as one batch "
                          "(s / P samples each) and u = u0 + sum_j v_j is superposed; 1 = one window")
+    ap.add_argument("--krylov", choices=["sai", "poly"], default="sai",
+                    help="Krylov space: shift-and-invert (rational) or polynomial block Krylov")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-compare", action="store_true",
-                    help="skip the other precision and the single-window split (same inputs, same process)")
+                    help="skip the other precision, the other window split and the other Krylov space "
+                         "(same inputs, same process)")
     ap.add_argument("--roofline-kernel", default=None, choices=["block_update", "block_proj"],
                     help="kernel family of the roofline figure (default: the one with the most GPU time, "
-                         "block_update for one window, block_proj for the window split)")
+                         "block_update, or block_proj for the polynomial space split into windows)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="run one device copy of this many MiB first (reference for memory counters)")
     ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work for the baseline")
@@ -78,14 +85,16 @@ def main():
 
     P = max(1, args.windows)
     if args.roofline_kernel is None:
-        args.roofline_kernel = "block_proj" if P > 1 else "block_update"
+        args.roofline_kernel = "block_proj" if (P > 1 and args.krylov == "poly") else "block_update"
     ctx = pe.Context(0)
     refs = {}
 
-    def run(precision, windows, steps, warmup, profile):
-        """Time `steps` solves of the workload at one precision and window split; returns
-        the figures of that run (accuracy against the oracle checked outside the timing)."""
+    def run(precision, windows, steps, warmup, profile, krylov):
+        """Time `steps` solves of the workload at one precision, window split and Krylov
+        space; returns the figures of that run (accuracy against the oracle checked
+        outside the timing)."""
         prec = pe.PE_FP64 if precision == "fp64" else pe.PE_MIXED
+        kr = pe.PE_KRYLOV_SAI if krylov == "sai" else pe.PE_KRYLOV_POLY
         # the FP32-stored basis puts a floor of ~1e-9 under the residual estimate, so the
         # mixed path runs at tol 1e-8 (its accuracy target is 1e-7 against the FP64 oracle)
         tol = 1e-12 if precision == "fp64" else 1e-8
@@ -98,6 +107,8 @@ def main():
                 subs += synth.split_windows(pr, windows, g_at, s=max(2, pr.s // windows))
         else:
             subs = probs
+        for sp in subs:
+            sp.krylov = kr
         staged = ctx.prepare(subs, prec)
 
         def solve():
@@ -109,7 +120,7 @@ def main():
         for i in range(warmup):
             tw = time.perf_counter()
             solve()
-            print(f"[{precision} P={windows}] warmup {i}: {time.perf_counter() - tw:.3f} s", file=sys.stderr,
+            print(f"[{krylov} {precision} P={windows}] warmup {i}: {time.perf_counter() - tw:.3f} s", file=sys.stderr,
                   flush=True)
         torch.cuda.synchronize()
         if profile:  # per-launch HIP-event timing of the dominant kernel family, on the solve's stream
@@ -118,7 +129,7 @@ def main():
         for i in range(steps):
             ts = time.perf_counter()
             outs, reps = solve()
-            print(f"[{precision} P={windows}] step {i}: {time.perf_counter() - ts:.3f} s "
+            print(f"[{krylov} {precision} P={windows}] step {i}: {time.perf_counter() - ts:.3f} s "
                   f"cycles={reps[0]['cycles']} rejected={reps[0]['rejected']}", file=sys.stderr, flush=True)
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t0
@@ -139,7 +150,7 @@ def main():
         return {"solves_per_s": len(probs) * steps / elapsed, "ms_per_step": 1e3 * elapsed / max(steps, 1),
                 "rel_l2_vs_oracle": err, "report": reps[0], "prof": prof, "probs": probs}
 
-    main_run = run(args.precision, P, args.steps, args.warmup, True)
+    main_run = run(args.precision, P, args.steps, args.warmup, True, args.krylov)
     probs = main_run["probs"]
     prob = probs[0]
     prof = main_run["prof"]
@@ -148,7 +159,7 @@ def main():
     # the counter record of the single-window split covers three whole restart cycles,
     # whose launch mix is the solve's; with several windows the early cycles carry every
     # window at full width and later ones fewer, so that record is not the timed launches'
-    traffic = (measured_traffic(args.roofline_kernel, P)
+    traffic = (measured_traffic(args.roofline_kernel, P, args.krylov)
                if args.batch <= 1 and P == 1 and args.n == 8192 and args.precision == "fp64" else None)
     if launches > 0 and k_ms > 0:
         achieved = k_bytes / (k_ms * 1e-3) / 1e9
@@ -160,21 +171,26 @@ def main():
     rep = main_run["report"]
     err = main_run["rel_l2_vs_oracle"]
 
-    # the same inputs at the other precision and as a single window (same process)
+    # the same inputs at the other precision, the other window split and the other
+    # Krylov space (same process)
     compare = {}
     if not args.no_compare:
+        keys = ("solves_per_s", "ms_per_step", "rel_l2_vs_oracle", "report")
         other = "mixed" if args.precision == "fp64" else "fp64"
+        other_kr = "poly" if args.krylov == "sai" else "sai"
         cmp_steps = max(1, min(args.steps, 2))
-        o = run(other, P, cmp_steps, 1, False)
-        compare[f"{other}_paraexp{P}" if P > 1 else other] = {
-            k: o[k] for k in ("solves_per_s", "ms_per_step", "rel_l2_vs_oracle", "report")}
+        tag = lambda prec, w, kr: f"{kr}_{prec}" + (f"_paraexp{w}" if w > 1 else "")
+        o = run(other, P, cmp_steps, 1, False, args.krylov)
+        compare[tag(other, P, args.krylov)] = {k: o[k] for k in keys}
         fp64_sps = main_run["solves_per_s"] if args.precision == "fp64" else o["solves_per_s"]
         mixed_sps = o["solves_per_s"] if args.precision == "fp64" else main_run["solves_per_s"]
         compare["speedup_mixed_over_fp64"] = mixed_sps / fp64_sps
-        if P > 1:
-            w1 = run(args.precision, 1, cmp_steps, 1, False)
-            compare[f"{args.precision}_single_window"] = {
-                k: w1[k] for k in ("solves_per_s", "ms_per_step", "rel_l2_vs_oracle", "report")}
+        P2 = 4 if P == 1 else 1
+        w = run(args.precision, P2, cmp_steps, 1, False, args.krylov)
+        compare[tag(args.precision, P2, args.krylov)] = {k: w[k] for k in keys}
+        pk = run(args.precision, P, 1, 1, False, other_kr)
+        compare[tag(args.precision, P, other_kr)] = {k: pk[k] for k in keys}
+        compare[f"speedup_{args.krylov}_over_{other_kr}"] = main_run["solves_per_s"] / pk["solves_per_s"]
     t_oracle = refs[(args.n, 2)][1]
 
     cpu = None
@@ -209,10 +225,12 @@ def main():
         "dtype": "f64" if args.precision == "fp64" else "f64+f32basis",
         "data": "synthetic",
         "config": {"workload": f"c2_advection_diffusion_n{args.n}_krylov60_s256_nout32"
+                               + ("_shift_invert" if args.krylov == "sai" else "_polynomial")
                                + (f"_paraexp{P}" if P > 1 else "")
                                + (f"_batch{len(probs)}" if len(probs) > 1 else ""), "n": args.n, "batch": len(probs),
                    "windows": P,
                    "krylov_steps": prob.krylov_steps, "samples": prob.s, "n_out": len(prob.t_out),
+                   "krylov": "shift_invert" if args.krylov == "sai" else "polynomial",
                    "precision": args.precision},
         "rel_l2_vs_oracle": err,
         "report": rep,

@@ -140,6 +140,12 @@ struct ExpmDev {
   double gamma;
   const double* Kinv;      // lbw x lbw (ld lbw)
   const double* GW;        // bw x bw
+  // dense output by propagation: Eprop = exp(delta Ht) for an output spacing delta and
+  // ycur the projected solution at the last output; a pass with prop = 1 forms
+  // y_0 = Eprop ycur (level 0, no squarings) instead of evaluating a trial
+  int32_t prop;
+  double* Eprop;           // N x N column-major
+  double* ycur;            // N
 };
 
 // Host-visible helpers ---------------------------------------------------------

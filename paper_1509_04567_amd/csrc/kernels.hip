@@ -1012,7 +1012,7 @@ __device__ __constant__ double c_taylor[17] = {
 // A = alpha Ht (op 0) or P = c16 A4 + c15 A3 + c14 A2 + c13 A + c12 I (op 1)
 __global__ void k_elementwise(const ExpmDev* __restrict__ E, int op) {
   const ExpmDev e = E[blockIdx.y];  // by value: uniform, loaded once
-  if (!e.active) return;
+  if (!e.active || e.prop) return;
   const int N = e.N;
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (int64_t)N * N) return;
@@ -1040,7 +1040,7 @@ void launch_elementwise(ExpmDev* e, int op, int nprob, int64_t maxNN, hipStream_
 constexpr int kGemmK = 64;  // K extent of one staged tile pair
 __global__ __launch_bounds__(256) void k_gemm(const ExpmDev* __restrict__ E, int op, int k) {
   const ExpmDev e = E[blockIdx.y];  // by value: uniform, loaded once
-  if (!e.active) return;
+  if (!e.active || e.prop) return;
   if (op == 6 && k >= e.nsq) return;
   const int N = e.N;
   const int nt = (N + 31) / 32;
@@ -1131,7 +1131,8 @@ void launch_gemm(ExpmDev* e, int op, int k, int nprob, int tiles_max, hipStream_
 }
 
 // y_k = exp(alpha 2^k Ht) b after k squarings (T for even k, P for odd k); rows spread
-// over workgroups.  Problems with fewer squarings than k skip.
+// over workgroups.  Problems with fewer squarings than k skip.  A propagation pass
+// (prop = 1) forms y_0 = Eprop ycur.
 // A workgroup takes 64 rows; its 16 column groups (of 64 lanes each, one row per lane)
 // sum strided columns with eight loads in flight and reduce through LDS.
 constexpr int kApplySplit = 16;
@@ -1144,7 +1145,8 @@ __global__ __launch_bounds__(1024) void k_expm_apply(const ExpmDev* __restrict__
   if (r0 >= N) return;
   const int r = r0 + lane;
   __shared__ double red[kApplySplit * 64];
-  const double* M = (level & 1) ? e.P : e.T;
+  const double* M = e.prop ? e.Eprop : (level & 1) ? e.P : e.T;
+  const double* bvec = e.prop ? e.ycur : e.b;
   double acc = 0.0;
   if (r < N)
     for (int c = cs; c < N; c += 8 * kApplySplit) {
@@ -1153,7 +1155,7 @@ __global__ __launch_bounds__(1024) void k_expm_apply(const ExpmDev* __restrict__
       for (int k = 0; k < 8; ++k) {
         const int c2 = c + k * kApplySplit;
         const int cc = c2 < N ? c2 : N - 1;
-        const double mv = M[(int64_t)r + (int64_t)N * cc], bv = e.b[cc];
+        const double mv = M[(int64_t)r + (int64_t)N * cc], bv = bvec[cc];
         v[k] = c2 < N ? mv : 0.0;
         bb[k] = c2 < N ? bv : 0.0;
       }
@@ -1287,6 +1289,19 @@ __global__ void k_row_norms(const double* R, int64_t ldR, int rows, int cols, do
 
 void launch_row_norms(const double* R, int64_t ldR, int rows, int cols, double* rn, hipStream_t st) {
   hipLaunchKernelGGL(k_row_norms, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, st, R, ldR, rows, cols, rn);
+}
+
+// out = |x|_2 of a vector of n entries, one workgroup (fixed summation order)
+__global__ __launch_bounds__(1024) void k_vec_norm(const double* __restrict__ x, int64_t n, double* out) {
+  __shared__ double red[16];
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) s += x[i] * x[i];
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) *out = sqrt(s);
+}
+
+void launch_vec_norm(const double* x, int64_t n, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_vec_norm, dim3(1), dim3(1024), 0, st, x, n, out);
 }
 
 // One-sided (Hestenes) Jacobi on A = R[sel, 0:s]^T (s x r): A J has orthogonal columns.

@@ -155,6 +155,10 @@ int sai_red_doubles(int C) {
 
 // bound on the re-expansion growth of the Chebyshev source basis over one step
 constexpr double kGrowthCap = 100.0;
+// An output spacing that matches the held propagator's step to this relative accuracy is
+// reached with it: the time offset, at most kPropRel delta, moves the result by about
+// kPropRel delta |u'|, far below any tolerance the march accepts.
+constexpr double kPropRel = 1e-13;
 // restart cycles of a march between two timed ones (pe_profile_enable)
 constexpr int kProfEvery = 8;
 // restart cycles per march before it gives up (flagged, unreached outputs NaN)
@@ -651,6 +655,10 @@ struct HostState {
   double tau_c = 0.0;
   bool reuse = false;      // the next plan tries the current space first
   bool reuse_now = false;  // this pass evaluates the current space (no new Arnoldi)
+  // outputs at a repeated spacing prop_dt (> 0 when Eprop = exp(prop_dt Ht) of the
+  // current space is held) are reached by one matrix-vector product from the last one
+  double prop_dt = 0.0;
+  bool prop_now = false;
 };
 
 pe_status march_batch(pe_ctx* ctx, const pe_problem* probs, const int* idx, int nb_prob, const double* const* Ul,
@@ -680,7 +688,7 @@ pe_status march_batch(pe_ctx* ctx, const pe_problem* probs, const int* idx, int 
     bo[ii] = carve_block(cv, caps[ii], mixed);
     o_x[ii] = cv.take<double>(p.op.n);
     Nmax[ii] = l * bwmax + ql[ii];
-    o_e[ii] = cv.take<double>(7 * (size_t)Nmax[ii] * Nmax[ii] + (PE_MAX_LEVELS + 2) * (size_t)Nmax[ii] +
+    o_e[ii] = cv.take<double>(8 * (size_t)Nmax[ii] * Nmax[ii] + (PE_MAX_LEVELS + 3) * (size_t)Nmax[ii] +
                               2 * (PE_MAX_LEVELS + 1));
     o_w[ii] = cv.take<double>(std::max(1, ql[ii]));
     maxn = std::max<int64_t>(maxn, p.op.n);
@@ -748,7 +756,7 @@ pe_status march_batch(pe_ctx* ctx, const pe_problem* probs, const int* idx, int 
     double* tmp = (double*)(base + o_nrm);
     for (int ii = 0; ii < nb_prob; ++ii) {
       const pe_problem& p = probs[idx[ii]];
-      pe::launch_row_norms(p.u0, 1, 1, (int)p.op.n, tmp + ii, st);
+      pe::launch_vec_norm(p.u0, p.op.n, tmp + ii, st);
     }
     HCK(hipMemcpyAsync(hp, tmp, sizeof(double) * nb_prob, hipMemcpyDeviceToHost, st));
     HCK(hipStreamSynchronize(st));
@@ -800,6 +808,8 @@ pe_status march_batch(pe_ctx* ctx, const pe_problem* probs, const int* idx, int 
     e.b = eb + 7 * NN;
     e.y = e.b + Nmax[ii];
     e.out = e.y + (size_t)(PE_MAX_LEVELS + 1) * Nmax[ii];
+    e.ycur = e.out + 2 * (PE_MAX_LEVELS + 1);
+    e.Eprop = e.ycur + Nmax[ii];
     e.H = d.H;
     e.R0 = d.Rf + 0;  // set per cycle (depends on bw)
     e.Pi = Pil[ii];
@@ -860,6 +870,8 @@ pe_status march_batch(pe_ctx* ctx, const pe_problem* probs, const int* idx, int 
       d.proj = 0;
       he[ii].active = 0;
       h.reuse_now = false;
+      h.prop_now = false;
+      he[ii].prop = 0;
       if (h.done) continue;
       const int m = ml[ii];
       h.src = (m > 0) && (h.tau < p.t1);
@@ -881,6 +893,8 @@ pe_status march_batch(pe_ctx* ctx, const pe_problem* probs, const int* idx, int 
         if (off > h.tau - h.tau_c) {  // the same space, evaluated further out
           h.dtry = off;
           h.reuse_now = true;
+          h.prop_now = h.prop_dt > 0.0 && off == h.target - h.tau_c &&
+                       std::fabs((h.target - h.tau) - h.prop_dt) <= kPropRel * h.prop_dt;
           ++nreuse;
           mb_N = std::max(mb_N, h.N);
           maxNN = std::max<int64_t>(maxNN, (int64_t)h.N * h.N);
@@ -889,6 +903,7 @@ pe_status march_batch(pe_ctx* ctx, const pe_problem* probs, const int* idx, int 
         h.reuse = false;
       }
       h.tau_c = h.tau;
+      h.prop_dt = 0.0;
       h.dtry = std::min(std::min(h.target - h.tau, h.dgrow * h.dlast), cap);
       h.bw = h.src ? (h.xzero ? m : m + 1) : 1;
       d.m = h.src ? m : 0;
@@ -1019,13 +1034,20 @@ pe_status march_batch(pe_ctx* ctx, const pe_problem* probs, const int* idx, int 
     // exponential is exp(alpha 2^k Ht) with alpha = dtry / 2^nsq, so the largest level
     // whose error estimate passes gives the accepted step without recomputation.
     for (int trial = 0; trial < kMaxTrials; ++trial) {
-      int maxsq = 0, npend = 0;
+      int maxsq = 0, npend = 0, nfull = 0;
       for (int ii = 0; ii < nb_prob; ++ii) {
         ExpmDev& e = he[ii];
         HostState& h = hs[ii];
         e.active = h.pending ? 1 : 0;
+        e.prop = h.pending && h.prop_now ? 1 : 0;
         if (!h.pending) continue;
         ++npend;
+        if (e.prop) {  // one product with the held propagator, evaluated as level 0
+          e.nsq = 0;
+          e.alpha = h.dtry;
+          continue;
+        }
+        ++nfull;
         const double nn = h.dtry * h.nrm;
         int s = 0;
         if (nn > kTaylorTheta) s = (int)std::ceil(std::log2(nn / kTaylorTheta));
@@ -1036,14 +1058,16 @@ pe_status march_batch(pe_ctx* ctx, const pe_problem* probs, const int* idx, int 
       }
       if (npend == 0) break;
       HCK(hipMemcpyAsync(ed, he.data(), sizeof(ExpmDev) * nb_prob, hipMemcpyHostToDevice, st));
-      pe::launch_elementwise(ed, 0, nb_prob, maxNN, st);
-      pe::launch_gemm(ed, 0, 0, nb_prob, tiles * tiles, st);
-      pe::launch_gemm(ed, 1, 0, nb_prob, tiles * tiles, st);
-      pe::launch_gemm(ed, 2, 0, nb_prob, tiles * tiles, st);
-      pe::launch_elementwise(ed, 1, nb_prob, maxNN, st);
-      pe::launch_gemm(ed, 3, 0, nb_prob, tiles * tiles, st);
-      pe::launch_gemm(ed, 4, 0, nb_prob, tiles * tiles, st);
-      pe::launch_gemm(ed, 5, 0, nb_prob, tiles * tiles, st);
+      if (nfull > 0) {
+        pe::launch_elementwise(ed, 0, nb_prob, maxNN, st);
+        pe::launch_gemm(ed, 0, 0, nb_prob, tiles * tiles, st);
+        pe::launch_gemm(ed, 1, 0, nb_prob, tiles * tiles, st);
+        pe::launch_gemm(ed, 2, 0, nb_prob, tiles * tiles, st);
+        pe::launch_elementwise(ed, 1, nb_prob, maxNN, st);
+        pe::launch_gemm(ed, 3, 0, nb_prob, tiles * tiles, st);
+        pe::launch_gemm(ed, 4, 0, nb_prob, tiles * tiles, st);
+        pe::launch_gemm(ed, 5, 0, nb_prob, tiles * tiles, st);
+      }
       pe::launch_expm_apply(ed, 0, nb_prob, mb_N, st);
       for (int k = 0; k < maxsq; ++k) {
         pe::launch_gemm(ed, 6, k, nb_prob, tiles * tiles, st);
@@ -1158,6 +1182,23 @@ pe_status march_batch(pe_ctx* ctx, const pe_problem* probs, const int* idx, int 
         }
       }
       if (h.k >= p.n_out) h.done = true;
+      if (h.reuse && !h.done) {
+        // the next output of this space starts from the projected solution here; the
+        // exponential of this step serves as the propagator when the next spacing equals
+        // it (the matrix of level k is T for even k, P for odd k, and the last two levels
+        // of a trial are still held)
+        ExpmDev& e = he[ii];
+        HCK(hipMemcpyAsync(e.ycur, d.yacc, sizeof(double) * h.N, hipMemcpyDeviceToDevice, st));
+        if (!h.prop_now) {
+          h.prop_dt = 0.0;
+          const double next = (h.src ? std::min(p.t_out[h.k], p.t1) : p.t_out[h.k]) - h.tau;
+          if (h.level >= e.nsq - 1 && std::fabs(next - h.dtry) <= kPropRel * h.dtry) {
+            HCK(hipMemcpyAsync(e.Eprop, (h.level & 1) ? e.P : e.T, sizeof(double) * h.N * h.N,
+                               hipMemcpyDeviceToDevice, st));
+            h.prop_dt = h.dtry;
+          }
+        }
+      }
     }
     // host descriptors are rewritten next cycle: drain the queued uploads first
     HCK(hipStreamSynchronize(st));
