@@ -160,7 +160,7 @@ constexpr double kGrowthCap = 100.0;
 // kPropRel delta |u'|, far below any tolerance the march accepts.
 constexpr double kPropRel = 1e-13;
 // restart cycles of a march between two timed ones (pe_profile_enable)
-constexpr int kProfEvery = 8;
+constexpr int kProfEvery = 1;
 // restart cycles per march before it gives up (flagged, unreached outputs NaN)
 constexpr int kCycleCap = 100000;
 
@@ -960,8 +960,8 @@ pe_status march_batch(pe_ctx* ctx, const pe_problem* probs, const int* idx, int 
       HCK(hipMemcpyAsync(tdd, ht.data(), sizeof(TriDev) * nb_prob, hipMemcpyHostToDevice, st));
       pe::launch_tri_factor(tdd, nb_prob, maxC, st);
     }
-    // event markers cost GPU time, so a march times every kProfEvery-th restart cycle
-    // (all of its block steps, so the sample spans the same step mix)
+    // a march times every kProfEvery-th restart cycle (all of its block steps, so the
+    // sample spans the same step mix)
     ctx->prof_sample = (guard % kProfEvery) == 0;
     if (nact > 0 && ++guard > (max_cycles > 0 ? max_cycles : kCycleCap)) {
       // out of cycles (a tolerance below the attainable accuracy crawls at the minimum
