@@ -58,6 +58,7 @@ struct ProbDev {
   int32_t rows_u_log2;     // rows_u is a power of two
   int32_t Cu;              // number of update chunks
   int32_t comb_global;     // 1: the TSQR combine works on the stacked factors in global memory
+  int32_t comb_tree;       // 1: two-level register combine (blocks of 17..32 columns)
   double dep_tol;          // a column whose remainder after projection is <= dep_tol times its
                            // norm before projection is deflated (dependent)
   int32_t rows_p;          // rows per projection chunk

@@ -18,12 +18,14 @@ constexpr int kUpdateLdsMax = 150 * 1024;
 constexpr int kSlotGroup = 4;
 // LDS doubles for the projection coefficients staged by the update kernel
 constexpr int kSb = 4096;
+// chunks per group of the two-level TSQR combine
+constexpr int kTreeFan = 8;
 
 // The TSQR combine of Cu stacked bw x bw factors runs register-resident (four waves)
 // when it fits; otherwise from LDS.
 __host__ __device__ inline bool combine_in_registers(int bw, int Cu) {
   const int rpl = (Cu * bw + 255) / 256;
-  return (bw <= 8 && rpl <= 4) || (bw <= 16 && rpl <= 2);
+  return (bw <= 8 && rpl <= 4) || (bw <= 16 && rpl <= 1);
 }
 
 // Y[:, c] = L X[:, c]
@@ -38,8 +40,9 @@ void launch_add_column(int64_t n, int s, const double* G, int64_t ldG, const dou
 void init_block_kernels();
 void launch_block_proj(ProbDev* d, int nprob, int grid_x, size_t smem, int j, int nb, int pass, int mode,
                        int mixed, hipStream_t st);
+// tree: some problem of the batch uses the two-level combine (k_tree_assemble follows)
 void launch_block_update(ProbDev* d, int nprob, int grid_x, size_t smem, int j, int nb, int pass, int mode,
-                         int mixed, hipStream_t st);
+                         int mixed, int tree, hipStream_t st);
 void launch_block_commit(ProbDev* d, int nprob, int grid_x, int j, int mixed, hipStream_t st);
 
 // exponential of the projected augmented matrix
@@ -70,7 +73,7 @@ void launch_tri_factor(TriDev* td, int nprob, int maxC, hipStream_t st);
 void launch_sai_solve(ProbDev* d, TriDev* td, int nprob, int groups, int64_t maxnbw, int j, int mixed,
                       hipStream_t st);
 void launch_sai_gram(ProbDev* d, TriDev* td, int nprob, int64_t maxn, double* part, hipStream_t st);
-void launch_hess_inverse(TriDev* td, int nprob, int maxN0, int maxbw, hipStream_t st);
+void launch_hess_inverse(TriDev* td, int nprob, int maxN0, int maxbw, int maxl, hipStream_t st);
 
 // x = V y (+ output column)
 void launch_project(ProbDev* d, ExpmDev* e, int nprob, int64_t maxn, int max_lbw, int mixed, hipStream_t st);

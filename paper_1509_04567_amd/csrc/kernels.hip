@@ -60,68 +60,79 @@ __device__ void mgs2_qr_block(double* X, int rows, int ld, int bw, double* R, do
 // Classical Gram-Schmidt applied twice, column by column, by a team of NW waves (NW = 1:
 // one wave, no barriers; NW > 1: the whole workgroup, barriers inside) on a rows x bw
 // array X with leading dimension ld, in LDS or global memory (thread t owns rows t,
-// t + 64 NW, ..., so no row is touched by two threads).  All dot products of a column
-// with the previous columns are reduced together: three team reductions per column.
-// A column whose remainder is <= dep_tol times its reference norm ref[b] is
-// dependent: it becomes a zero column with a zero row in R (deflation), so it adds no
-// direction and later columns do not couple to it.  R (bw x bw, row-major, pre-zeroed)
-// receives the triangular factor.  `red`: LDS scratch of 32 NW doubles (NW > 1).
+// t + 64 NW, ..., so no row is touched by two threads).  The dot products of a column
+// with the previous columns are reduced eight at a time within each wave (independent
+// reductions overlap); one wave keeps dot a in lane a, a team exchanges the per-wave sums
+// through the LDS scratch `red` (32 NW doubles) with one barrier pair per pass.  No
+// per-thread array is indexed at run time.  A column whose remainder is <= dep_tol times
+// its reference norm ref[b] is dependent: it becomes a zero column with a zero row in R
+// (deflation), so it adds no direction and later columns do not couple to it.  R (bw x
+// bw, row-major, pre-zeroed) receives the triangular factor.
+__device__ __forceinline__ double lane_value(double v, int src) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), src);
+  return __hiloint2double(hi, lo);
+}
 template <int NW>
 __device__ __forceinline__ void cgs2_qr_team(double* X, int rows, int ld, int bw, double* R, const double* ref,
                                              double dep_tol, double* red) {
   const int t = (NW == 1) ? (int)(threadIdx.x & 63) : (int)threadIdx.x;
-  const int w = t >> 6;
+  const int w = t >> 6, lane = t & 63;
   constexpr int T = 64 * NW;
-  auto team_sums = [&](double* sd, int na) {
-#pragma unroll
-    for (int a = 0; a < 32; ++a)
-      if (a < na) sd[a] = wave_sum(sd[a]);
-    if (NW > 1) {
-      __syncthreads();
-      if ((t & 63) == 0)
-#pragma unroll
-        for (int a = 0; a < 32; ++a)
-          if (a < na) red[w * 32 + a] = sd[a];
-      __syncthreads();
-#pragma unroll
-      for (int a = 0; a < 32; ++a)
-        if (a < na) {
-          double v = 0.0;
-          for (int ww = 0; ww < NW; ++ww) v += red[ww * 32 + a];
-          sd[a] = v;
-        }
-    }
+  double mydot = 0.0;  // NW == 1: lane a holds the dot product with column a
+  auto team = [&](int a) -> double {
+    if (NW == 1) return lane_value(mydot, a);
+    double v = 0.0;
+    for (int ww = 0; ww < NW; ++ww) v += red[ww * 32 + a];
+    return v;
   };
   for (int b = 0; b < bw; ++b) {
     for (int pass = 0; pass < 2; ++pass) {
-      double sd[32];
+      for (int a0 = 0; a0 < b; a0 += 8) {
+        double sd[8];
 #pragma unroll
-      for (int a = 0; a < 32; ++a) sd[a] = 0.0;
-      for (int r = t; r < rows; r += T) {
-        const double xb = X[(int64_t)r * ld + b];
+        for (int k = 0; k < 8; ++k) sd[k] = 0.0;
+        for (int r = t; r < rows; r += T) {
+          const double xb = X[(int64_t)r * ld + b];
 #pragma unroll
-        for (int a = 0; a < 32; ++a)
-          if (a < b) sd[a] += X[(int64_t)r * ld + a] * xb;
+          for (int k = 0; k < 8; ++k)
+            if (a0 + k < b) sd[k] += X[(int64_t)r * ld + a0 + k] * xb;
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) sd[k] = wave_sum(sd[k]);
+        if (NW == 1) {
+#pragma unroll
+          for (int k = 0; k < 8; ++k)
+            if (lane == a0 + k) mydot = sd[k];
+        } else if (lane == 0) {
+#pragma unroll
+          for (int k = 0; k < 8; ++k)
+            if (a0 + k < b) red[w * 32 + a0 + k] = sd[k];
+        }
       }
-      team_sums(sd, b);
+      if (NW > 1) __syncthreads();
       for (int r = t; r < rows; r += T) {
         double acc = X[(int64_t)r * ld + b];
-#pragma unroll
-        for (int a = 0; a < 32; ++a)
-          if (a < b) acc -= sd[a] * X[(int64_t)r * ld + a];
+        for (int a = 0; a < b; ++a) acc -= team(a) * X[(int64_t)r * ld + a];
         X[(int64_t)r * ld + b] = acc;
       }
-      if (t == 0) {
-#pragma unroll
-        for (int a = 0; a < 32; ++a)
-          if (a < b) R[a * bw + b] += sd[a];
+      for (int a = 0; a < b; ++a) {
+        const double v = team(a);
+        if (t == 0) R[a * bw + b] += v;
       }
+      if (NW > 1) __syncthreads();
     }
-    double s1[32];
-    s1[0] = 0.0;
-    for (int r = t; r < rows; r += T) s1[0] += X[(int64_t)r * ld + b] * X[(int64_t)r * ld + b];
-    team_sums(s1, 1);
-    const double nr = sqrt(s1[0]);
+    double s1 = 0.0;
+    for (int r = t; r < rows; r += T) s1 += X[(int64_t)r * ld + b] * X[(int64_t)r * ld + b];
+    s1 = wave_sum(s1);
+    double nsq = s1;
+    if (NW > 1) {
+      if (lane == 0) red[w * 32] = s1;
+      __syncthreads();
+      nsq = team(0);
+      __syncthreads();
+    }
+    const double nr = sqrt(nsq);
     const bool dep = !(nr > dep_tol * ref[b] && nr > 1e-300);
     const double inv = dep ? 0.0 : 1.0 / nr;
     for (int r = t; r < rows; r += T) X[(int64_t)r * ld + b] *= inv;
@@ -259,10 +270,10 @@ __device__ __forceinline__ bool cgs2_dispatch(const double* Xi, int ldi, double*
     if (rpl <= 4) { cgs2_team<8, 4, NW>(Xi, ldi, X, ld, rows, bw, R, ref, dep_tol, red); return true; }
   } else if (bw <= 16) {
     if (rpl <= 1) { cgs2_team<16, 1, NW>(Xi, ldi, X, ld, rows, bw, R, ref, dep_tol, red); return true; }
-    if (rpl <= 2) { cgs2_team<16, 2, NW>(Xi, ldi, X, ld, rows, bw, R, ref, dep_tol, red); return true; }
   }
   return false;  // wider blocks or more rows: cgs2_qr_team on an LDS or global array
 }
+
 
 // ------------------------------------------------------------------------------------
 // S0: Y = L X, column-major blocks
@@ -716,13 +727,17 @@ __global__ __launch_bounds__(256) void k_block_update(const ProbDev* __restrict_
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const bool reg_comb = combine_in_registers(bw, p.Cu);
   extern __shared__ double smem[];
-  const int64_t xs_cap = (int64_t)ld * (reg_comb || p.comb_global || rmax > p.Cu * bw ? rmax : p.Cu * bw);
+  const int64_t xs_cap =
+      p.comb_tree ? (int64_t)ld * max(rmax, max(kTreeFan, (p.Cu + kTreeFan - 1) / kTreeFan) * bw)
+                  : (int64_t)ld * (reg_comb || p.comb_global || rmax > p.Cu * bw ? rmax : p.Cu * bw);
   double* X = smem;                               // xs_cap
-  double* Sb = X + xs_cap;                        // kSb
-  double* Rl = Sb + kSb;                          // bw^2
+  // the input rows staged for form_block are dead once the block is formed: the
+  // projection coefficients of the subtraction reuse that space
+  double* Qrow = X + xs_cap;                      // (rmax + 2) * bw
+  double* Sb = Qrow;                              // kSb
+  double* Rl = Qrow + max((int64_t)kSb, (int64_t)(rmax + 2) * bw);  // bw^2
   double* Rn = Rl + nout;                         // bw
-  double* Qrow = Rn + bw;                         // (rmax + 2) * bw
-  double* Qsl = Qrow + (int64_t)(rmax + 2) * bw;  // max(bw^2, 128)
+  double* Qsl = Rn + bw;                          // max(bw^2, 128)
   __shared__ int is_last;
   const TS* V = basis_ptr<TS>(p);
   const int64_t blk = n * bw;
@@ -780,7 +795,7 @@ __global__ __launch_bounds__(256) void k_block_update(const ProbDev* __restrict_
   __syncthreads();
   if (w == 0) {
     if (!cgs2_dispatch<1>(X, ld, Qloc, bw, rows, bw, Rl, Rn, p.dep_tol, nullptr)) {
-      cgs2_qr_team<1>(X, rows, ld, bw, Rl, Rn, p.dep_tol, nullptr);
+      cgs2_qr_team<1>(X, rows, ld, bw, Rl, Rn, p.dep_tol, Qsl);
       if (lane == 0) reg_qr = 0;
     }
   }
@@ -791,10 +806,44 @@ __global__ __launch_bounds__(256) void k_block_update(const ProbDev* __restrict_
       for (int rr = t / bw; rr < rows; rr += rstep) Qloc[rr * bw + col] = X[rr * ld + col];
   }
   for (int o = t; o < nout; o += 256) st_agent(p.Rloc + (int64_t)u * nout + o, Rl[o]);
-  // 4. TSQR combine by the last workgroup
-  if (!arrive_last(p.cnt + 2 * p.nbmax, (unsigned)p.Cu, &is_last)) return;
   double* Qs = pass == 0 ? p.Qs1 : p.Qs2;
-  const int srows = p.Cu * bw;
+  int ngroups = 0;
+  if (p.comb_tree) {
+    // 4a. two-level combine (stacks too tall for one workgroup's LDS): the last workgroup
+    // of each group of kTreeFan chunks factors the group's stacked factors (one wave, from
+    // LDS; dependence judged against the group's column norms), writes the group's Q
+    // blocks to Qs and its R factor over the first chunk's slot of Rloc
+    ngroups = (p.Cu + kTreeFan - 1) / kTreeFan;
+    const int g = u / kTreeFan, ua = g * kTreeFan, ub = min(p.Cu, ua + kTreeFan);
+    if (!arrive_last(p.cnt + 2 * p.nbmax + 2 + g, (unsigned)(ub - ua), &is_last)) return;
+    const int rg = (ub - ua) * bw;
+    bulk_load(
+        (int64_t)rg * bw, [&](int64_t e) -> double { return p.Rloc[(int64_t)ua * nout + e]; },
+        [&](int64_t e, double v) { X[(e / bw) * ld + (e % bw)] = v; });
+    for (int o = t; o < nout; o += 256) Rl[o] = 0.0;
+    {
+      const int per = 256 / bw, b = t % bw, k = t / bw;
+      double acc = 0.0;
+      if (k < per)
+        for (int uu = ua + k; uu < ub; uu += per) acc += p.Cn[(int64_t)uu * bw + b];
+      Sb[t] = acc;
+    }
+    __syncthreads();
+    for (int b = t; b < bw; b += 256) {
+      double s0 = 0.0;
+      for (int k = 0; k < 256 / bw; ++k) s0 += Sb[k * bw + b];
+      Rn[b] = sqrt(s0);
+    }
+    __syncthreads();
+    if (w == 0) cgs2_qr_team<1>(X, rg, ld, bw, Rl, Rn, p.dep_tol, Qsl);
+    __syncthreads();
+    for (int e = t; e < rg * bw; e += 256) st_agent(Qs + (int64_t)ua * nout + e, X[(e / bw) * ld + (e % bw)]);
+    for (int o = t; o < nout; o += 256) st_agent(p.Rloc + (int64_t)ua * nout + o, Rl[o]);
+    if (t == 0) atomicExch(p.cnt + 2 * p.nbmax + 2 + g, 0u);
+  }
+  // 4. TSQR combine by the last workgroup (of all chunks, or of all groups)
+  if (!arrive_last(p.cnt + 2 * p.nbmax, (unsigned)(p.comb_tree ? ngroups : p.Cu), &is_last)) return;
+  const int srows = (p.comb_tree ? ngroups : p.Cu) * bw;
   for (int o = t; o < nout; o += 256) Rl[o] = 0.0;
   {
     // global reference norms: 256 / bw threads per column, eight loads in flight each
@@ -821,7 +870,27 @@ __global__ __launch_bounds__(256) void k_block_update(const ProbDev* __restrict_
     Rn[b] = sqrt(s0);
   }
   __syncthreads();
-  if (reg_comb) {
+  if (p.comb_tree) {
+    // 4b. the group factors (each in its group's first chunk slot of Rloc) stacked and
+    // factored by one wave
+    bulk_load(
+        (int64_t)srows * bw,
+        [&](int64_t e) -> double {
+          const int gg = (int)(e / nout);
+          return p.Rloc[(int64_t)gg * kTreeFan * nout + (e - (int64_t)gg * nout)];
+        },
+        [&](int64_t e, double v) { X[(e / bw) * ld + (e % bw)] = v; });
+    __syncthreads();
+    if (w == 0) cgs2_qr_team<1>(X, srows, ld, bw, Rl, Rn, p.dep_tol, Qsl);
+    __syncthreads();
+    // the group blocks of the second-level Q replace the group factors in Rloc;
+    // k_tree_assemble multiplies them into the chunks' Q blocks
+    for (int e = t; e < srows * bw; e += 256) {
+      const int gg = e / nout, o = e - gg * nout;
+      p.Rloc[(int64_t)gg * kTreeFan * nout + o] = X[(int64_t)(gg * bw + o / bw) * ld + (o % bw)];
+    }
+    __syncthreads();
+  } else if (reg_comb) {
     // stacked chunk factors read straight from global memory into registers
     cgs2_dispatch<4>(p.Rloc, bw, Qs, bw, srows, bw, Rl, Rn, p.dep_tol, Qsl);
     __syncthreads();
@@ -852,7 +921,7 @@ __global__ __launch_bounds__(256) void k_block_update(const ProbDev* __restrict_
     __shared__ int skip;
     if (w == 0) {
       bool ok = true;  // lane b: column b of Q1 orthogonal enough
-      if (lane < bw) ok = reorth_column_ok(Rl, Rn, bw, lane, kReorthSkip);
+      if (lane < bw) ok = reorth_column_ok(Rl, Rn, bw, lane, kReorthSkip, Sb + lane * 32);
       const bool all_ok = __all(ok);
       if (lane == 0) {
         skip = all_ok ? 1 : 0;
@@ -920,8 +989,33 @@ void launch_block_proj(ProbDev* d, int nprob, int grid_x, size_t smem, int j, in
     hipLaunchKernelGGL(k_block_proj<double>, grid, dim3(256), smem, st, d, j, nb, pass, mode);
 }
 
+// Two-level combine, last step: the Q block of chunk u becomes its group-level block
+// times its group's block of the second-level Q (left in the group's first Rloc slot).
+__global__ __launch_bounds__(256) void k_tree_assemble(const ProbDev* __restrict__ probs, int j, int pass, int mode) {
+  const ProbDev p = probs[blockIdx.y];  // by value: uniform, loaded once
+  if (!p.active || !p.comb_tree || (mode != MODE_INIT && j >= p.l)) return;
+  if (arnoldi_mode(mode) && pass == 1 && p.cnt[2 * p.nbmax + 1]) return;  // second pass skipped
+  const int u = blockIdx.x;
+  if (u >= p.Cu) return;
+  const int bw = p.bw, nout = bw * bw;
+  double* Qs = (pass == 0 ? p.Qs1 : p.Qs2) + (int64_t)u * nout;
+  const double* Q2 = p.Rloc + (int64_t)(u / kTreeFan) * kTreeFan * nout;
+  __shared__ double qa[1024], qb[1024];
+  for (int e = threadIdx.x; e < nout; e += 256) {
+    qa[e] = Qs[e];
+    qb[e] = Q2[e];
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < nout; e += 256) {
+    const int r = e / bw, c = e - r * bw;
+    double acc = 0.0;
+    for (int k = 0; k < bw; ++k) acc += qa[r * bw + k] * qb[k * bw + c];
+    Qs[e] = acc;
+  }
+}
+
 void launch_block_update(ProbDev* d, int nprob, int grid_x, size_t smem, int j, int nb, int pass, int mode,
-                         int mixed, hipStream_t st) {
+                         int mixed, int tree, hipStream_t st) {
   if (grid_x <= 0 || nprob <= 0) return;
   init_block_kernels();
   dim3 grid((unsigned)grid_x, (unsigned)nprob);
@@ -929,6 +1023,7 @@ void launch_block_update(ProbDev* d, int nprob, int grid_x, size_t smem, int j, 
     hipLaunchKernelGGL(k_block_update<float>, grid, dim3(256), smem, st, d, j, nb, pass, mode);
   else
     hipLaunchKernelGGL(k_block_update<double>, grid, dim3(256), smem, st, d, j, nb, pass, mode);
+  if (tree) hipLaunchKernelGGL(k_tree_assemble, grid, dim3(256), 0, st, d, j, pass, mode);
 }
 
 void launch_block_commit(ProbDev* d, int nprob, int grid_x, int j, int mixed, hipStream_t st) {
@@ -1188,24 +1283,32 @@ __global__ __launch_bounds__(256) void k_expm_resid(const ExpmDev* __restrict__ 
   double rr = 0.0;
   const int bw = e.bw, l = e.l;
   if (e.sai) {
-    const int lbw = e.lbw, N = e.N;
-    for (int a = 0; a < bw; ++a) {
+    // z = E_l^T (I - gamma H_L) y (one wave per row), c = K_{l+1,l} z, |r|^2 = c^T GW c
+    const int lbw = e.lbw, N = e.N, lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    __shared__ double cvs[32];
+    for (int a = w; a < bw; a += 4) {
       double sa = 0.0;
-      for (int c = threadIdx.x; c < lbw; c += blockDim.x) sa += e.Ht[(int64_t)(lbw - bw + a) + (int64_t)N * c] * y[c];
-      sa = block_sum(sa, red);
-      if (threadIdx.x == 0) zs[a] = y[lbw - bw + a] - e.gamma * sa;
+      for (int c = lane; c < lbw; c += 64) sa += e.Ht[(int64_t)(lbw - bw + a) + (int64_t)N * c] * y[c];
+      sa = wave_sum(sa);
+      if (lane == 0) zs[a] = y[lbw - bw + a] - e.gamma * sa;
     }
     __syncthreads();
+    if ((int)threadIdx.x < bw) {
+      const int a = threadIdx.x;
+      double acc = 0.0;
+      for (int b = 0; b < bw; ++b) acc += e.H[(int64_t)(l * bw + a) + e.ldH * (int64_t)((l - 1) * bw + b)] * zs[b];
+      cvs[a] = acc;
+    }
+    __syncthreads();
+    double q = 0.0;
+    if ((int)threadIdx.x < bw) {
+      const int a = threadIdx.x;
+      double acc = 0.0;
+      for (int b = 0; b < bw; ++b) acc += e.GW[a * bw + b] * cvs[b];
+      q = cvs[a] * acc;
+    }
+    q = block_sum(q, red);
     if (threadIdx.x == 0) {
-      double cv[32];
-      for (int a = 0; a < bw; ++a) {
-        double acc = 0.0;
-        for (int b = 0; b < bw; ++b) acc += e.H[(int64_t)(l * bw + a) + e.ldH * (int64_t)((l - 1) * bw + b)] * zs[b];
-        cv[a] = acc;
-      }
-      double q = 0.0;
-      for (int a = 0; a < bw; ++a)
-        for (int b = 0; b < bw; ++b) q += cv[a] * e.GW[a * bw + b] * cv[b];
       e.out[2 * level] = sqrt(fmax(q, 0.0)) / e.gamma;
       e.out[2 * level + 1] = sqrt(yn);
     }

@@ -18,12 +18,13 @@ namespace pe {
 // where the sum runs over the columns the QR kept (a deflated column is a zero column of
 // Q1 with a zero row and diagonal in R1).  Column b is orthogonal enough without a second
 // pass when rho_b <= 1 / kappa: its loss of orthogonality is then at most c eps / kappa.
-// R1 is bw x bw upper triangular, row-major; Rn[a] = |w_a|.
-__host__ __device__ inline bool reorth_column_ok(const double* R, const double* Rn, int bw, int b, double kappa) {
+// R1 is bw x bw upper triangular, row-major; Rn[a] = |w_a|.  z: caller storage of bw
+// doubles (device code passes LDS, so no per-thread array is indexed at run time).
+__host__ __device__ inline bool reorth_column_ok(const double* R, const double* Rn, int bw, int b, double kappa,
+                                                 double* z) {
   const double rbb = R[b * bw + b];
   if (rbb == 0.0) return true;  // deflated: contributes no direction
   // z = R1^{-1} e_b on the kept columns, by back substitution from row b upwards
-  double z[32];
   double rho = Rn[b] * fabs(1.0 / rbb);
   z[b] = 1.0 / rbb;
   for (int a = b - 1; a >= 0; --a) {

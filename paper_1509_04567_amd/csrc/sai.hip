@@ -13,7 +13,8 @@
 //   k_sai_solve / k_sai_recon           W = T^{-1} V_j for the Arnoldi step j (V_j formed
 //                                        from its TSQR factors and committed to the basis)
 //   k_sai_gram                          Gram of (I - gamma L) V_l for the residual estimate
-//   k_hess_lu / k_hess_inv              K_l^{-1} by LU with row interchanges
+//   k_lu_panel / k_lu_trail / k_hess_inv   K_l^{-1} by LU with row interchanges
+#include <algorithm>
 #include <type_traits>
 
 #include "devutil.h"
@@ -469,208 +470,135 @@ __global__ __launch_bounds__(kGramRows) void k_sai_gram(const ProbDev* __restric
 
 // ---- inverse of the projected matrix --------------------------------------------------
 // K (N0 = l bw) is block upper Hessenberg with blocks of bw: column k has nonzeros down
-// to row pe(k) = min(N0, (k / bw + 2) bw) - 1 only.  LU with row interchanges, done one
-// block column (panel) at a time with the 2 bw band rows of the panel in LDS when they
-// fit (else in place in global memory):
-//   (a) one wave factors the panel: for each of its columns k the pivot is the largest
-//       entry of column k in rows [k, pe), rows k and pivot are exchanged in the panel
-//       columns >= k only (LINPACK storage: multipliers stay where they were computed),
-//       the multipliers are formed and the rest of the panel updated;
-//   (b) every thread takes trailing columns and applies the panel's interchanges and
-//       eliminations to them in order;
-//   (c) the finished rows (and the panel multipliers of the lower band rows) go back to
-//       global memory and the next block row of K comes in.
+// to row pe(k) = min(N0, (k / bw + 2) bw) - 1 only.  LU with row interchanges, one block
+// column (panel) at a time, K in place in global memory:
+//   (a) one wave factors the panel in LDS: for each of its columns k the pivot is the
+//       largest entry of column k in rows [k, pe) (NaN entries never chosen), rows k and
+//       pivot are exchanged in the panel columns >= k only (LINPACK storage: multipliers
+//       stay where they were computed), the multipliers are formed and the rest of the
+//       panel updated;
+//   (b) one wave per trailing column applies the panel's interchanges and eliminations
+//       to the column's 2 bw band entries (one per lane), in order.
 // A deflated basis column (a zero vector) leaves row and column k of K zero: it gets a
 // unit pivot (K^{-1} = 1 there, the projected operator 0).  A zero pivot column with a
 // nonzero row (a singular K) makes the result NaN, and the march stops on the non-finite
 // projected matrix.
-__device__ __forceinline__ bool khess_in_block(int r, int c, int bw) { return r / bw <= c / bw + 1; }
+__device__ __forceinline__ void lds_order() {
+  __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): this wave's LDS operations are done
+  __builtin_amdgcn_wave_barrier();
+}
 
-// the panel of a block column (rows [k0, pe), columns [k0, k1), BW >= k1 - k0): one
-// wave, lane q holds row k0 + q of the panel in registers; pivots by readlane
-template <int BW, typename At>
-__device__ __forceinline__ void lu_panel(At& at, int* pv, int* bad, int k0, int k1, int pe, int N0, int lane) {
-  const int nb = pe - k0, nc = k1 - k0;
-  double row[BW];
-#pragma unroll
-  for (int c = 0; c < BW; ++c) row[c] = (lane < nb && c < nc) ? at(k0 + lane, k0 + c) : 0.0;
-  auto bcast = [](double v, int src) {
-    const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
-    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), src);
-    return __hiloint2double(hi, lo);
-  };
-#pragma unroll
-  for (int kq = 0; kq < BW; ++kq) {
-    if (kq >= nc) break;
-    // pivot: the largest |entry| of column kq in rows kq..nb-1 (smallest row among equals)
-    double best = -1.0;
-    int bi = kq;
-    for (int q = kq; q < nb; ++q) {
-      const double v = fabs(bcast(row[kq], q));
-      if (v > best) {
-        best = v;
-        bi = q;
+// One launch pair per block column: the panel (one wave, in LDS) and the trailing update
+// (one wave per trailing column, the column's band rows one per lane), so the trailing
+// sweeps run over the whole chip.
+__global__ void k_lu_init(const TriDev* __restrict__ tds) {
+  const TriDev t = tds[blockIdx.y];
+  if (!t.active) return;
+  const int N0 = t.N0, bw = t.bw;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < (int64_t)N0 * N0;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int r = (int)(e % N0), c = (int)(e / N0);
+    t.LU[e] = c >= (r / bw - 1) * bw ? t.H[(int64_t)r + t.ldH * c] : 0.0;
+  }
+}
+
+__device__ __forceinline__ double lane_bcast(double v, int src) {
+  const int s = __builtin_amdgcn_readfirstlane(src);
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), s);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), s);
+  return __hiloint2double(hi, lo);
+}
+
+// panel jb: rows [k0, pe) (at most 2 bw <= 64), columns [k0, k1); lane q holds row k0 + q
+__global__ __launch_bounds__(64) void k_lu_panel(const TriDev* __restrict__ tds, int jb) {
+  const TriDev t = tds[blockIdx.x];
+  if (!t.active) return;
+  const int N0 = t.N0, bw = t.bw, lane = threadIdx.x;
+  if (jb >= N0 / bw) return;
+  constexpr int LD = 33;
+  __shared__ double P[64 * LD];
+  double* A = t.LU;
+  const int k0 = jb * bw, k1 = k0 + bw, pe = min(N0, k1 + bw), nb = pe - k0, nc = bw;
+  for (int c = 0; c < nc; ++c) P[lane * LD + c] = lane < nb ? A[(int64_t)(k0 + lane) + (int64_t)N0 * (k0 + c)] : 0.0;
+  lds_order();
+  int bad = 0;
+  for (int kq = 0; kq < nc; ++kq) {
+    // pivot: the largest |entry| of column kq in rows kq..nb-1, the smallest row among equals
+    double best = (lane >= kq && lane < nb) ? fabs(P[lane * LD + kq]) : -1.0;
+    if (!(best >= 0.0)) best = -1.0;
+    int bi = lane;
+    for (int off = 32; off >= 1; off >>= 1) {
+      const double ob = __shfl_xor(best, off);
+      const int oi = __shfl_xor(bi, off);
+      if (ob > best || (ob == best && oi < bi)) {
+        best = ob;
+        bi = oi;
       }
     }
     if (!(best > 0.0)) {
-      // zero column: a deflated basis direction when row kq is zero as well
+      // zero column: a deflated basis direction when row kq is zero as well (unit pivot)
       int nz = 0;
-#pragma unroll
-      for (int c = 0; c < BW; ++c)
-        if (c > kq && c < nc && lane == kq) nz |= (row[c] != 0.0);
-      for (int c = k1 + lane; c < N0; c += 64) nz |= (at(k0 + kq, c) != 0.0);
-      if (__any(nz) && lane == 0) *bad = 1;
-      if (lane == kq) row[kq] = 1.0;
-      if (lane == 0) pv[kq] = k0 + kq;
+      for (int c = kq + 1 + lane; c < nc; c += 64) nz |= (P[kq * LD + c] != 0.0);
+      for (int c = k1 + lane; c < N0; c += 64) nz |= (A[(int64_t)(k0 + kq) + (int64_t)N0 * c] != 0.0);
+      bad |= __any(nz);
+      lds_order();
+      if (lane == kq) P[kq * LD + kq] = 1.0;
+      if (lane == 0) t.piv[k0 + kq] = k0 + kq;
+      lds_order();
       continue;
     }
-    if (lane == 0) pv[kq] = k0 + bi;
-    if (bi != kq) {  // exchange rows kq and bi in panel columns >= kq
-#pragma unroll
-      for (int c = 0; c < BW; ++c) {
-        if (c < kq) continue;
-        const double vk = bcast(row[c], kq), vb = bcast(row[c], bi);
-        if (lane == kq) row[c] = vb;
-        if (lane == bi) row[c] = vk;
+    if (lane == 0) t.piv[k0 + kq] = k0 + bi;
+    if (bi != kq) {  // exchange rows kq and bi in columns >= kq (multipliers stay in place)
+      for (int c = kq + lane; c < nc; c += 64) {
+        const double a = P[kq * LD + c], b = P[bi * LD + c];
+        P[kq * LD + c] = b;
+        P[bi * LD + c] = a;
       }
+      lds_order();
     }
-    double prow[BW];  // the pivot row, read by every lane
-#pragma unroll
-    for (int c = 0; c < BW; ++c) prow[c] = c >= kq ? bcast(row[c], kq) : 0.0;
+    const double piv = P[kq * LD + kq];
     if (lane > kq && lane < nb) {
-      const double m = row[kq] / prow[kq];
-      row[kq] = m;
-#pragma unroll
-      for (int c = 0; c < BW; ++c)
-        if (c > kq) row[c] -= m * prow[c];
+      const double m = P[lane * LD + kq] / piv;
+      P[lane * LD + kq] = m;
+      for (int c = kq + 1; c < nc; ++c) P[lane * LD + c] -= m * P[kq * LD + c];
     }
+    lds_order();
   }
-#pragma unroll
-  for (int c = 0; c < BW; ++c)
-    if (lane < nb && c < nc) at(k0 + lane, k0 + c) = row[c];
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+  for (int c = 0; c < nc; ++c)
+    if (lane < nb) A[(int64_t)(k0 + lane) + (int64_t)N0 * (k0 + c)] = P[lane * LD + c];
+  // a zero pivot column with a nonzero row: K is singular (row 0 is final by now)
+  if (lane == 0 && bad) A[0] = __longlong_as_double(0x7ff8000000000000LL);
 }
 
-// the trailing columns of a panel (rows [k0, pe), B2 >= pe - k0 compile-time slots):
-// interchanges and eliminations in order, the column in registers
-template <int B2, typename At>
-__device__ __forceinline__ void lu_trailing(At& at, const int* pv, int k0, int k1, int pe, int N0, int tid) {
-  const int nb = pe - k0;
-  for (int c = k1 + tid; c < N0; c += 256) {
-    double xr[B2];
-#pragma unroll
-    for (int q = 0; q < B2; ++q) xr[q] = q < nb ? at(k0 + q, c) : 0.0;
-#pragma unroll
-    for (int kq = 0; kq < B2 / 2; ++kq) {
-      if (k0 + kq >= k1) break;
-      const int pq = pv[kq] - k0;  // pivot row, relative to k0
-      double xk = 0.0, xo = 0.0;
-#pragma unroll
-      for (int q = 0; q < B2; ++q) {
-        if (q == pq) xk = xr[q];
-        if (q == kq) xo = xr[q];
-      }
-#pragma unroll
-      for (int q = 0; q < B2; ++q) {
-        if (q == pq) xr[q] = xo;
-        if (q == kq) xr[q] = xk;
-      }
-      if (xk != 0.0) {
-#pragma unroll
-        for (int q = kq + 1; q < B2; ++q)
-          if (q < nb) xr[q] -= at(k0 + q, k0 + kq) * xk;
-      }
-    }
-#pragma unroll
-    for (int q = 0; q < B2; ++q)
-      if (q < nb) at(k0 + q, c) = xr[q];
-  }
-}
-
-template <bool kLds>
-__global__ __launch_bounds__(256) void k_hess_lu(const TriDev* __restrict__ tds) {
-  const TriDev t = tds[blockIdx.x];
+// trailing columns of panel jb: the interchanges and eliminations in order
+__global__ __launch_bounds__(256) void k_lu_trail(const TriDev* __restrict__ tds, int jb) {
+  const TriDev t = tds[blockIdx.y];
   if (!t.active) return;
-  extern __shared__ double band[];
+  const int N0 = t.N0, bw = t.bw;
+  if (jb >= N0 / bw) return;
+  const int k0 = jb * bw, k1 = k0 + bw, pe = min(N0, k1 + bw), nb = pe - k0;
+  __shared__ double mul[32 * 64];  // mul[kq * 64 + q] = L(k0 + q, k0 + kq)
   __shared__ int pv[32];
-  __shared__ int bad;
-  const int N0 = t.N0, bw = t.bw, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int l = N0 / bw;
-  double* A = t.LU;
-  // current panel: rows [k0, k0 + bw) sit in band slots hb0.., rows [k0 + bw, k0 + 2 bw)
-  // in slots hb1.. (the halves alternate from panel to panel)
-  int k0 = 0, hb0 = 0, hb1 = bw;
-  auto at = [&](int r, int c) -> double& {
-    if (kLds) {
-      const int rl = r - k0;
-      return band[(int64_t)(rl < bw ? hb0 + rl : hb1 + rl - bw) * N0 + c];
-    }
-    return A[(int64_t)r + (int64_t)N0 * c];
-  };
-  if (tid == 0) bad = 0;
-  if (kLds) {
-    // block rows 0 and 1 of K: every column may be nonzero
-    const int rows = min(N0, 2 * bw);
-    bulk_load(
-        (int64_t)rows * N0, [&](int64_t e) -> double { return t.H[(int64_t)(e % rows) + t.ldH * (e / rows)]; },
-        [&](int64_t e, double v) { band[(e % rows) * N0 + e / rows] = v; });
-  } else {
-    for (int64_t e = tid; e < (int64_t)N0 * N0; e += 256) {
-      const int r = (int)(e % N0), c = (int)(e / N0);
-      A[e] = c >= (r / bw - 1) * bw ? t.H[(int64_t)r + t.ldH * c] : 0.0;
-    }
+  const double* A = t.LU;
+  for (int e = threadIdx.x; e < nb * bw; e += 256) {
+    const int q = e % nb, kq = e / nb;
+    mul[kq * 64 + q] = A[(int64_t)(k0 + q) + (int64_t)N0 * (k0 + kq)];
   }
+  if (threadIdx.x < bw) pv[threadIdx.x] = t.piv[k0 + threadIdx.x] - k0;
   __syncthreads();
-  for (int jb = 0; jb < l; ++jb) {
-    k0 = jb * bw;
-    hb0 = (jb & 1) * bw;
-    hb1 = bw - hb0;
-    const int k1 = k0 + bw, pe = min(N0, k1 + bw);
-    // (a) panel
-    if (w == 0) {
-      if (bw <= 8)
-        lu_panel<8>(at, pv, &bad, k0, k1, pe, N0, lane);
-      else if (bw <= 16)
-        lu_panel<16>(at, pv, &bad, k0, k1, pe, N0, lane);
-      else
-        lu_panel<32>(at, pv, &bad, k0, k1, pe, N0, lane);
-    }
-    __syncthreads();
-    // (b) trailing columns: the panel's interchanges and eliminations, in order, on the
-    // column's 2 bw band entries held in registers
-    if (bw <= 8)
-      lu_trailing<16>(at, pv, k0, k1, pe, N0, tid);
-    else if (bw <= 16)
-      lu_trailing<32>(at, pv, k0, k1, pe, N0, tid);
-    else
-      lu_trailing<64>(at, pv, k0, k1, pe, N0, tid);
-    if (tid == 0)
-      for (int k = k0; k < k1; ++k) t.piv[k] = pv[k - k0];
-    __syncthreads();
-    if (kLds) {
-      // (c) finished rows k0..k1-1 (columns >= k0) and the panel multipliers of the rows
-      // below; then block row jb + 2 of K (nonzero from column block jb + 1 on) enters
-      // the freed slots
-      for (int e = tid; e < bw * (N0 - k0); e += 256) {
-        const int r = k0 + e % bw, c = k0 + e / bw;
-        A[(int64_t)r + (int64_t)N0 * c] = at(r, c);
-      }
-      const int nlow = pe - k1;
-      for (int e = tid; e < nlow * bw; e += 256) {
-        const int r = k1 + e % nlow, c = k0 + e / nlow;
-        A[(int64_t)r + (int64_t)N0 * c] = at(r, c);
-      }
-      __syncthreads();
-      const int nr0 = k1 + bw, nr1 = min(N0, nr0 + bw), nnew = nr1 - nr0;
-      if (nnew > 0)
-        bulk_load(
-            (int64_t)nnew * (N0 - k1),
-            [&](int64_t e) -> double { return t.H[(int64_t)(nr0 + e % nnew) + t.ldH * (k1 + e / nnew)]; },
-            [&](int64_t e, double v) { band[(int64_t)(hb0 + e % nnew) * N0 + k1 + e / nnew] = v; });
-      __syncthreads();
-    }
+  const int lane = threadIdx.x & 63;
+  const int c = k1 + blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (c >= N0) return;
+  double* col = t.LU + (int64_t)N0 * c + k0;
+  double x = lane < nb ? col[lane] : 0.0;
+  for (int kq = 0; kq < bw; ++kq) {
+    const int pq = pv[kq];
+    const double xk = lane_bcast(x, pq), xo = lane_bcast(x, kq);
+    if (lane == kq) x = xk;
+    else if (lane == pq) x = xo;
+    if (xk != 0.0 && lane > kq && lane < nb) x -= mul[kq * 64 + lane] * xk;
   }
-  if (bad && tid == 0) A[0] = __longlong_as_double(0x7ff8000000000000LL);
+  if (lane < nb) col[lane] = x;
 }
 
 // Kinv = K^{-1}: one wave per column of the identity, the column in LDS: forward sweep
@@ -678,10 +606,6 @@ __global__ __launch_bounds__(256) void k_hess_lu(const TriDev* __restrict__ tds)
 // multipliers of column k sit in rows (k, pe(k)) and are staged in LDS for the
 // workgroup when they fit), then back substitution with U, whose columns are staged in
 // LDS a block at a time by the whole workgroup.
-__device__ __forceinline__ void lds_order() {
-  __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): this wave's LDS operations are done
-  __builtin_amdgcn_wave_barrier();
-}
 template <bool kStageL>
 __global__ __launch_bounds__(256) void k_hess_inv(const TriDev* __restrict__ tds) {
   const TriDev t = tds[blockIdx.y];
@@ -795,22 +719,24 @@ void launch_sai_gram(ProbDev* d, TriDev* td, int nprob, int64_t maxn, double* pa
                      dim3(kGramRows), 0, st, d, td, part);
 }
 
-void launch_hess_inverse(TriDev* td, int nprob, int maxN0, int maxbw, hipStream_t st) {
+void launch_hess_inverse(TriDev* td, int nprob, int maxN0, int maxbw, int maxl, hipStream_t st) {
   static bool attr = false;
   if (!attr) {
-    const void* fns[3] = {(const void*)k_hess_lu<true>, (const void*)k_hess_inv<true>,
-                          (const void*)k_hess_inv<false>};
+    const void* fns[2] = {(const void*)k_hess_inv<true>, (const void*)k_hess_inv<false>};
     for (const void* f : fns)
       if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024) != hipSuccess)
         (void)hipGetLastError();
     attr = true;
   }
-  // the band of 2 bw rows in LDS when it fits for every problem of the batch
-  const size_t band = sizeof(double) * 2 * (size_t)maxbw * maxN0;
-  if (band <= (size_t)kSaiLdsDoubles * sizeof(double))
-    hipLaunchKernelGGL(k_hess_lu<true>, dim3((unsigned)nprob), dim3(256), band, st, td);
-  else
-    hipLaunchKernelGGL(k_hess_lu<false>, dim3((unsigned)nprob), dim3(256), 0, st, td);
+  {
+    const unsigned gi = (unsigned)std::min<int64_t>(1024, ((int64_t)maxN0 * maxN0 + 255) / 256);
+    hipLaunchKernelGGL(k_lu_init, dim3(gi, (unsigned)nprob), dim3(256), 0, st, td);
+    const dim3 gt((unsigned)((maxN0 + 3) / 4), (unsigned)nprob);
+    for (int jb = 0; jb < maxl; ++jb) {
+      hipLaunchKernelGGL(k_lu_panel, dim3((unsigned)nprob), dim3(64), 0, st, td, jb);
+      hipLaunchKernelGGL(k_lu_trail, gt, dim3(256), 0, st, td, jb);
+    }
+  }
   // four columns in LDS plus a work region (the staged multipliers, N0 x 2 bw, when they
   // fit -- else read in place -- then blocks of U's columns)
   const size_t ldsfull = sizeof(double) * kSaiLdsDoubles;

@@ -223,11 +223,38 @@ size_t update_smem(const ProbDev& d);
 size_t proj_smem(const ProbDev& d);
 int rows_p_for(int bw) { return bw <= 8 ? 128 : (bw <= 16 ? 64 : 32); }
 
-// Rows per update chunk: the smallest power of two from kRowsU up for which the update
-// kernel (chunk staging plus a register- or LDS-resident TSQR combine) fits in LDS; when
+// Rows per update chunk: kRowsU when the update kernel (chunk staging plus a register- or
+// LDS-resident TSQR combine) fits in LDS; else the smallest power of two from kRowsU up
+// for which the two-level combine (groups of kTreeFan chunk factors, then the stacked
+// group factors, each in LDS) fits; else the smallest with a one-level LDS combine; when
 // none does (wide blocks on long grids), the largest chunk whose staging fits, with the
 // combine working on the stacked chunk factors in global memory.
-void choose_update_chunks(int64_t n, int bw, int& rows_u, int& comb_global) {
+void choose_update_chunks(int64_t n, int bw, int& rows_u, int& comb_global, int& comb_tree) {
+  comb_tree = 0;
+  {
+    ProbDev d{};
+    d.bw = bw;
+    d.rows_u = kRowsU;
+    d.Cu = (int)std::max<int64_t>(1, n / kRowsU);
+    if (update_smem(d) <= (size_t)pe::kUpdateLdsMax) {
+      rows_u = kRowsU;
+      comb_global = 0;
+      return;
+    }
+  }
+  for (int ru = kRowsU; ru <= 1024; ru *= 2) {
+    ProbDev d{};
+    d.bw = bw;
+    d.rows_u = ru;
+    d.Cu = (int)std::max<int64_t>(1, n / ru);
+    d.comb_tree = 1;
+    if (update_smem(d) <= (size_t)pe::kUpdateLdsMax) {
+      rows_u = ru;
+      comb_global = 0;
+      comb_tree = 1;
+      return;
+    }
+  }
   for (int glob = 0; glob < 2; ++glob) {
     int best = 0;
     for (int ru = kRowsU; ru <= 4096; ru *= 2) {
@@ -253,7 +280,7 @@ void choose_update_chunks(int64_t n, int bw, int& rows_u, int& comb_global) {
 
 void set_geometry(ProbDev& d, int64_t n, int bw) {
   d.bw = bw;
-  choose_update_chunks(n, bw, d.rows_u, d.comb_global);
+  choose_update_chunks(n, bw, d.rows_u, d.comb_global, d.comb_tree);
   d.rows_u_log2 = 0;
   while ((1 << d.rows_u_log2) < d.rows_u) ++d.rows_u_log2;
   d.Cu = (int)std::max<int64_t>(1, n / d.rows_u);
@@ -274,9 +301,13 @@ size_t update_smem(const ProbDev& d) {
   const size_t ld = d.bw + 1;
   const size_t rmax = 2 * (size_t)d.rows_u;
   const bool reg = pe::combine_in_registers(d.bw, d.Cu);
-  const size_t xs = (reg || d.comb_global || rmax > (size_t)d.Cu * d.bw) ? rmax * ld : (size_t)d.Cu * d.bw * ld;
   const size_t bw2 = (size_t)d.bw * d.bw;
-  return sizeof(double) * (xs + pe::kSb + bw2 + d.bw + (rmax + 2) * d.bw + std::max<size_t>(bw2, 128)) + 64;
+  const size_t ng = (size_t)(d.Cu + pe::kTreeFan - 1) / pe::kTreeFan;
+  const size_t xs = d.comb_tree ? ld * std::max(rmax, std::max<size_t>(pe::kTreeFan, ng) * d.bw)
+                                : ((reg || d.comb_global || rmax > (size_t)d.Cu * d.bw) ? rmax * ld
+                                                                                        : (size_t)d.Cu * d.bw * ld);
+  return sizeof(double) * (xs + std::max<size_t>(pe::kSb, (rmax + 2) * d.bw) + bw2 + d.bw + std::max<size_t>(bw2, 128)) +
+         64;
 }
 
 // capacities of the per-problem block workspace for block widths up to bwmax
@@ -292,12 +323,13 @@ BlockCaps block_caps(int64_t n, int bwmax, int nbmax, int64_t H_rows, int64_t H_
   c.n = n;
   c.bwmax = bwmax;
   c.nbmax = nbmax;
-  size_t cu_bw2 = 0, cp_bw2 = 0;
+  size_t cu_bw2 = 0, cp_bw2 = 0, ngmax = 0;
   for (int bw = 1; bw <= bwmax; ++bw) {
     ProbDev d{};
     set_geometry(d, n, bw);
     cu_bw2 = std::max(cu_bw2, (size_t)d.Cu * bw * bw);
     cp_bw2 = std::max(cp_bw2, (size_t)d.Cp * bw * bw);
+    ngmax = std::max(ngmax, (size_t)(d.Cu + pe::kTreeFan - 1) / pe::kTreeFan);
   }
   c.basis = (size_t)nbmax * n * bwmax;
   c.qloc = (size_t)n * bwmax;
@@ -306,7 +338,9 @@ BlockCaps block_caps(int64_t n, int bwmax, int nbmax, int64_t H_rows, int64_t H_
   c.part = 2 * (size_t)nbmax * cp_bw2;
   c.S = 2 * (size_t)nbmax * bwmax * bwmax;
   c.H = (size_t)H_rows * H_cols;
-  c.cnt = 2 * (size_t)nbmax + 2;  // projection groups (2 passes), update counter, reorth flag
+  // projection groups (2 passes), update counter, reorth flag, group counters of the
+  // two-level combine
+  c.cnt = 2 * (size_t)nbmax + 2 + ngmax;
   c.ldH_rows = H_rows;
   c.H_cols = H_cols;
   return c;
@@ -447,7 +481,7 @@ struct StepCost {
 };
 
 void run_block_step(pe_ctx* ctx, ProbDev* dd, int nprob, int gx_proj, size_t smem_p, int gx_upd, size_t smem_u,
-                    int j, int nb, int mode, int mixed, const StepCost& cost, hipStream_t st) {
+                    int j, int nb, int mode, int mixed, int tree, const StepCost& cost, hipStream_t st) {
   // Timing covers the first pass, which every step runs in full; the second pass runs
   // only where the first lost too much of a column (decided on the device), so its
   // launches do not all carry the algorithmic traffic of the cost model.
@@ -456,7 +490,7 @@ void run_block_step(pe_ctx* ctx, ProbDev* dd, int nprob, int gx_proj, size_t sme
     pe::launch_block_proj(dd, nprob, gx_proj, smem_p, j, nb, pass, mode, mixed, st);
     prof_end(ctx, ev, cost.proj_bytes, cost.flops, st);
     ev = pass == 0 ? prof_begin(ctx, "block_update", st) : -1;
-    pe::launch_block_update(dd, nprob, gx_upd, smem_u, j, nb, pass, mode, mixed, st);
+    pe::launch_block_update(dd, nprob, gx_upd, smem_u, j, nb, pass, mode, mixed, tree, st);
     prof_end(ctx, ev, cost.upd_bytes, cost.flops, st);
   }
 }
@@ -859,7 +893,7 @@ pe_status march_batch(pe_ctx* ctx, const pe_problem* probs, const int* idx, int 
   const int max_cycles = env_int("PARAEXP_MAX_CYCLES", 0);
   while (true) {
     // ---- plan the cycle
-    int nact = 0, nreuse = 0, lmax = 0, gx_p = 0, gx_u = 0, mb_N = 1;
+    int nact = 0, nreuse = 0, lmax = 0, tree = 0, gx_p = 0, gx_u = 0, mb_N = 1;
     size_t smem_p = 0, smem_u = 0;
     int64_t maxNN = 1;
     for (int ii = 0; ii < nb_prob; ++ii) {
@@ -915,6 +949,7 @@ pe_status march_batch(pe_ctx* ctx, const pe_problem* probs, const int* idx, int 
         return pe_fail(ctx, PE_ERR_UNSUPPORTED, "cycle geometry exceeds the workspace");
       d.active = 1;
       ++nact;
+      tree |= d.comb_tree;
       lmax = std::max(lmax, d.l);
       gx_p = std::max(gx_p, d.Cp);
       gx_u = std::max(gx_u, d.Cu);
@@ -980,7 +1015,7 @@ pe_status march_batch(pe_ctx* ctx, const pe_problem* probs, const int* idx, int 
     // ---- S5: initial block and block Arnoldi (problems that start a new space)
     if (nact > 0) {
       HCK(hipMemcpyAsync(dd, hd.data(), sizeof(ProbDev) * nb_prob, hipMemcpyHostToDevice, st));
-      pe::launch_block_update(dd, nb_prob, gx_u, smem_u, 0, 0, 1, pe::MODE_INIT, mixed, st);
+      pe::launch_block_update(dd, nb_prob, gx_u, smem_u, 0, 0, 1, pe::MODE_INIT, mixed, tree, st);
       for (int j = 0; j < lmax; ++j) {
         const int groups = (j + 1 + pe::kSlotGroup - 1) / pe::kSlotGroup;
         StepCost cost;
@@ -993,16 +1028,16 @@ pe_status march_batch(pe_ctx* ctx, const pe_problem* probs, const int* idx, int 
           }
         if (sai) {
           pe::launch_sai_solve(dd, tdd, nb_prob, sai_groups, maxn_all * maxbwall, j, mixed, st);
-          run_block_step(ctx, dd, nb_prob, gx_p * groups, smem_p, gx_u, smem_u, j, j + 1, pe::MODE_SAI, mixed, cost,
-                         st);
+          run_block_step(ctx, dd, nb_prob, gx_p * groups, smem_p, gx_u, smem_u, j, j + 1, pe::MODE_SAI, mixed, tree,
+                         cost, st);
         } else {
-          run_block_step(ctx, dd, nb_prob, gx_p * groups, smem_p, gx_u, smem_u, j, j + 1, pe::MODE_ARNOLDI, mixed, cost,
-                         st);
+          run_block_step(ctx, dd, nb_prob, gx_p * groups, smem_p, gx_u, smem_u, j, j + 1, pe::MODE_ARNOLDI, mixed,
+                         tree, cost, st);
         }
       }
       if (sai) {  // residual Gram of the last block, then K^{-1} for the projected operator
         pe::launch_sai_gram(dd, tdd, nb_prob, maxn_all, (double*)(base + o_gpart), st);
-        pe::launch_hess_inverse(tdd, nb_prob, maxN0, maxbwall, st);
+        pe::launch_hess_inverse(tdd, nb_prob, maxN0, maxbwall, lmax, st);
       }
     }
     // ---- S6: projected exponential with step-size trials (a reused space keeps its
@@ -1762,8 +1797,9 @@ double pe_policy_step_growth(double rho, double pexp, int32_t krylov_steps) {
 
 int32_t pe_policy_reorth_skip(const double* R, const double* Rn, int32_t bw, double kappa) {
   if (!R || !Rn || bw < 1 || bw > 32) return 0;
+  double z[32];
   for (int b = 0; b < bw; ++b)
-    if (!pe::reorth_column_ok(R, Rn, bw, b, kappa)) return 0;
+    if (!pe::reorth_column_ok(R, Rn, bw, b, kappa, z)) return 0;
   return 1;
 }
 

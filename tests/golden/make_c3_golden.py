@@ -1,10 +1,11 @@
-"""Writes c3_burgers_k2.txt: sampled values of the oracle's waveform-relaxation iterate
+"""Writes c3_burgers_k<K>.txt: sampled values of the oracle's waveform-relaxation iterate
 for the full-size Burgers workload (n = 4096, nu = 5e-3, T = 0.5, one window, 512
 uniform samples, Jacobian-corrected iteration of Secs. 2.3-2.4, rank <= 24, l = 80)
-after two iterations.  Calls only the oracle and the seeded input generator; the dense
-oracle route takes about half a minute per iteration at this size.
+after K iterations (K = 2 and the workload's full K = 12 are stored).  Calls only the
+oracle and the seeded input generator; the dense oracle route takes about half a minute
+per iteration at this size.
 
-    python tests/golden/make_c3_golden.py
+    python tests/golden/make_c3_golden.py [K]
 """
 import os
 import sys
@@ -17,7 +18,6 @@ sys.path.insert(0, ROOT)
 import oracle  # noqa: E402
 import synth  # noqa: E402
 
-K = 2
 N_SAMPLED = 96
 
 
@@ -26,14 +26,14 @@ def sample_points(n, s, count, seed=5):
     return rng.integers(0, n, count), rng.integers(0, s, count)
 
 
-def main():
+def main(K):
     bp = synth.config_c3(K=K)
     ref, hist = oracle.wr_burgers(bp, "dense", return_history=True)  # (n, s)
     ii, kk = sample_points(bp.n, bp.s, N_SAMPLED)
-    out = os.path.join(os.path.dirname(os.path.abspath(__file__)), "c3_burgers_k2.txt")
+    out = os.path.join(os.path.dirname(os.path.abspath(__file__)), f"c3_burgers_k{K}.txt")
     with open(out, "w") as f:
         f.write("# Oracle waveform relaxation (Secs. 2.3-2.4, eqs. 2.10-2.20), Burgers n=4096, nu=5e-3,\n")
-        f.write("# T=0.5, P=1, s=512 uniform samples, Jacobian-corrected, rank<=24, l=80, K=2 iterations.\n")
+        f.write(f"# T=0.5, P=1, s=512 uniform samples, Jacobian-corrected, rank<=24, l=80, K={K} iterations.\n")
         f.write("# Written by tests/golden/make_c3_golden.py (oracle only).\n")
         f.write("increments " + " ".join(f"{h['increment']:.17e}" for h in hist) + "\n")
         f.write("column_norms " + " ".join(f"{v:.17e}" for v in np.linalg.norm(ref, axis=0)) + "\n")
@@ -42,4 +42,4 @@ def main():
 
 
 if __name__ == "__main__":
-    main()
+    main(int(sys.argv[1]) if len(sys.argv) > 1 else 2)
