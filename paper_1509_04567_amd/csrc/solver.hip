@@ -145,6 +145,9 @@ constexpr int kSaiMaxN0 = 4000;
 void sai_chunking(int64_t n, int& R, int& C) {
   C = 1;
   while (2 * C <= 256 && 2 * (int64_t)C * 16 <= n) C *= 2;
+  // the last chunk takes the remainder; the solve kernels hold R..2R-1 rows per chunk
+  // (LDS staging, sweeps), so C is halved until the remainder is below R
+  while (C > 1 && n % C >= n / C) C /= 2;
   R = (int)(n / C);
 }
 int sai_red_doubles(int C) {

@@ -141,3 +141,19 @@ def test_sai_shift_choice_does_not_change_the_result(ctx):
         sai(p, f)
         outs, reps = ctx.solve_batch([p])
         assert rel(gpu_out(outs[0]), ref) < FP64_TOL, (f, reps[0])
+
+
+@pytest.mark.parametrize("idx", [21, 63])
+def test_sai_grids_with_a_long_remainder(ctx, idx):
+    # n = 14832 and 10689 (instances 21 and 63 of the 512-instance batch): with 256 chunks
+    # the remainder rows (240, 193) would exceed a chunk's length (the solve then returned
+    # errors of 3e-2 with no flag); the chunk count is reduced until the last chunk keeps
+    # fewer than 2R rows.  These operators are stiff (|L| ~ 1e7 for instance 21), so the
+    # workload's own tolerance 1e-9 and ten times it as the bar, as in the batch test.
+    p = synth.config_c4(indices=[idx], tol=1e-9)[0]
+    p.krylov = 1
+    ref, _ = oracle.solve_window(p, "spectral")
+    outs, reps = ctx.solve_batch([p])
+    assert not reps[0]["flags"] & 1, reps[0]
+    err = rel(gpu_out(outs[0]), ref)
+    assert err < 1e-8, (err, reps[0])

@@ -6,7 +6,8 @@ nu = 1e-2, dx = 1e-3 (n = 1000), 100 samples per window, rank-2 source; the inte
 Pins: (1) the superposed GPU solution equals the oracle's (spectral route) to the FP64
 bar; (2) its error against the exact PDE solution at T = 1 reproduces the serial
 error of Table 1 (tests/golden/table1_serial_error.txt) within 1% for every P -- the
-Paraexp split does not change the result, which is the paper's claim for PEBK."""
+Paraexp split does not change the result, which is the paper's claim for PEBK.  Every P of
+the table (1 to 32) with both Krylov spaces."""
 import os
 
 import numpy as np
@@ -42,10 +43,14 @@ def ctx():
     c.close()
 
 
-@pytest.mark.parametrize("P", [1, 2, 4, 8])
-def test_table1_manufactured_ade_on_gpu(ctx, P):
+@pytest.mark.parametrize("krylov", [0, 1])
+@pytest.mark.parametrize("P", [1, 2, 4, 8, 16, 32])
+def test_table1_manufactured_ade_on_gpu(ctx, P, krylov):
+    # krylov 0: the polynomial block Krylov space; 1: shift-and-invert
     wins, exact = synth.manufactured_ade(n=1000, P=P, s=100, krylov_steps=20, rank_max=8, q_max=32,
                                          tol=1e-12, svd_tol=1e-12, fit_tol=1e-13)
+    for w in wins:
+        w.krylov = krylov
     outs, reps = ctx.solve_batch(wins)
     assert all(r["rank"] == 2 for r in reps)
     u = ctx.superpose(wins[0].u0, outs).detach().cpu().numpy()[0]
