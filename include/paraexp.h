@@ -233,6 +233,9 @@ pe_status pe_superpose(pe_ctx* ctx, const double* u0, const double* const* v, in
  *   u0       device, n
  *   u_init   device, n x (P s), ld n, window-major columns; NULL = u0 at every sample
  *   u_final  device, n x (P s), ld n: the iterate after K iterations (may alias u_init)
+ *   forcing  device, n x (P s), ld n, window-major columns: samples of an external source
+ *            f(x, t) added to the nonlinear term at every sample (the manufactured source
+ *            of Sec. 4.1, eq. 4.1); NULL = none
  *   the remaining fields are as in pe_problem and apply to every window solve.
  * reports: host, P entries (the window solves of the last iteration); increments: host,
  * K entries (|u_{k+1} - u_k| / |u_{k+1}| over all samples), or NULL. */
@@ -250,6 +253,7 @@ typedef struct {
   pe_precision prec;
   pe_krylov krylov;
   double sai_shift;
+  const double* forcing;
 } pe_wr_problem;
 pe_status pe_wr_burgers(pe_ctx* ctx, const pe_wr_problem* wr, pe_report* reports, double* increments,
                         void* stream);

@@ -3,7 +3,8 @@
 Semi-discrete Burgers (eq. (4.1), central differences, Sec. 4.1):
     u' = A u + N(u),   A = nu D2,   N(u)_i = -u_i (u_{i+1} - u_{i-1}) / (2h).
 Iteration k -> k+1 treats the nonlinearity as a known source g_k(t) = N(u_k(t))
-(eq. (2.10)).  With the Jacobian correction (eqs. (2.12)-(2.13), windowed as in
+(eq. (2.10)), plus an external source f(x, t) when the problem carries one (the
+manufactured source of Sec. 4.1).  With the Jacobian correction (eqs. (2.12)-(2.13), windowed as in
 eq. (2.14)) the operator on window j is A + Jbar_j, where Jbar_j is the time average
 of dN/du(u_k(t)) over the window (trapezoid rule over the window's samples), and the
 source is g_k - Jbar_j u_k.  The shifted source of eq. (2.16) is read as
@@ -75,6 +76,8 @@ def wr_burgers(bp, route: str = "dense", return_history: bool = False):
             if not bp.jacobian and route == "spectral":
                 Lj = A.copy()
             Graw = burgers_nonlinear(uk, h) - apply_stencil(Jbar, uk)
+            if getattr(bp, "forcing", None) is not None:  # external source f(x, t) (Sec. 4.1)
+                Graw = Graw + np.asarray(bp.forcing)[:, j * s:(j + 1) * s]
             Ghat = source_samples(Lj, u0, Graw, True)
             m, U, C, sig, tail, _ = compress(Ghat, bp.svd_tol, bp.rank_max)
             q, Pi, res, _ = fit_time_polynomial(C, times[j], times[j][0], times[j][-1],

@@ -116,6 +116,7 @@ class PeWrProblem(ctypes.Structure):
         ("prec", ctypes.c_int32),
         ("krylov", ctypes.c_int32),
         ("sai_shift", ctypes.c_double),
+        ("forcing", ctypes.c_void_p),
     ]
 
 
@@ -471,13 +472,17 @@ class Context:
         u0 = _dev(bp.u0, self.device)
         out = torch.empty((P * s, n), dtype=torch.float64, device=self.device)
         ui = _dev(u_init, self.device) if u_init is not None else None
+        fo = getattr(bp, "forcing", None)
+        # (n, P*s) samples, window-major columns -> device (P*s, n) rows, i.e. ld n
+        fd = _dev(np.ascontiguousarray(np.asarray(fo, dtype=np.float64).T), self.device) if fo is not None else None
         wp = PeWrProblem(n=n, nu=float(bp.nu), T=float(bp.T), P=P, s=s, K=K, jacobian=int(bool(bp.jacobian)),
                          u0=u0.data_ptr(), u_init=ui.data_ptr() if ui is not None else None,
                          u_final=out.data_ptr(), krylov_steps=int(bp.krylov_steps), rank_max=int(bp.rank_max),
                          q_max=int(bp.q_max), tol=float(bp.tol), svd_tol=float(bp.svd_tol),
                          fit_tol=float(bp.fit_tol), prec=int(precision),
                          krylov=int(getattr(bp, "krylov", PE_KRYLOV_POLY)),
-                         sai_shift=float(getattr(bp, "sai_shift", 0.0)))
+                         sai_shift=float(getattr(bp, "sai_shift", 0.0)),
+                         forcing=fd.data_ptr() if fd is not None else None)
         reps = (PeReport * P)()
         inc = (ctypes.c_double * max(K, 1))()
         self._check(self.lib.pe_wr_burgers(self.h, ctypes.byref(wp), reps, inc, _stream_ptr()))

@@ -102,8 +102,9 @@ void launch_cp_range(int64_t n, int s, int kcap, const double* G, double* A, dou
 void read_cp_state(const void* host_copy, int* k, double* gfro2, double* res2);
 
 // waveform relaxation (Burgers): per-point operator and source samples of one window
+// F: forcing samples of the window (n x s, ld n) added to the source, or null
 void launch_wr_source(int64_t n, int s, double h, double nu, const double* U, int jacobian, double w_end, double w_in,
-                      double* coef, double* G, hipStream_t st);
+                      const double* F, double* coef, double* G, hipStream_t st);
 void launch_diff_norms(const double* a, const double* b, int64_t cnt, double* part, int blocks, hipStream_t st);
 
 // utilities

@@ -1670,7 +1670,8 @@ void launch_superpose(const double* u0, const double* const* v, int P, int64_t n
 // Jbar = 0 (Picard iteration).  One thread per grid point.
 // ------------------------------------------------------------------------------------
 __global__ void k_wr_source(int64_t n, int s, double h, double nu, const double* __restrict__ U, int jacobian,
-                            double w_end, double w_in, double* __restrict__ coef, double* __restrict__ G) {
+                            double w_end, double w_in, const double* __restrict__ F, double* __restrict__ coef,
+                            double* __restrict__ G) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= n) return;
   const int64_t rm = r == 0 ? n - 1 : r - 1, rp = r == n - 1 ? 0 : r + 1;
@@ -1692,14 +1693,14 @@ __global__ void k_wr_source(int64_t n, int s, double h, double nu, const double*
   for (int i = 0; i < s; ++i) {
     const double* u = U + (int64_t)i * n;
     const double um = u[rm], uz = u[r], up = u[rp];
-    G[(int64_t)i * n + r] = -uz * (up - um) * i2h - (j0 * um + j1 * uz + j2 * up);
+    G[(int64_t)i * n + r] = -uz * (up - um) * i2h - (j0 * um + j1 * uz + j2 * up) + (F ? F[(int64_t)i * n + r] : 0.0);
   }
 }
 
 void launch_wr_source(int64_t n, int s, double h, double nu, const double* U, int jacobian, double w_end, double w_in,
-                      double* coef, double* G, hipStream_t st) {
+                      const double* F, double* coef, double* G, hipStream_t st) {
   hipLaunchKernelGGL(k_wr_source, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, s, h, nu, U, jacobian,
-                     w_end, w_in, coef, G);
+                     w_end, w_in, F, coef, G);
 }
 
 // per-block partial sums of |a - b|^2 and |a|^2 over cnt contiguous doubles

@@ -1548,7 +1548,8 @@ pe_status pe_wr_burgers(pe_ctx* ctx, const pe_wr_problem* wr, pe_report* reports
     for (int k = 0; k < w.K && res == PE_OK; ++k) {
       // sources and operators of every window from the current iterate
       for (int j = 0; j < P; ++j)
-        pe::launch_wr_source(n, s, h, w.nu, Uk + (size_t)j * s * n, w.jacobian, w_end, w_in, coef + 3 * (size_t)n * j,
+        pe::launch_wr_source(n, s, h, w.nu, Uk + (size_t)j * s * n, w.jacobian, w_end, w_in,
+                             w.forcing ? w.forcing + (size_t)j * s * n : nullptr, coef + 3 * (size_t)n * j,
                              G + (size_t)j * s * n, st);
       // the P window subproblems, batched: v_j at the window's own samples
       std::vector<pe_problem> pr((size_t)P);

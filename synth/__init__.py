@@ -22,6 +22,8 @@ from .workloads import (  # noqa: F401
     config_c4,
     config_c4_subset,
     manufactured_ade,
+    manufactured_burgers,
+    sawtooth_wave,
     split_windows,
     c2_source,
     random_ade_problem,

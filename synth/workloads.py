@@ -81,6 +81,7 @@ class BurgersProblem:
     name: str = ""
     krylov: int = 0
     sai_shift: float = 0.0
+    forcing: Optional[np.ndarray] = None   # (n, P*s) external source samples, window-major
 
     def window_times(self, j: int) -> np.ndarray:
         t0 = self.T * j / self.P
@@ -272,6 +273,44 @@ def manufactured_ade(n: int = 1000, P: int = 8, s: int = 100, nu: float = 1e-2, 
 
     wins = ade_windows(n, ade_coeffs(n, a, nu), u0, f_at, T, P, s, np.array([T]), **kw)
     return wins, exact
+
+
+def sawtooth_wave(xi: np.ndarray, eps: float = 0.1, kmax: int = 100):
+    """Smoothed sawtooth of Sec. 4.1 (eq. 4.2): u(xi) = 1/2 - sum_{k<=kmax} sin(2 pi k xi)
+    Phi(k, eps) / (pi k), Phi = (pi k eps / 2) / sinh(pi k eps / 2); returns u, u', u''."""
+    xi = np.asarray(xi, dtype=np.float64)
+    u = np.full(xi.shape, 0.5)
+    du = np.zeros(xi.shape)
+    d2u = np.zeros(xi.shape)
+    for k in range(1, kmax + 1):
+        z = np.pi * k * eps / 2
+        c = (z / np.sinh(z)) / (np.pi * k)
+        arg = 2 * np.pi * k * xi
+        u -= c * np.sin(arg)
+        du -= c * 2 * np.pi * k * np.cos(arg)
+        d2u += c * (2 * np.pi * k) ** 2 * np.sin(arg)
+    return u, du, d2u
+
+
+def manufactured_burgers(n: int = 100, nu: float = 1e-2, T: float = 0.1, P: int = 1, s: int = 50, K: int = 8,
+                         speed: float = 0.5, **kw):
+    """Travelling smoothed sawtooth of Sec. 4.1: u(x, t) = sawtooth(xi), xi = x - speed t +
+    1/2, an exact solution of u_t + u u_x = nu u_xx + f with f = (u - speed) u_xi - nu u_xixi
+    (eq. 4.1 with the manufactured source), sampled at the WR samples of every window.
+    Returns (BurgersProblem, exact(t) -> u(x, t) on the grid)."""
+    x = grid(n)
+
+    def exact(t):
+        return sawtooth_wave(x - speed * t + 0.5)[0]
+
+    bp = BurgersProblem(n=n, nu=nu, T=T, P=P, s=s, K=K, u0=exact(0.0), name=f"sawtooth_n{n}_P{P}", **kw)
+    cols = []
+    for j in range(P):
+        for t in bp.window_times(j):
+            u, du, d2u = sawtooth_wave(x - speed * t + 0.5)
+            cols.append((u - speed) * du - nu * d2u)
+    bp.forcing = np.stack(cols, axis=1)
+    return bp, exact
 
 
 def random_ade_problem(seed: int, n: int, modes: int = 3, deg: int = 4, s: int = 24,

@@ -448,3 +448,16 @@ def test_truncation_floor_and_cap():
     assert _rank_by_eckart_young(sig, 1e-13) == 4
     m, *_ = oracle.compress(G, 1e-13, 30)
     assert m == 4
+
+
+def test_wr_with_the_manufactured_sawtooth_source_reaches_a_second_order_floor():
+    # Sec. 4.1: with the manufactured source the waveform-relaxation iterate converges to
+    # the semi-discrete solution, whose distance to the exact travelling sawtooth is the
+    # O(dx^2) error of the central differences (the floor of the paper's error histories)
+    floors = []
+    for n in (100, 200):
+        bp, exact = synth.manufactured_burgers(n=n, P=1, s=50, K=8)
+        U = oracle.wr_burgers(bp, "dense")
+        ex = np.stack([exact(t) for t in bp.window_times(0)], axis=1)
+        floors.append(np.linalg.norm(U - ex) / np.linalg.norm(ex))
+    assert 3.6 < floors[0] / floors[1] < 4.5, floors
