@@ -69,6 +69,12 @@ typedef enum { PE_FP64 = 0, PE_MIXED = 1 } pe_precision;
  * (Sec. 2.1, Sec. 3.2), whose convergence does not degrade with the grid's stiffness. */
 typedef enum { PE_KRYLOV_POLY = 0, PE_KRYLOV_SAI = 1 } pe_krylov;
 
+/* The time dependence p(t) of the compressed source (Sec. 2.1, eq. 2.3): one
+ * least-squares polynomial over the window in the Chebyshev basis (degree chosen by
+ * fit_tol, capped by q_max), or the paper's own choice (Sec. 3): the piecewise cubic
+ * spline interpolating the coefficients at the samples, not-a-knot end conditions. */
+typedef enum { PE_FIT_CHEBYSHEV = 0, PE_FIT_SPLINE = 1 } pe_source_fit;
+
 typedef struct pe_ctx pe_ctx; /* opaque: device, stream-independent workspace */
 
 /* The operator L (Sec. 3, eq. 3.2):
@@ -100,7 +106,10 @@ typedef struct {
  *   sai_shift shift-and-invert only: gamma = sai_shift times the step a restart cycle
  *             aims at (0: 0.1); the shifted system is solved as a periodic tridiagonal
  *             system without pivoting, so I - gamma L should be diagonally dominant
- *             (always so for 2 nu >= |a| h, the cell Peclet condition). */
+ *             (always so for 2 nu >= |a| h, the cell Peclet condition)
+ *   source_fit PE_FIT_CHEBYSHEV or PE_FIT_SPLINE (then q_max and fit_tol are unused, the
+ *             report's q is 4, and every sample time is a restart point of the march;
+ *             pe_expaction_batch takes Chebyshev coefficients only). */
 typedef struct {
   pe_stencil op;
   const double* u0;
@@ -123,6 +132,7 @@ typedef struct {
   pe_precision prec;
   pe_krylov krylov;
   double sai_shift;
+  pe_source_fit source_fit;
 } pe_problem;
 
 /* Per-problem report (host). */
@@ -158,7 +168,9 @@ pe_status pe_stencil_apply(pe_ctx* ctx, const pe_stencil* op, const double* X, i
  * Chebyshev fit of the coefficients, for one problem.
  *   U     device, n x rank_max (ldU = n): the m retained left singular vectors
  *   Pi    device, rank_max x q_max (ld = rank_max): p(t) = sum_k Pi[:,k] T_k(x(t)),
- *         x = (2t - t0 - t1)/(t1 - t0)
+ *         x = (2t - t0 - t1)/(t1 - t0); with source_fit = PE_FIT_SPLINE it receives the
+ *         spline pieces instead (room for 4 (s - 1) rank_max doubles): Pi[(i 4 + k) m + a]
+ *         is coefficient k of row a on piece i, p_a(t) = sum_k c_k (t - t_i)^k
  *   sigma host, s entries (may be NULL): singular values of the shifted samples that
  *         the routine resolved (zeros beyond the numerical rank), descending
  *   m, q  host out; report host out (rank, q, fit_resid, svd_tail, sigma1, flags). */
@@ -254,6 +266,7 @@ typedef struct {
   pe_krylov krylov;
   double sai_shift;
   const double* forcing;
+  pe_source_fit source_fit;
 } pe_wr_problem;
 pe_status pe_wr_burgers(pe_ctx* ctx, const pe_wr_problem* wr, pe_report* reports, double* increments,
                         void* stream);

@@ -15,6 +15,13 @@ t1)/(t1 - t0)) one has w' = K w with a constant nilpotent K, and
 
 so the window solution at any time is one matrix exponential of this augmented
 matrix applied to [v(t0); w(t0)].
+
+With the piecewise-cubic source (the paper's choice, Sec. 3) each spline piece
+[t_i, t_{i+1}] is a segment of its own: the state carries the piece's Taylor
+coefficients z_j = p^(j)(t) / j! (blocks of m), z' = K z with K the shift
+z_j' = (j + 1) z_{j+1}, the source is U z_0, and at t_i the polynomial part restarts
+from the piece's coefficients.  The augmented matrix [[L, [U 0 0 0]], [0, K]] is the
+same for every piece, so its exponentials are shared.
 """
 from __future__ import annotations
 
@@ -23,7 +30,8 @@ from typing import List, Optional
 
 import numpy as np
 
-from .compress import chebyshev_vandermonde, compress, fit_time_polynomial, source_samples
+from .compress import (chebyshev_vandermonde, compress, fit_cubic_spline, fit_time_polynomial, source_samples,
+                       spline_generator)
 from .expm import expm
 from .operator import dense_operator, stencil_symbol
 
@@ -39,12 +47,19 @@ def time_generator(q: int, t0: float, t1: float) -> np.ndarray:
 
 
 def window_model(p):
-    """S1-S4 of one window: shifted samples, truncated SVD, Chebyshev fit.
+    """S1-S4 of one window: shifted samples, truncated SVD, Chebyshev fit (or, with
+    p.source_fit == 1, the piecewise-cubic spline).
 
     Returns a dict with B = U Pi (n, q) (so that the fitted source is B w(t)), K, the
-    window start vector w(t0) = [T_k(-1)], and diagnostics."""
+    window start vector w(t0) = [T_k(-1)], and diagnostics; for the spline also Cp
+    (pieces, 4, m) and the shared piece matrices."""
     Ghat = source_samples(p.coeffs, p.u0, p.G, p.shift)
     m, U, C, sig, tail, f1 = compress(Ghat, p.svd_tol, p.rank_max)
+    if getattr(p, "source_fit", 0) == 1:
+        Cp = fit_cubic_spline(C, p.t_samples) if m > 0 else None
+        Bz = np.hstack([U, np.zeros((p.n, 3 * m))]) if m > 0 else np.zeros((p.n, 0))
+        return dict(m=m, q=4 * m, U=U, C=C, Cp=Cp, Bz=Bz, Kz=spline_generator(m) if m > 0 else None,
+                    spline=True, sigma=sig, svd_tail=tail, fit_resid=0.0, flags=f1)
     q, Pi, res, f2 = fit_time_polynomial(C, p.t_samples, p.t0, p.t1, p.fit_tol, p.q_max)
     B = U @ Pi if m > 0 else np.zeros((p.n, 0))
     K = time_generator(q, p.t0, p.t1)
@@ -58,13 +73,17 @@ def _delta_key(d: float) -> float:
 
 
 class _Segment:
-    """Time interval [ta, tb) with operator coefficients and an optional fitted source."""
+    """Time interval [ta, tb) with operator coefficients and an optional fitted source.
+    Segments with the same `key` share B, K and coefficients (their exponentials are
+    cached once); `cheb` marks a Chebyshev-basis source (w(t) = [T_k(x(t))])."""
 
-    def __init__(self, ta, tb, coeffs, B=None, K=None, w_a=None):
+    def __init__(self, ta, tb, coeffs, B=None, K=None, w_a=None, key=None, cheb=True):
         self.ta, self.tb, self.coeffs = float(ta), float(tb), coeffs
         q = 0 if K is None else K.shape[0]
         self.q = q if (B is not None and q > 0) else 0
         self.B, self.K, self.w_a = B, K, w_a
+        self.key = id(self) if key is None else key
+        self.cheb = cheb
 
 
 class _DenseStepper:
@@ -73,7 +92,7 @@ class _DenseStepper:
         self.cache = {}
 
     def _aug(self, seg):
-        key = ("A", id(seg))
+        key = ("A", seg.key)
         if key not in self.cache:
             L = dense_operator(self.n, seg.coeffs)
             if seg.q:
@@ -93,7 +112,7 @@ class _DenseStepper:
         return st
 
     def advance(self, seg, st, w, delta):
-        key = ("E", id(seg), _delta_key(delta))
+        key = ("E", seg.key, _delta_key(delta))
         if key not in self.cache:
             self.cache[key] = expm(_delta_key(delta) * self._aug(seg))
         E = self.cache[key]
@@ -118,7 +137,7 @@ class _SpectralStepper:
         return np.fft.ifft(st).real
 
     def _aug(self, seg):
-        key = ("A", id(seg))
+        key = ("A", seg.key)
         if key not in self.cache:
             lam = stencil_symbol(self.n, seg.coeffs)
             if seg.q:
@@ -133,7 +152,7 @@ class _SpectralStepper:
 
     def advance(self, seg, st, w, delta):
         d = _delta_key(delta)
-        key = ("E", id(seg), d)
+        key = ("E", seg.key, d)
         A = self._aug(seg)
         if not seg.q:
             return np.exp(d * A) * st, w
@@ -171,7 +190,7 @@ def _march(route, n, segments: List[_Segment], x0, t_start, t_out):
             seg = segments[si]
             te = min(tk, seg.tb)
             if te > t:
-                if seg.q:
+                if seg.q and seg.cheb:
                     # The polynomial block's exponential over a long step multiplies
                     # rounding by the Chebyshev re-expansion coefficients of the shift
                     # (about (1 + sqrt(2c))^q for a shift of c = 2 step / window in x),
@@ -195,6 +214,19 @@ def _march(route, n, segments: List[_Segment], x0, t_start, t_out):
     return out
 
 
+def source_segments(mdl, coeffs, t0, t1, t_samples, key=None):
+    """The source-carrying segments of a window: one Chebyshev segment [t0, t1], or one
+    segment per spline piece [t_i, t_{i+1}] sharing one augmented matrix."""
+    if not mdl.get("spline"):
+        return [_Segment(t0, t1, coeffs, mdl["B"] if mdl["q"] else None, mdl["K"], mdl["w0"])]
+    if mdl["m"] == 0:
+        return [_Segment(t0, t1, coeffs)]
+    key = ("spline", id(mdl)) if key is None else key
+    ts = np.asarray(t_samples, dtype=np.float64)
+    return [_Segment(ts[i], ts[i + 1], coeffs, mdl["Bz"], mdl["Kz"], mdl["Cp"][i].reshape(-1), key=key, cheb=False)
+            for i in range(len(ts) - 1)]
+
+
 def _auto_route(p, route):
     if route != "auto":
         return route
@@ -207,8 +239,7 @@ def solve_window(p, route: str = "auto", model: Optional[dict] = None):
     route = _auto_route(p, route)
     mdl = model or window_model(p)
     n = p.n
-    segs = [_Segment(p.t0, p.t1, p.coeffs, mdl["B"] if mdl["q"] else None, mdl["K"], mdl["w0"]),
-            _Segment(p.t1, math.inf, p.coeffs)]
+    segs = source_segments(mdl, p.coeffs, p.t0, p.t1, p.t_samples) + [_Segment(p.t1, math.inf, p.coeffs)]
     t_out = np.asarray(p.t_out, dtype=np.float64)
     out = np.zeros((n, len(t_out)))
     later = t_out >= p.t0
@@ -239,7 +270,7 @@ def solve_sequential(probs, route: str = "auto"):
     segs = []
     for p in probs:
         mdl = window_model(p)
-        segs.append(_Segment(p.t0, p.t1, p.coeffs, mdl["B"] if mdl["q"] else None, mdl["K"], mdl["w0"]))
+        segs += source_segments(mdl, p.coeffs, p.t0, p.t1, p.t_samples)
     segs.append(_Segment(probs[-1].t1, math.inf, probs[-1].coeffs))
     u0 = np.asarray(probs[0].u0, dtype=np.float64)
     out = _march(route, n, segs, np.zeros(n), probs[0].t0, probs[0].t_out)
@@ -248,6 +279,7 @@ def solve_sequential(probs, route: str = "auto"):
 
 def march_segments(route, n, seg_specs, x0, t_start, t_out):
     """Public form of the segment march for the waveform-relaxation oracle: seg_specs is a
-    list of (ta, tb, coeffs, B or None, K or None, w_a or None)."""
-    segs = [_Segment(*s) for s in seg_specs]
+    list of (ta, tb, coeffs, B or None, K or None, w_a or None) tuples or of segments made
+    by source_segments."""
+    segs = [s if isinstance(s, _Segment) else _Segment(*s) for s in seg_specs]
     return _march(route, n, segs, x0, t_start, t_out)

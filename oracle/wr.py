@@ -21,8 +21,8 @@ import math
 
 import numpy as np
 
-from .compress import compress, fit_time_polynomial, source_samples
-from .march import march_segments, time_generator
+from .compress import compress, fit_cubic_spline, fit_time_polynomial, source_samples, spline_generator
+from .march import march_segments, source_segments, time_generator
 from .compress import chebyshev_vandermonde
 from .operator import apply_stencil
 
@@ -80,6 +80,13 @@ def wr_burgers(bp, route: str = "dense", return_history: bool = False):
                 Graw = Graw + np.asarray(bp.forcing)[:, j * s:(j + 1) * s]
             Ghat = source_samples(Lj, u0, Graw, True)
             m, U, C, sig, tail, _ = compress(Ghat, bp.svd_tol, bp.rank_max)
+            if getattr(bp, "source_fit", 0) == 1:  # piecewise-cubic p(t)
+                mdl = dict(m=m, q=4 * m, spline=True, Cp=fit_cubic_spline(C, times[j]) if m else None,
+                           Bz=np.hstack([U, np.zeros((n, 3 * m))]) if m else None,
+                           Kz=spline_generator(m) if m else None)
+                models.append((mdl, None, None, m, 4 * m))
+                opers.append(Lj)
+                continue
             q, Pi, res, _ = fit_time_polynomial(C, times[j], times[j][0], times[j][-1],
                                                 bp.fit_tol, bp.q_max)
             B = U @ Pi if m > 0 else None
@@ -90,7 +97,10 @@ def wr_burgers(bp, route: str = "dense", return_history: bool = False):
         V = np.zeros((n, P * s))
         for j in range(P):
             B, K, w0, m, q = models[j]
-            specs = [(times[j][0], times[j][-1], opers[j], B, K, w0)]
+            if isinstance(B, dict):  # spline pieces of window j
+                specs = source_segments(B, opers[j], times[j][0], times[j][-1], times[j])
+            else:
+                specs = [(times[j][0], times[j][-1], opers[j], B, K, w0)]
             for i in range(j + 1, P):
                 specs.append((times[i][0], times[i][-1], opers[i], None, None, None))
             specs.append((times[-1][-1], math.inf, opers[-1], None, None, None))

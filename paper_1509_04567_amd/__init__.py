@@ -13,6 +13,8 @@ from .binding import (  # noqa: F401
     PE_MIXED,
     PE_KRYLOV_POLY,
     PE_KRYLOV_SAI,
+    PE_FIT_CHEBYSHEV,
+    PE_FIT_SPLINE,
     PE_OK,
     PE_ERR_ARG,
     PE_ERR_NONFINITE,

@@ -30,6 +30,8 @@ PE_FP64 = 0
 PE_MIXED = 1
 PE_KRYLOV_POLY = 0
 PE_KRYLOV_SAI = 1
+PE_FIT_CHEBYSHEV = 0
+PE_FIT_SPLINE = 1
 FLAG_NOT_CONVERGED = 1
 FLAG_BREAKDOWN = 2
 FLAG_RANK_CAPPED = 4
@@ -74,6 +76,7 @@ class PeProblem(ctypes.Structure):
         ("prec", ctypes.c_int32),
         ("krylov", ctypes.c_int32),
         ("sai_shift", ctypes.c_double),
+        ("source_fit", ctypes.c_int32),
     ]
 
 
@@ -117,6 +120,7 @@ class PeWrProblem(ctypes.Structure):
         ("krylov", ctypes.c_int32),
         ("sai_shift", ctypes.c_double),
         ("forcing", ctypes.c_void_p),
+        ("source_fit", ctypes.c_int32),
     ]
 
 
@@ -305,6 +309,7 @@ def make_problem(src, device, precision: int = PE_FP64, out=None) -> DeviceProbl
     st.prec = int(precision)
     st.krylov = int(getattr(src, "krylov", PE_KRYLOV_POLY))
     st.sai_shift = float(getattr(src, "sai_shift", 0.0))
+    st.source_fit = int(getattr(src, "source_fit", PE_FIT_CHEBYSHEV))
     return DeviceProblem(struct=st, out=out[:n_out], keep=keep)
 
 
@@ -387,8 +392,10 @@ class Context:
         torch = _torch()
         dp = make_problem(src, self.device, precision)
         n, rmax, qmax = int(src.n), int(src.rank_max), int(src.q_max)
+        spline = int(getattr(src, "source_fit", PE_FIT_CHEBYSHEV)) == PE_FIT_SPLINE
+        npc = max(int(dp.struct.s) - 1, 1)
         U = torch.zeros((max(rmax, 1), n), dtype=torch.float64, device=self.device)
-        Pi = torch.zeros((qmax, max(rmax, 1)), dtype=torch.float64, device=self.device)
+        Pi = torch.zeros((4 * npc if spline else qmax, max(rmax, 1)), dtype=torch.float64, device=self.device)
         m, q = ctypes.c_int32(), ctypes.c_int32()
         sig = (ctypes.c_double * max(dp.struct.s, 1))()
         rep = PeReport()
@@ -397,6 +404,10 @@ class Context:
                        ctypes.c_void_p(Pi.data_ptr()), ctypes.byref(m), ctypes.byref(q), sig,
                        ctypes.byref(rep), _stream_ptr()))
         mm, qq = m.value, q.value
+        if spline:  # piece coefficients: Pw[(i 4 + k) m + a] -> (pieces, 4, m)
+            flat = Pi.reshape(-1)[:4 * npc * mm]
+            return dict(U=U[:mm], Pw=flat.reshape(npc, 4, mm), m=mm, q=qq,
+                        sigma=np.array(sig[:dp.struct.s]), report=rep.as_dict())
         # U rows 0..m-1 are the retained columns; Pi is (rank_max x q_max) column-major
         return dict(U=U[:mm], Pi=Pi[:qq, :mm].T.contiguous() if mm else Pi[:0, :0], m=mm, q=qq,
                     sigma=np.array(sig[:dp.struct.s]), report=rep.as_dict())
@@ -482,7 +493,8 @@ class Context:
                          fit_tol=float(bp.fit_tol), prec=int(precision),
                          krylov=int(getattr(bp, "krylov", PE_KRYLOV_POLY)),
                          sai_shift=float(getattr(bp, "sai_shift", 0.0)),
-                         forcing=fd.data_ptr() if fd is not None else None)
+                         forcing=fd.data_ptr() if fd is not None else None,
+                         source_fit=int(getattr(bp, "source_fit", PE_FIT_CHEBYSHEV)))
         reps = (PeReport * P)()
         inc = (ctypes.c_double * max(K, 1))()
         self._check(self.lib.pe_wr_burgers(self.h, ctypes.byref(wp), reps, inc, _stream_ptr()))

@@ -147,6 +147,14 @@ struct ExpmDev {
   int32_t prop;
   double* Eprop;           // N x N column-major
   double* ycur;            // N
+  // piecewise-cubic source: q = 4 m, the polynomial part holds the Taylor coefficients
+  // z_j = p^(j)(t) / j! (blocks of m, z_j' = (j + 1) z_{j+1}); Pw[(i 4 + k) m + a] is
+  // coefficient k of piece i of row a; piece / pdelta locate the current time
+  int32_t spline;
+  const double* Pw;
+  int32_t piece;
+  double pdelta;
+  int32_t zreset;          // 1: k_spline_reset rewrites ycur's z part
 };
 
 // Host-visible helpers ---------------------------------------------------------

@@ -87,6 +87,10 @@ void launch_form_u(const double* Q, int bwc, int64_t n, const int* sel, int r, c
                    int m, double* U, int64_t ldU, hipStream_t st);
 void launch_fit(const double* A, int s, const int* perm, int m, const double* ts, double t0, double t1, int qcap,
                 double fit_tol, double* Pi, int ldPi, double* work, double* info, hipStream_t st);
+// piecewise-cubic p(t): not-a-knot spline coefficients of the m rows (work: 3 s m doubles)
+void launch_spline(const double* A, int s, const int* perm, int m, const double* ts, double* Pw, double* work,
+                   hipStream_t st);
+void launch_spline_reset(ExpmDev* e, int nprob, hipStream_t st);
 
 // column-pivoted Gram-Schmidt range finder of the shifted samples (compress.hip):
 // Q (n x k, ld n) orthonormal, R = Q^T G (k x s, ld kcap); k and the squared norms of G

@@ -1041,6 +1041,21 @@ void launch_block_commit(ProbDev* d, int nprob, int grid_x, int j, int mixed, hi
 // Taylor polynomial of degree 16 (Paterson-Stockmeyer with A^2, A^3, A^4) on
 // A = (delta / 2^s) Ht, then s squarings; y = exp(delta Ht) b.
 // ------------------------------------------------------------------------------------
+// Taylor coefficient z_j (entry idx = j m + a) of the piecewise-cubic source at offset
+// pdelta into piece `piece`: z_j = sum_{k >= j} C(k, j) c_k pdelta^(k - j)
+__device__ __forceinline__ double spline_z(const ExpmDev& e, int idx) {
+  const int j = idx / e.m, a = idx - j * e.m;
+  const double* c = e.Pw + (int64_t)e.piece * 4 * e.m + a;
+  const double d = e.pdelta;
+  const double c0 = c[0], c1 = c[e.m], c2 = c[2 * e.m], c3 = c[3 * e.m];
+  switch (j) {
+    case 0: return c0 + d * (c1 + d * (c2 + d * c3));
+    case 1: return c1 + d * (2.0 * c2 + 3.0 * d * c3);
+    case 2: return c2 + 3.0 * d * c3;
+    default: return c3;
+  }
+}
+
 __global__ void k_build_aug(const ExpmDev* __restrict__ E) {
   const ExpmDev e = E[blockIdx.y];  // by value: uniform, loaded once
   if (!e.active) return;
@@ -1059,9 +1074,17 @@ __global__ void k_build_aug(const ExpmDev* __restrict__ E) {
         v = e.H[(int64_t)r + e.ldH * c];
     } else if (r < bw && c >= lbw) {
       const int k = c - lbw;
-      for (int cc = 0; cc < e.m; ++cc) v += e.R0[r * bw + cc] * e.Pi[cc + (int64_t)e.ldPi * k];
+      if (e.spline)  // the source U z_0 in Krylov coordinates: E_1 R0[:, :m]
+        v = k < e.m ? e.R0[r * bw + k] : 0.0;
+      else
+        for (int cc = 0; cc < e.m; ++cc) v += e.R0[r * bw + cc] * e.Pi[cc + (int64_t)e.ldPi * k];
     } else if (r >= lbw && c >= lbw) {
-      v = e.kscale * e.Dm[(r - lbw) * e.qmax + (c - lbw)];
+      if (e.spline) {  // z_j' = (j + 1) z_{j+1}, blocks of m
+        const int rr = r - lbw, cc = c - lbw;
+        v = (cc == rr + e.m && rr < 3 * e.m) ? (double)(rr / e.m + 1) : 0.0;
+      } else {
+        v = e.kscale * e.Dm[(r - lbw) * e.qmax + (c - lbw)];
+      }
     }
     e.Ht[idx] = v;
   }
@@ -1069,9 +1092,21 @@ __global__ void k_build_aug(const ExpmDev* __restrict__ E) {
     const int r = (int)idx;
     double v = 0.0;
     if (r < bw) v = e.with_x ? e.R0[r * bw + e.m] : 0.0;
-    else if (r >= lbw) v = e.w[r - lbw];
+    else if (r >= lbw) v = e.spline ? spline_z(e, r - lbw) : e.w[r - lbw];
     e.b[r] = v;
   }
+}
+
+// piecewise source: the z part of the held solution ycur restarts from the Taylor
+// coefficients of the current piece at the current time (problems with zreset set)
+__global__ void k_spline_reset(const ExpmDev* __restrict__ E) {
+  const ExpmDev e = E[blockIdx.y];  // by value: uniform, loaded once
+  if (!e.zreset) return;
+  for (int i = threadIdx.x; i < 4 * e.m; i += blockDim.x) e.ycur[e.lbw + i] = spline_z(e, i);
+}
+
+void launch_spline_reset(ExpmDev* e, int nprob, hipStream_t st) {
+  hipLaunchKernelGGL(k_spline_reset, dim3(1, (unsigned)nprob), dim3(128), 0, st, e);
 }
 
 void launch_build_aug(ExpmDev* e, int nprob, int64_t maxNN, hipStream_t st) {
@@ -1625,6 +1660,76 @@ void launch_fit(const double* A, int s, const int* perm, int m, const double* ts
                 double fit_tol, double* Pi, int ldPi, double* work, double* info, hipStream_t st) {
   hipLaunchKernelGGL(k_fit, dim3(1), dim3(256), 0, st, A, s, perm, m, ts, t0, t1, qcap, fit_tol, Pi, ldPi, work,
                      info);
+}
+
+// S4, piecewise: the not-a-knot cubic spline through each coefficient row (one thread per
+// row).  Unknowns are the second derivatives M_i at the samples; the not-a-knot
+// conditions (third derivative continuous at the second and the second-to-last sample)
+// give M_0 = (1 + h0/h1) M_1 - (h0/h1) M_2 and the mirror for M_{s-1}, which turn the
+// first and last interior continuity equations into rows of a diagonally dominant
+// tridiagonal system for M_1..M_{s-2}, solved by elimination without pivoting.  Three
+// samples give one parabola, two a straight line.  Output: Pw[(i 4 + k) m + a] = c_k of
+// piece i of row a, p(t) = sum_k c_k (t - t_i)^k on [t_i, t_{i+1}].
+// work: 3 s doubles per row.
+__global__ void k_spline(const double* A, int s, const int* perm, int m, const double* ts, double* Pw,
+                         double* work) {
+  const int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= m) return;
+  const double* y = A + (int64_t)perm[a] * s;
+  double* M = work + (int64_t)a * 3 * s;
+  double* cp = M + s;  // eliminated super-diagonal
+  double* dp = cp + s; // eliminated right-hand side
+  auto hh = [&](int i) { return ts[i + 1] - ts[i]; };
+  auto slope = [&](int i) { return (y[i + 1] - y[i]) / hh(i); };
+  for (int i = 0; i < s; ++i) M[i] = 0.0;
+  if (s == 3) {
+    const double dd = (slope(1) - slope(0)) / (ts[2] - ts[0]);
+    M[0] = M[1] = M[2] = 2.0 * dd;
+  } else if (s >= 4) {
+    // rows i = 1..s-2 of the reduced system: sub[i] M_{i-1} + dia[i] M_i + sup[i] M_{i+1} = rhs[i]
+    for (int i = 1; i <= s - 2; ++i) {
+      const double h0 = hh(i - 1), h1 = hh(i);
+      double sub = h0, dia = 2.0 * (h0 + h1), sup = h1;
+      const double rhs = 6.0 * (slope(i) - slope(i - 1));
+      if (i == 1) {  // M_0 eliminated
+        dia += h0 + h0 * h0 / h1;
+        sup -= h0 * h0 / h1;
+        sub = 0.0;
+      }
+      if (i == s - 2) {  // M_{s-1} eliminated
+        dia += h1 + h1 * h1 / h0;
+        sub -= h1 * h1 / h0;
+        sup = 0.0;
+      }
+      if (i == 1) {
+        cp[i] = sup / dia;
+        dp[i] = rhs / dia;
+      } else {
+        const double den = dia - sub * cp[i - 1];
+        cp[i] = sup / den;
+        dp[i] = (rhs - sub * dp[i - 1]) / den;
+      }
+    }
+    M[s - 2] = dp[s - 2];
+    for (int i = s - 3; i >= 1; --i) M[i] = dp[i] - cp[i] * M[i + 1];
+    const double g0 = hh(0) / hh(1), g1 = hh(s - 2) / hh(s - 3);
+    M[0] = (1.0 + g0) * M[1] - g0 * M[2];
+    M[s - 1] = (1.0 + g1) * M[s - 2] - g1 * M[s - 3];
+  }
+  for (int i = 0; i + 1 < s; ++i) {
+    const double h = hh(i);
+    double* c = Pw + (int64_t)i * 4 * m + a;
+    c[0] = y[i];
+    c[m] = slope(i) - h * (2.0 * M[i] + M[i + 1]) / 6.0;
+    c[2 * m] = 0.5 * M[i];
+    c[3 * m] = (M[i + 1] - M[i]) / (6.0 * h);
+  }
+}
+
+void launch_spline(const double* A, int s, const int* perm, int m, const double* ts, double* Pw, double* work,
+                   hipStream_t st) {
+  if (m <= 0 || s < 2) return;
+  hipLaunchKernelGGL(k_spline, dim3(1), dim3(64), 0, st, A, s, perm, m, ts, Pw, work);
 }
 
 // ------------------------------------------------------------------------------------

@@ -49,6 +49,13 @@ struct pe_ctx {
   std::string err;
   char* arena = nullptr;
   size_t arena_cap = 0;
+  // buffers that live across the calls using the arena: the compressed sources of
+  // pe_solve_batch, the iterates and window sources of pe_wr_burgers; grown on demand and
+  // kept like the arena
+  char* keep = nullptr;
+  size_t keep_cap = 0;
+  char* keep_wr = nullptr;
+  size_t keep_wr_cap = 0;
   char* pinned = nullptr;
   size_t pinned_cap = 0;
   // kernel timing (pe_profile_enable / pe_profile_read)
@@ -206,6 +213,22 @@ pe_status ensure_arena(pe_ctx* ctx, size_t bytes) {
   hipError_t e = hipMalloc((void**)&ctx->arena, cap);
   if (e != hipSuccess) return pe_fail(ctx, PE_ERR_OOM, "device workspace allocation failed", e);
   ctx->arena_cap = cap;
+  return PE_OK;
+}
+
+// one of the context's kept device buffers (pe_ctx::keep, keep_wr), at least `bytes`
+pe_status ensure_kept(pe_ctx* ctx, char*& buf, size_t& cap, size_t bytes) {
+  if (bytes <= cap) return PE_OK;
+  if (buf) {
+    hipDeviceSynchronize();
+    hipFree(buf);
+    buf = nullptr;
+    cap = 0;
+  }
+  const size_t c = bytes + bytes / 4 + (1 << 20);
+  hipError_t e = hipMalloc((void**)&buf, c);
+  if (e != hipSuccess) return pe_fail(ctx, PE_ERR_OOM, "device workspace allocation failed", e);
+  cap = c;
   return PE_OK;
 }
 
@@ -446,6 +469,8 @@ pe_status validate_problem(pe_ctx* ctx, const pe_problem& p, bool need_samples) 
   if (p.prec != PE_FP64 && p.prec != PE_MIXED) return pe_fail(ctx, PE_ERR_ARG, "unknown precision");
   if (p.krylov != PE_KRYLOV_POLY && p.krylov != PE_KRYLOV_SAI) return pe_fail(ctx, PE_ERR_ARG, "unknown Krylov space");
   if (!(p.sai_shift >= 0.0) || !std::isfinite(p.sai_shift)) return pe_fail(ctx, PE_ERR_ARG, "bad sai_shift");
+  if (p.source_fit != PE_FIT_CHEBYSHEV && p.source_fit != PE_FIT_SPLINE)
+    return pe_fail(ctx, PE_ERR_ARG, "unknown source fit");
   if (need_samples) {
     if (p.s < 1 || !p.t_samples || !p.G) return pe_fail(ctx, PE_ERR_ARG, "missing source samples");
     if (p.ldG < p.op.n) return pe_fail(ctx, PE_ERR_ARG, "ldG < n");
@@ -555,7 +580,8 @@ pe_status compress_one(pe_ctx* ctx, const pe_problem& p, double* U, int64_t ldU,
   const size_t o_perm = cv.take<int>(std::max(1, kcap));
   const size_t o_info = cv.take<int>(4);
   const size_t o_ts = cv.take<double>(s);
-  const size_t o_fw = cv.take<double>((size_t)s * qcap + (size_t)qcap * qcap + (size_t)32 * qcap + (size_t)32 * s);
+  const size_t o_fw = cv.take<double>(std::max((size_t)s * qcap + (size_t)qcap * qcap + (size_t)32 * qcap + (size_t)32 * s,
+                                               (size_t)3 * 32 * s));
   const size_t o_fi = cv.take<double>(4);
   const size_t o_flag = cv.take<int>(4);
   const size_t host_need = std::max(sizeof(double) * (4 * (size_t)std::max(1, kcap) + 64), pe::cp_state_bytes());
@@ -656,8 +682,15 @@ pe_status compress_one(pe_ctx* ctx, const pe_problem& p, double* U, int64_t ldU,
   if (m == 0) return PE_OK;
   // U = Q J[:, perm[0:m]]  (Q column-major: blocks of width 1)
   pe::launch_form_u(Qc, 1, n, (int*)(base + o_sel), r, J, (int*)(base + o_perm), m, U, ldU, st);
-  // S4: Chebyshev fit of C = Sigma Z^T rows over the samples
+  // S4: Chebyshev fit (or cubic spline) of C = Sigma Z^T rows over the samples
   HCK(hipMemcpyAsync(base + o_ts, p.t_samples, sizeof(double) * s, hipMemcpyHostToDevice, st));
+  if (p.source_fit == PE_FIT_SPLINE) {
+    pe::launch_spline(A, s, (int*)(base + o_perm), m, (double*)(base + o_ts), Pi, (double*)(base + o_fw), st);
+    HCK(hipStreamSynchronize(st));
+    res.q = 4;
+    res.fit_resid = 0.0;
+    return PE_OK;
+  }
   pe::launch_fit(A, s, (int*)(base + o_perm), m, (double*)(base + o_ts), p.t0, p.t1, qcap, p.fit_tol, Pi, ldPi,
                  (double*)(base + o_fw), (double*)(base + o_fi), st);
   HCK(hipMemcpyAsync(hp, base + o_fi, sizeof(double) * 3, hipMemcpyDeviceToHost, st));
@@ -696,6 +729,8 @@ struct HostState {
   // current space is held) are reached by one matrix-vector product from the last one
   double prop_dt = 0.0;
   bool prop_now = false;
+  // piecewise-cubic source: the spline piece holding tau; every sample time is a target
+  int piece = 0;
 };
 
 pe_status march_batch(pe_ctx* ctx, const pe_problem* probs, const int* idx, int nb_prob, const double* const* Ul,
@@ -855,6 +890,8 @@ pe_status march_batch(pe_ctx* ctx, const pe_problem* probs, const int* idx, int 
     e.Dm = (double*)(base + o_Dm);
     e.qmax = qmax_all;
     e.kscale = 2.0 / (p.t1 - p.t0);
+    e.spline = (p.source_fit == PE_FIT_SPLINE && ml[ii] > 0) ? 1 : 0;
+    e.Pw = Pil[ii];
   }
   std::vector<TriDev> ht(sai ? nb_prob : 0);
   TriDev* tdd = (TriDev*)(base + o_td);
@@ -894,9 +931,21 @@ pe_status march_batch(pe_ctx* ctx, const pe_problem* probs, const int* idx, int 
   int guard = 0;
   const int trace = env_int("PARAEXP_TRACE", 0);
   const int max_cycles = env_int("PARAEXP_MAX_CYCLES", 0);
+  // next restart target of problem ii: the next output, the window end while the source
+  // acts, and with a spline source the end of the piece holding tau (a sample time)
+  auto target_of = [&](int ii) -> double {
+    const pe_problem& p = probs[idx[ii]];
+    HostState& h = hs[ii];
+    double tg = h.src ? std::min(p.t_out[h.k], p.t1) : p.t_out[h.k];
+    if (h.src && he[ii].spline) {
+      while (h.piece + 1 <= p.s - 2 && p.t_samples[h.piece + 1] <= h.tau) ++h.piece;
+      tg = std::min(tg, p.t_samples[h.piece + 1]);
+    }
+    return tg;
+  };
   while (true) {
     // ---- plan the cycle
-    int nact = 0, nreuse = 0, lmax = 0, tree = 0, gx_p = 0, gx_u = 0, mb_N = 1;
+    int nact = 0, nreuse = 0, nzreset = 0, lmax = 0, tree = 0, gx_p = 0, gx_u = 0, mb_N = 1;
     size_t smem_p = 0, smem_u = 0;
     int64_t maxNN = 1;
     for (int ii = 0; ii < nb_prob; ++ii) {
@@ -909,6 +958,7 @@ pe_status march_batch(pe_ctx* ctx, const pe_problem* probs, const int* idx, int 
       h.reuse_now = false;
       h.prop_now = false;
       he[ii].prop = 0;
+      he[ii].zreset = 0;
       if (h.done) continue;
       const int m = ml[ii];
       h.src = (m > 0) && (h.tau < p.t1);
@@ -917,21 +967,33 @@ pe_status march_batch(pe_ctx* ctx, const pe_problem* probs, const int* idx, int 
         h.done = true;
         continue;
       }
-      h.target = h.src ? std::min(p.t_out[h.k], p.t1) : p.t_out[h.k];
+      h.target = target_of(ii);
       // The exponential of the Chebyshev generator over a step re-expands the basis at a
       // shift of c = 2 step / (t1 - t0) in x, with coefficients growing like
       // (1 + sqrt(2c))^q; rounding in the projected exponential grows with them.  Steps
       // (offsets from the cycle start) are capped so that the growth stays below kGrowthCap.
-      const double cap = (h.src && ql[ii] > 0)
+      const bool spl = he[ii].spline && h.src;
+      const double cap = (h.src && ql[ii] > 0 && !spl)
                              ? 0.25 * std::pow(std::pow(kGrowthCap, 1.0 / ql[ii]) - 1.0, 2) * (p.t1 - p.t0)
                              : HUGE_VAL;
+      if (spl) {  // the piece holding tau, and tau's offset into it
+        he[ii].piece = h.piece;
+        he[ii].pdelta = h.tau - p.t_samples[h.piece];
+      }
       if (h.reuse) {
+        // spline pieces: each pass restarts from the held solution at tau (its polynomial
+        // part reset to the current piece), so offsets count from tau
+        if (spl) h.tau_c = h.tau;
         const double off = std::min(h.target - h.tau_c, cap);
         if (off > h.tau - h.tau_c) {  // the same space, evaluated further out
           h.dtry = off;
           h.reuse_now = true;
           h.prop_now = h.prop_dt > 0.0 && off == h.target - h.tau_c &&
                        std::fabs((h.target - h.tau) - h.prop_dt) <= kPropRel * h.prop_dt;
+          if (spl) {
+            he[ii].zreset = 1;
+            ++nzreset;
+          }
           ++nreuse;
           mb_N = std::max(mb_N, h.N);
           maxNN = std::max<int64_t>(maxNN, (int64_t)h.N * h.N);
@@ -971,7 +1033,7 @@ pe_status march_batch(pe_ctx* ctx, const pe_problem* probs, const int* idx, int 
       e.lbw = d.l * h.bw;
       e.ldH = d.ldH;
       e.R0 = d.Rf + 2 * (size_t)h.bw * h.bw;
-      if (h.src && ql[ii] > 0) {
+      if (h.src && ql[ii] > 0 && !he[ii].spline) {
         chebyshev_values((2.0 * h.tau - p.t0 - p.t1) / (p.t1 - p.t0), ql[ii], wv[ii].data());
         HCK(hipMemcpyAsync((void*)e.w, wv[ii].data(), sizeof(double) * ql[ii], hipMemcpyHostToDevice, st));
       }
@@ -1065,6 +1127,18 @@ pe_status march_batch(pe_ctx* ctx, const pe_problem* probs, const int* idx, int 
         h.pending = false;
         h.stop = true;
         h.flags |= PE_FLAG_NOT_CONVERGED;
+      }
+    }
+    if (nzreset > 0) {
+      // spline pieces evaluated from the held solution: its polynomial part restarts from
+      // the current piece, and the trial starts from it
+      HCK(hipMemcpyAsync(ed, he.data(), sizeof(ExpmDev) * nb_prob, hipMemcpyHostToDevice, st));
+      pe::launch_spline_reset(ed, nb_prob, st);
+      for (int ii = 0; ii < nb_prob; ++ii) {
+        if (!he[ii].zreset) continue;
+        if (!hs[ii].prop_now)
+          HCK(hipMemcpyAsync(he[ii].b, he[ii].ycur, sizeof(double) * hs[ii].N, hipMemcpyDeviceToDevice, st));
+        he[ii].zreset = 0;
       }
     }
     const int tiles = (mb_N + 31) / 32;
@@ -1210,7 +1284,7 @@ pe_status march_batch(pe_ctx* ctx, const pe_problem* probs, const int* idx, int 
       if (!h.reuse_now) ++h.cycles;
       // landed on an output inside the source interval (or past it): try the next output
       // from the same space
-      h.reuse = d.outcol != nullptr && !(h.src && h.target >= p.t1);
+      h.reuse = landed && !(h.src && h.target >= p.t1);
       if (d.outcol) {
         const double tk = p.t_out[h.k];
         ++h.k;
@@ -1229,7 +1303,7 @@ pe_status march_batch(pe_ctx* ctx, const pe_problem* probs, const int* idx, int 
         HCK(hipMemcpyAsync(e.ycur, d.yacc, sizeof(double) * h.N, hipMemcpyDeviceToDevice, st));
         if (!h.prop_now) {
           h.prop_dt = 0.0;
-          const double next = (h.src ? std::min(p.t_out[h.k], p.t1) : p.t_out[h.k]) - h.tau;
+          const double next = target_of(ii) - h.tau;
           if (h.level >= e.nsq - 1 && std::fabs(next - h.dtry) <= kPropRel * h.dtry) {
             HCK(hipMemcpyAsync(e.Eprop, (h.level & 1) ? e.P : e.T, sizeof(double) * h.N * h.N,
                                hipMemcpyDeviceToDevice, st));
@@ -1315,6 +1389,8 @@ pe_status pe_destroy(pe_ctx* ctx) {
   hipSetDevice(ctx->device);
   hipDeviceSynchronize();
   if (ctx->arena) hipFree(ctx->arena);
+  if (ctx->keep) hipFree(ctx->keep);
+  if (ctx->keep_wr) hipFree(ctx->keep_wr);
   if (ctx->pinned) hipHostFree(ctx->pinned);
   for (hipEvent_t e : ctx->ev) hipEventDestroy(e);
   delete ctx;
@@ -1414,6 +1490,8 @@ pe_status pe_expaction_batch(pe_ctx* ctx, const pe_problem* probs, const double*
     if (m[i] < 0 || m[i] > 31 || q[i] < 0 || q[i] > 64 || (m[i] > 0 && (q[i] < 1 || !U[i] || !Pi[i])))
       return pe_fail(ctx, PE_ERR_ARG, "pe_expaction_batch: bad m/q/U/Pi");
     if (probs[i].op.n < m[i] + 1) return pe_fail(ctx, PE_ERR_ARG, "n too small for the block width");
+    if (probs[i].source_fit != PE_FIT_CHEBYSHEV && m[i] > 0)
+      return pe_fail(ctx, PE_ERR_UNSUPPORTED, "pe_expaction_batch takes Chebyshev coefficients only");
   }
   HCK(hipSetDevice(ctx->device));
   hipStream_t st = (hipStream_t)stream;
@@ -1453,10 +1531,14 @@ pe_status pe_solve_batch(pe_ctx* ctx, const pe_problem* probs, int32_t nprob, pe
     tot += sizeof(double) * (size_t)probs[i].op.n * std::max(1, probs[i].rank_max);
     tot = (tot + 255) & ~(size_t)255;
     offPi[i] = tot;
-    tot += sizeof(double) * (size_t)std::max(1, probs[i].rank_max) * probs[i].q_max;
+    tot += sizeof(double) * (size_t)std::max(1, probs[i].rank_max) *
+           (probs[i].source_fit == PE_FIT_SPLINE ? 4 * (size_t)std::max(1, probs[i].s - 1) : (size_t)probs[i].q_max);
   }
-  char* src = nullptr;
-  HCK(hipMalloc((void**)&src, std::max<size_t>(tot, 256)));
+  {
+    const pe_status ks = ensure_kept(ctx, ctx->keep, ctx->keep_cap, std::max<size_t>(tot, 256));
+    if (ks != PE_OK) return ks;
+  }
+  char* src = ctx->keep;
   std::vector<const double*> Ul(nprob), Pil(nprob);
   std::vector<int> ld(nprob), mm(nprob), qq(nprob);
   pe_status s = PE_OK;
@@ -1471,9 +1553,11 @@ pe_status pe_solve_batch(pe_ctx* ctx, const pe_problem* probs, int32_t nprob, pe
     Pil[i] = Pi;
     ld[i] = std::max(1, probs[i].rank_max);
     mm[i] = co.m;
-    qq[i] = co.m > 0 ? co.q : 0;
+    // the march's polynomial part: q Chebyshev terms, or the 4 m Taylor coefficients of
+    // the spline pieces
+    qq[i] = co.m > 0 ? (probs[i].source_fit == PE_FIT_SPLINE ? 4 * co.m : co.q) : 0;
     reports[i].rank = co.m;
-    reports[i].q = qq[i];
+    reports[i].q = co.q;
     reports[i].flags = co.flags;
     reports[i].fit_resid = co.fit_resid;
     reports[i].svd_tail = co.svd_tail;
@@ -1482,7 +1566,6 @@ pe_status pe_solve_batch(pe_ctx* ctx, const pe_problem* probs, int32_t nprob, pe
   if (s == PE_OK) s = march_all(ctx, probs, nprob, Ul.data(), Pil.data(), ld.data(), mm.data(), qq.data(), reports, st);
   hipStreamSynchronize(st);
   prof_collect(ctx);
-  hipFree(src);
   if (s != PE_OK) return s;
   HCK(hipGetLastError());
   return PE_OK;
@@ -1521,7 +1604,11 @@ pe_status pe_wr_burgers(pe_ctx* ctx, const pe_wr_problem* wr, pe_report* reports
   const int nblk = 256;
   double* base = nullptr;
   const size_t tot = sizeof(double) * (4 * blkn + 3 * (size_t)n * P + n + 2 * nblk);
-  if (hipMalloc((void**)&base, tot) != hipSuccess) return pe_fail(ctx, PE_ERR_OOM, "pe_wr_burgers: workspace");
+  {
+    const pe_status ks = ensure_kept(ctx, ctx->keep_wr, ctx->keep_wr_cap, tot);
+    if (ks != PE_OK) return ks;
+  }
+  base = (double*)ctx->keep_wr;
   double* Uk = base;
   double* Vown = Uk + blkn;
   double* Cc = Vown + blkn;
@@ -1580,6 +1667,7 @@ pe_status pe_wr_burgers(pe_ctx* ctx, const pe_wr_problem* wr, pe_report* reports
         q.prec = w.prec;
         q.krylov = w.krylov;
         q.sai_shift = w.sai_shift;
+        q.source_fit = w.source_fit;
       }
       {
         const pe_status sb = pe_solve_batch(ctx, pr.data(), P, reports, stream);
@@ -1615,6 +1703,7 @@ pe_status pe_wr_burgers(pe_ctx* ctx, const pe_wr_problem* wr, pe_report* reports
         q.prec = w.prec;
         q.krylov = w.krylov;
         q.sai_shift = w.sai_shift;
+        q.source_fit = w.source_fit;
         const double* nullp = nullptr;
         const int32_t zero = 0;
         pe_report rep;
@@ -1651,7 +1740,6 @@ pe_status pe_wr_burgers(pe_ctx* ctx, const pe_wr_problem* wr, pe_report* reports
       fail(pe_fail(ctx, PE_ERR_DEVICE, "pe_wr_burgers: copy u_final"));
   } while (false);
   hipStreamSynchronize(st);
-  hipFree(base);
   if (res != PE_OK) return res;
   HCK(hipGetLastError());
   return PE_OK;
@@ -1685,14 +1773,15 @@ pe_status pe_workspace_query(pe_ctx* ctx, const pe_problem* probs, int32_t nprob
     pe_status s = compress_one(c, p, nullptr, p.op.n, nullptr, std::max(1, p.rank_max), co, nullptr);
     if (s != kQueryStop) return s == PE_OK ? pe_fail(c, PE_ERR_DEVICE, "query did not stop") : s;
     arena = std::max(arena, c->query_bytes);
-    // compressed sources, allocated per call (as in pe_solve_batch)
+    // compressed sources (the context's kept buffer in pe_solve_batch)
     src = (src + 255) & ~(size_t)255;
     src += sizeof(double) * (size_t)p.op.n * std::max(1, p.rank_max);
     src = (src + 255) & ~(size_t)255;
-    src += sizeof(double) * (size_t)std::max(1, p.rank_max) * p.q_max;
+    const bool spl = p.source_fit == PE_FIT_SPLINE;
+    src += sizeof(double) * (size_t)std::max(1, p.rank_max) * (spl ? 4 * (size_t)std::max(1, p.s - 1) : p.q_max);
     // the march at the largest rank and polynomial order the problem allows
     ml[i] = std::min(p.rank_max, p.s);
-    ql[i] = std::min(p.q_max, p.s);
+    ql[i] = spl ? 4 * ml[i] : std::min(p.q_max, p.s);
     // every cycle geometry the march can meet (rank m' <= ml, block width m' in the
     // zero-state cycle, m' + 1 after it, 1 past the window) must fit its workspace
     const int l = p.krylov_steps;

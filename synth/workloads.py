@@ -48,6 +48,7 @@ class Problem:
     name: str = ""
     krylov: int = 0             # 0: polynomial Krylov space, 1: shift-and-invert
     sai_shift: float = 0.0      # shift-and-invert: gamma / cycle step (0: default)
+    source_fit: int = 0         # p(t): 0 one Chebyshev least-squares polynomial, 1 cubic spline
 
     @property
     def s(self) -> int:
@@ -82,6 +83,7 @@ class BurgersProblem:
     krylov: int = 0
     sai_shift: float = 0.0
     forcing: Optional[np.ndarray] = None   # (n, P*s) external source samples, window-major
+    source_fit: int = 0                    # p(t): 0 Chebyshev least squares, 1 cubic spline
 
     def window_times(self, j: int) -> np.ndarray:
         t0 = self.T * j / self.P

@@ -461,3 +461,36 @@ def test_wr_with_the_manufactured_sawtooth_source_reaches_a_second_order_floor()
         ex = np.stack([exact(t) for t in bp.window_times(0)], axis=1)
         floors.append(np.linalg.norm(U - ex) / np.linalg.norm(ex))
     assert 3.6 < floors[0] / floors[1] < 4.5, floors
+
+
+def test_cubic_spline_fit_matches_scipy():
+    # the piecewise-cubic p(t) of Sec. 3 ("piecewise cubic polynomials"), read as the
+    # not-a-knot interpolating spline: same coefficients as scipy's CubicSpline
+    from scipy.interpolate import CubicSpline
+    from oracle.compress import fit_cubic_spline
+    rng = np.random.default_rng(11)
+    for s in (3, 4, 5, 9, 64):
+        t = np.sort(rng.uniform(0.0, 1.0, s))
+        t[0], t[-1] = 0.0, 1.0
+        C = rng.standard_normal((4, s))
+        Cp = fit_cubic_spline(C, t)
+        ref = CubicSpline(t, C.T, bc_type="not-a-knot").c   # (4, s-1, m), highest power first
+        for k in range(4):  # relative to the largest coefficient of that power, or to 1
+            scale = max(np.abs(ref[3 - k]).max(), 1.0)
+            assert np.abs(Cp[:, k, :] - ref[3 - k]).max() <= 1e-12 * scale, (s, k)
+    # two samples: the straight line
+    Cp = fit_cubic_spline(np.array([[1.0, 3.0]]), np.array([0.0, 0.5]))
+    assert np.allclose(Cp[0, :, 0], [1.0, 4.0, 0.0, 0.0])
+
+
+def test_spline_source_of_a_cubic_in_time_equals_the_polynomial_route():
+    # a source that is cubic in time is reproduced exactly by the spline, so the piecewise
+    # march (one segment per piece, Taylor-coefficient state) equals the single
+    # Chebyshev-polynomial march; dense and spectral routes agree on the pieces
+    p = synth.random_ade_problem(5, 64, modes=3, deg=3, s=12, krylov_steps=12, n_out=5)
+    r_cheb, _ = oracle.solve_window(p, "dense")
+    p.source_fit = 1
+    r_dense, _ = oracle.solve_window(p, "dense")
+    r_spec, _ = oracle.solve_window(p, "spectral")
+    assert np.linalg.norm(r_dense - r_cheb) <= 1e-12 * np.linalg.norm(r_cheb)
+    assert np.linalg.norm(r_spec - r_dense) <= 1e-12 * np.linalg.norm(r_dense)
