@@ -271,13 +271,36 @@ typedef struct {
 pe_status pe_wr_burgers(pe_ctx* ctx, const pe_wr_problem* wr, pe_report* reports, double* increments,
                         void* stream);
 
+/* Tile autotuning of the block orthogonalisation kernels (the batched pipeline of
+ * Sec. 2.2: every window's and instance's block Arnoldi, eq. 2.4, runs on them).  For each
+ * block width a march of the given problems can meet (rank_max + 1, rank_max, 1) and each
+ * precision, times 12 block Arnoldi steps on a seeded random block of the problem's size
+ * for every admissible pair (rows per update chunk in {64, 128, 256, 512}, rows per
+ * projection chunk in {16, ..., 256} with rows x width <= 1024) and keeps the fastest in
+ * ctx.  The key is (ceil(log2 n), block width, precision): later calls on ctx with grids
+ * of the same power-of-two bucket use the choice; keys already in ctx are not re-timed.
+ * The choice changes only the partition of the rows into chunks (and so the rounding
+ * order of the reductions), never the method.
+ *   probs       host array of nprob; only op.n, rank_max and prec are read
+ *   cache_path  text file of lines "log2n width mixed rows_u rows_p", or NULL; read before
+ *               tuning (its entries are taken as tuned) and rewritten after with every
+ *               entry of ctx
+ *   tuned       host, or NULL: the number of keys timed by this call
+ * Uses the context workspace (grown on demand) and synchronises the stream.  Errors:
+ * PE_ERR_ARG for n < 64, rank_max outside [0, 31] or an unwritable cache file. */
+pe_status pe_autotune(pe_ctx* ctx, const pe_problem* probs, int32_t nprob, const char* cache_path,
+                      int32_t* tuned, void* stream);
+/* The tuning table of ctx: writes up to max_rows rows of five int32 (log2n, width, mixed,
+ * rows_u, rows_p) to rows (host, may be NULL) and returns the number of entries. */
+int32_t pe_autotune_table(const pe_ctx* ctx, int32_t* rows, int32_t max_rows);
+
 /* Kernel timing for roofline measurements.  Enables HIP-event timing, on the stream of
  * each call, of one kernel family: "block_update" (block Gram-Schmidt update + chunk QR
  * + TSQR combine) or "block_proj" (block projections) -- the first orthogonalisation
  * pass of every block Arnoldi step, which always runs in full -- or "stencil"
  * (pe_stencil_apply), or NULL to switch timing off.  Resets the accumulators.  Timing
- * adds two event records per timed launch; within a march only every 8th restart cycle
- * is timed (all of its block steps), which keeps the markers' cost small. */
+ * adds two event records per timed launch; within a march every restart cycle is timed
+ * (all of its block steps). */
 pe_status pe_profile_enable(pe_ctx* ctx, const char* family);
 /* Read and reset the accumulators: timed launches, their summed duration (ms), and the
  * algorithmic traffic (bytes, each datum read or written once per launch) and flops of

@@ -40,7 +40,7 @@ FLAG_FIT_CAPPED = 8
 EXPORTED = ["pe_create", "pe_destroy", "pe_last_error", "pe_version", "pe_stencil_apply", "pe_compress",
             "pe_compress_noalloc",
             "pe_expaction_batch", "pe_solve_batch", "pe_workspace_query", "pe_superpose", "pe_wr_burgers",
-            "pe_profile_enable", "pe_profile_read",
+            "pe_profile_enable", "pe_profile_read", "pe_autotune", "pe_autotune_table",
             # host-only decision rules (include/paraexp_policy.h)
             "pe_policy_step", "pe_policy_step_growth", "pe_policy_reorth_skip"]
 PE_STEP_ACCEPT = 0
@@ -180,6 +180,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.pe_wr_burgers.argtypes = [vp, ctypes.POINTER(PeWrProblem), ctypes.POINTER(PeReport),
                                   ctypes.POINTER(ctypes.c_double), vp]
     lib.pe_profile_enable.argtypes = [vp, ctypes.c_char_p]
+    lib.pe_autotune.argtypes = [vp, ctypes.POINTER(PeProblem), i32, ctypes.c_char_p, ctypes.POINTER(i32), vp]
+    lib.pe_autotune_table.argtypes = [vp, ctypes.POINTER(i32), i32]
+    lib.pe_autotune_table.restype = i32
     lib.pe_profile_read.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double),
                                     ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
     lib.pe_policy_step.argtypes = [ctypes.POINTER(PeStepTrial), ctypes.POINTER(PeStepDecision)]
@@ -190,7 +193,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.pe_policy_reorth_skip.restype = i32
     for name in ["pe_create", "pe_destroy", "pe_stencil_apply", "pe_compress", "pe_compress_noalloc",
                  "pe_expaction_batch",
-                 "pe_solve_batch", "pe_superpose", "pe_wr_burgers", "pe_profile_enable", "pe_profile_read"]:
+                 "pe_solve_batch", "pe_superpose", "pe_wr_burgers", "pe_profile_enable", "pe_profile_read",
+                 "pe_autotune"]:
         getattr(lib, name).restype = ctypes.c_int
     _LIB = lib
     return lib
@@ -459,6 +463,27 @@ class Context:
         reps = (PeReport * len(dps))()
         self._check(self.lib.pe_expaction_batch(self.h, arr, Uptr, Pptr, ms, qs, len(dps), reps, _stream_ptr()))
         return [d.out for d in dps], [r.as_dict() for r in reps]
+
+    # -- tile autotuning
+    def autotune(self, shapes, cache_path: Optional[str] = None) -> int:
+        """pe_autotune on (n, rank_max, precision) triples; returns the number of keys timed."""
+        shapes = list(shapes)
+        arr = (PeProblem * max(1, len(shapes)))()
+        for i, (n, rank_max, prec) in enumerate(shapes):
+            arr[i].op.n = int(n)
+            arr[i].rank_max = int(rank_max)
+            arr[i].prec = int(prec)
+        tuned = ctypes.c_int32()
+        self._check(self.lib.pe_autotune(self.h, arr, len(shapes), cache_path.encode() if cache_path else None,
+                                         ctypes.byref(tuned), _stream_ptr()))
+        return tuned.value
+
+    def autotune_table(self):
+        """The context's tiling choices: {(log2n, width, mixed): (rows_u, rows_p)}."""
+        k = self.lib.pe_autotune_table(self.h, None, 0)
+        rows = (ctypes.c_int32 * (5 * max(1, k)))()
+        self.lib.pe_autotune_table(self.h, rows, k)
+        return {(rows[5 * i], rows[5 * i + 1], rows[5 * i + 2]): (rows[5 * i + 3], rows[5 * i + 4]) for i in range(k)}
 
     # -- kernel timing
     def profile_enable(self, family: Optional[str]):

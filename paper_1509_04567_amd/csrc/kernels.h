@@ -81,6 +81,7 @@ void launch_project(ProbDev* d, ExpmDev* e, int nprob, int64_t maxn, int max_lbw
 // compression helpers (single problem)
 void launch_row_norms(const double* R, int64_t ldR, int rows, int cols, double* rn, hipStream_t st);
 void launch_vec_norm(const double* x, int64_t n, double* out, hipStream_t st);
+void launch_fill_hash(double* x, int64_t n, uint64_t seed, hipStream_t st);
 void launch_jacobi_svd(const double* R, int64_t ldR, const int* sel, int s, int r, double* A, double* J,
                        double* sig, int* perm, int* info, hipStream_t st);
 void launch_form_u(const double* Q, int bwc, int64_t n, const int* sel, int r, const double* J, const int* perm,

@@ -1438,6 +1438,22 @@ __global__ __launch_bounds__(1024) void k_vec_norm(const double* __restrict__ x,
   if (threadIdx.x == 0) *out = sqrt(s);
 }
 
+// deterministic pseudo-random fill in [-1/2, 1/2) (splitmix64 of the index), for tuning runs
+__global__ void k_fill_hash(double* x, int64_t n, uint64_t seed) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint64_t z = (uint64_t)i + seed * 0x9E3779B97F4A7C15ULL;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  z ^= z >> 31;
+  x[i] = (double)(z >> 11) * (1.0 / 9007199254740992.0) - 0.5;
+}
+
+void launch_fill_hash(double* x, int64_t n, uint64_t seed, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_fill_hash, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, x, n, seed);
+}
+
 void launch_vec_norm(const double* x, int64_t n, double* out, hipStream_t st) {
   hipLaunchKernelGGL(k_vec_norm, dim3(1), dim3(1024), 0, st, x, n, out);
 }

@@ -19,6 +19,8 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <fstream>
+#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -44,8 +46,22 @@ static hipError_t g_scratch_err[kMaxDevices] = {};
 // singular values, permutation and fit summary (kept in the context, sized at creation)
 constexpr size_t kScratchHostDoubles = 1024;
 
+// Block-kernel tiling chosen by pe_autotune for a (grid-size bucket, block width,
+// precision): rows per update chunk and per projection chunk.
+struct TuneKey {
+  int nlog2, bw, mixed;
+  bool operator<(const TuneKey& o) const {
+    return nlog2 != o.nlog2 ? nlog2 < o.nlog2 : (bw != o.bw ? bw < o.bw : mixed < o.mixed);
+  }
+};
+struct TuneVal {
+  int rows_u, rows_p;
+};
+using TuneTable = std::map<TuneKey, TuneVal>;
+
 struct pe_ctx {
   int device = 0;
+  TuneTable tune;  // pe_autotune's choices, consulted by every call on this context
   std::string err;
   char* arena = nullptr;
   size_t arena_cap = 0;
@@ -304,13 +320,59 @@ void choose_update_chunks(int64_t n, int bw, int& rows_u, int& comb_global, int&
   comb_global = 1;
 }
 
+// the tuning table of the call in progress (pe_autotune's choices on its context), or null
+thread_local const TuneTable* g_tune = nullptr;
+struct TuneScope {
+  explicit TuneScope(const pe_ctx* c) { g_tune = c ? &c->tune : nullptr; }
+  ~TuneScope() { g_tune = nullptr; }
+};
+int tune_nlog2(int64_t n) {
+  int k = 0;
+  while (((int64_t)1 << k) < n) ++k;
+  return k;
+}
+
+// update-chunk layout for a given chunk height: the combine placement as in
+// choose_update_chunks (registers or LDS, else two-level, else global); false when even
+// the staging does not fit
+bool update_chunks_for(int64_t n, int bw, int ru, int& comb_global, int& comb_tree) {
+  for (int mode = 0; mode < 3; ++mode) {
+    ProbDev d{};
+    d.bw = bw;
+    d.rows_u = ru;
+    d.Cu = (int)std::max<int64_t>(1, n / ru);
+    d.comb_tree = mode == 1;
+    d.comb_global = mode == 2;
+    if (update_smem(d) <= (size_t)pe::kUpdateLdsMax) {
+      comb_global = d.comb_global;
+      comb_tree = d.comb_tree;
+      return true;
+    }
+  }
+  return false;
+}
+
 void set_geometry(ProbDev& d, int64_t n, int bw) {
   d.bw = bw;
   choose_update_chunks(n, bw, d.rows_u, d.comb_global, d.comb_tree);
+  int tuned_p = 0;
+  if (g_tune) {
+    auto it = g_tune->find(TuneKey{tune_nlog2(n), bw, d.mixed});
+    if (it != g_tune->end()) {
+      int cg, ct;
+      if (it->second.rows_u >= 64 && it->second.rows_u <= 4096 && it->second.rows_u <= n &&
+          update_chunks_for(n, bw, it->second.rows_u, cg, ct)) {
+        d.rows_u = it->second.rows_u;
+        d.comb_global = cg;
+        d.comb_tree = ct;
+      }
+      if (it->second.rows_p >= 16 && it->second.rows_p * bw <= 1024) tuned_p = it->second.rows_p;
+    }
+  }
   d.rows_u_log2 = 0;
   while ((1 << d.rows_u_log2) < d.rows_u) ++d.rows_u_log2;
   d.Cu = (int)std::max<int64_t>(1, n / d.rows_u);
-  d.rows_p = rows_p_for(bw);  // rows_p * bw <= 1024: the projection kernel's staging assumes it
+  d.rows_p = tuned_p ? tuned_p : rows_p_for(bw);  // rows_p * bw <= 1024: the projection kernel's staging assumes it
   d.Cp = (int)((n + d.rows_p - 1) / d.rows_p);
 }
 
@@ -350,13 +412,15 @@ BlockCaps block_caps(int64_t n, int bwmax, int nbmax, int64_t H_rows, int64_t H_
   c.bwmax = bwmax;
   c.nbmax = nbmax;
   size_t cu_bw2 = 0, cp_bw2 = 0, ngmax = 0;
-  for (int bw = 1; bw <= bwmax; ++bw) {
-    ProbDev d{};
-    set_geometry(d, n, bw);
-    cu_bw2 = std::max(cu_bw2, (size_t)d.Cu * bw * bw);
-    cp_bw2 = std::max(cp_bw2, (size_t)d.Cp * bw * bw);
-    ngmax = std::max(ngmax, (size_t)(d.Cu + pe::kTreeFan - 1) / pe::kTreeFan);
-  }
+  for (int bw = 1; bw <= bwmax; ++bw)
+    for (int mixed = 0; mixed < 2; ++mixed) {  // tuned tilings may differ per precision
+      ProbDev d{};
+      d.mixed = mixed;
+      set_geometry(d, n, bw);
+      cu_bw2 = std::max(cu_bw2, (size_t)d.Cu * bw * bw);
+      cp_bw2 = std::max(cp_bw2, (size_t)d.Cp * bw * bw);
+      ngmax = std::max(ngmax, (size_t)(d.Cu + pe::kTreeFan - 1) / pe::kTreeFan);
+    }
   c.basis = (size_t)nbmax * n * bwmax;
   c.qloc = (size_t)n * bwmax;
   c.rloc = cu_bw2;
@@ -1482,6 +1546,7 @@ pe_status pe_compress_noalloc(pe_ctx* ctx, const pe_problem* prob, double* U, do
 pe_status pe_expaction_batch(pe_ctx* ctx, const pe_problem* probs, const double* const* U, const double* const* Pi,
                              const int32_t* m, const int32_t* q, int32_t nprob, pe_report* reports, void* stream) {
   if (!ctx) return PE_ERR_ARG;
+  TuneScope tune_scope(ctx);
   if (nprob < 0 || (nprob > 0 && (!probs || !m || !q || !reports || !U || !Pi)))
     return pe_fail(ctx, PE_ERR_ARG, "pe_expaction_batch: bad arguments");
   for (int i = 0; i < nprob; ++i) {
@@ -1514,6 +1579,7 @@ pe_status pe_expaction_batch(pe_ctx* ctx, const pe_problem* probs, const double*
 
 pe_status pe_solve_batch(pe_ctx* ctx, const pe_problem* probs, int32_t nprob, pe_report* reports, void* stream) {
   if (!ctx) return PE_ERR_ARG;
+  TuneScope tune_scope(ctx);
   if (nprob < 0 || (nprob > 0 && (!probs || !reports))) return pe_fail(ctx, PE_ERR_ARG, "pe_solve_batch: bad arguments");
   for (int i = 0; i < nprob; ++i) {
     pe_status s = validate_problem(ctx, probs[i], true);
@@ -1748,6 +1814,7 @@ pe_status pe_wr_burgers(pe_ctx* ctx, const pe_wr_problem* wr, pe_report* reports
 pe_status pe_workspace_query(pe_ctx* ctx, const pe_problem* probs, int32_t nprob, size_t* bytes) {
   pe_ctx local;  // host-only arithmetic: a null ctx is allowed
   pe_ctx* c = ctx ? ctx : &local;
+  TuneScope tune_scope(c);
   if (!bytes || nprob < 0 || (nprob > 0 && !probs)) return pe_fail(c, PE_ERR_ARG, "pe_workspace_query: bad arguments");
   *bytes = 0;
   struct QueryScope {
@@ -1790,6 +1857,7 @@ pe_status pe_workspace_query(pe_ctx* ctx, const pe_problem* probs, int32_t nprob
       const BlockCaps caps = block_caps(p.op.n, bwc, l + 1, (int64_t)(l + 1) * bwc, (int64_t)l * bwc);
       for (int bw : {1, std::max(1, mm), bwc}) {
         ProbDev d{};
+        d.mixed = p.prec == PE_MIXED ? 1 : 0;
         set_geometry(d, p.op.n, bw);
         if (!geometry_fits(d, caps, l + 1))
           return pe_fail(c, PE_ERR_UNSUPPORTED, "cycle geometry exceeds the workspace");
@@ -1817,6 +1885,159 @@ pe_status pe_workspace_query(pe_ctx* ctx, const pe_problem* probs, int32_t nprob
   }
   *bytes = arena + src;
   return PE_OK;
+}
+
+// ---- pe_autotune: block-kernel tiling per (grid bucket, block width, precision) ------
+// Times kTuneSteps block Arnoldi steps of the polynomial space on a random block for
+// every admissible (rows per update chunk, rows per projection chunk) and keeps the
+// fastest; the choice applies to grids of the same power-of-two bucket.
+constexpr int kTuneSteps = 12;
+
+pe_status tune_one(pe_ctx* ctx, int64_t n, int bw, int mixed, hipStream_t st, TuneVal& best) {
+  const int L = kTuneSteps;
+  // capacities for the smallest chunks (the most chunks of any candidate)
+  BlockCaps caps;
+  {
+    const TuneTable* saved = g_tune;
+    g_tune = nullptr;
+    caps = block_caps(n, bw, L + 1, (int64_t)(L + 1) * bw, (int64_t)L * bw);
+    g_tune = saved;
+  }
+  caps.rloc = std::max(caps.rloc, (size_t)std::max<int64_t>(1, n / 64) * bw * bw);
+  caps.part = std::max(caps.part, 2 * (size_t)(L + 1) * (size_t)((n + 15) / 16) * bw * bw);
+  caps.cnt = std::max(caps.cnt, 2 * (size_t)(L + 1) + 2 + (size_t)(n / 64 + pe::kTreeFan - 1) / pe::kTreeFan);
+  Carver cv;
+  const BlockOffsets bo = carve_block(cv, caps, mixed != 0);
+  const size_t o_u = cv.take<double>((size_t)n * bw);
+  const size_t o_pd = cv.take<ProbDev>(1);
+  pe_status stt = ensure_arena(ctx, cv.off);
+  if (stt != PE_OK) return stt;
+  char* base = ctx->arena;
+  double* Ux = (double*)(base + o_u);  // columns 0..bw-2: U, column bw-1: x
+  pe::launch_fill_hash(Ux, (int64_t)n * bw, 0x5eedULL + (uint64_t)bw, st);
+  ProbDev d{};
+  d.n = n;
+  d.per_point = 0;
+  d.c3[0] = 1.0;
+  d.c3[1] = -2.0;
+  d.c3[2] = 1.0;
+  bind_block(d, base, bo, mixed != 0, L + 1);
+  d.U = Ux;
+  d.m = bw - 1;
+  d.x = Ux + (size_t)n * (bw - 1);
+  d.xstate = (double*)d.x;
+  d.with_x = 1;
+  d.dep_tol = kDepTolArnoldi;
+  d.l = L;
+  d.ldH = (int64_t)(L + 1) * bw;
+  d.active = 1;
+  ProbDev* dd = (ProbDev*)(base + o_pd);
+  hipEvent_t e0, e1;
+  HCK(hipEventCreate(&e0));
+  HCK(hipEventCreate(&e1));
+  double best_ms = HUGE_VAL;
+  best = TuneVal{0, 0};
+  for (int ru : {64, 128, 256, 512})
+    for (int rp : {16, 32, 64, 128, 256}) {
+      int cg, ct;
+      if (ru > n || rp * bw > 1024 || rp > n || !update_chunks_for(n, bw, ru, cg, ct)) continue;
+      d.bw = bw;
+      d.rows_u = ru;
+      d.rows_u_log2 = 0;
+      while ((1 << d.rows_u_log2) < ru) ++d.rows_u_log2;
+      d.Cu = (int)std::max<int64_t>(1, n / ru);
+      d.comb_global = cg;
+      d.comb_tree = ct;
+      d.rows_p = rp;
+      d.Cp = (int)((n + rp - 1) / rp);
+      if (!geometry_fits(d, caps, L + 1)) continue;
+      HCK(hipMemsetAsync(d.cnt, 0, caps.cnt * sizeof(unsigned), st));
+      HCK(hipMemcpyAsync(dd, &d, sizeof(ProbDev), hipMemcpyHostToDevice, st));
+      const size_t smem_p = proj_smem(d), smem_u = update_smem(d);
+      double ms = HUGE_VAL;
+      for (int rep = 0; rep < 2; ++rep) {  // the first pass warms the caches
+        HCK(hipEventRecord(e0, st));
+        pe::launch_block_update(dd, 1, d.Cu, smem_u, 0, 0, 1, pe::MODE_INIT, mixed, ct, st);
+        for (int j = 0; j < L; ++j) {
+          const int groups = (j + 1 + pe::kSlotGroup - 1) / pe::kSlotGroup;
+          StepCost cost;
+          run_block_step(ctx, dd, 1, d.Cp * groups, smem_p, d.Cu, smem_u, j, j + 1, pe::MODE_ARNOLDI, mixed, ct, cost,
+                         st);
+        }
+        HCK(hipEventRecord(e1, st));
+        HCK(hipEventSynchronize(e1));
+        float t = 0.0f;
+        HCK(hipEventElapsedTime(&t, e0, e1));
+        ms = std::min(ms, (double)t);
+      }
+      if (ms < best_ms) {
+        best_ms = ms;
+        best = TuneVal{ru, rp};
+      }
+    }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  HCK(hipGetLastError());
+  return best.rows_u ? PE_OK : pe_fail(ctx, PE_ERR_UNSUPPORTED, "pe_autotune: no tiling fits");
+}
+
+pe_status pe_autotune(pe_ctx* ctx, const pe_problem* probs, int32_t nprob, const char* cache_path, int32_t* tuned,
+                      void* stream) {
+  if (!ctx) return PE_ERR_ARG;
+  if (nprob < 0 || (nprob > 0 && !probs)) return pe_fail(ctx, PE_ERR_ARG, "pe_autotune: bad arguments");
+  HCK(hipSetDevice(ctx->device));
+  hipStream_t st = (hipStream_t)stream;
+  if (cache_path) {  // earlier choices: lines "nlog2 bw mixed rows_u rows_p"
+    std::ifstream in(cache_path);
+    int a, b, c, ru, rp;
+    while (in >> a >> b >> c >> ru >> rp)
+      if (a > 0 && a < 48 && b >= 1 && b <= 32 && (c == 0 || c == 1)) ctx->tune[TuneKey{a, b, c}] = TuneVal{ru, rp};
+  }
+  int count = 0;
+  for (int i = 0; i < nprob; ++i) {
+    const pe_problem& p = probs[i];
+    if (p.op.n < 64 || p.rank_max < 0 || p.rank_max > 31) return pe_fail(ctx, PE_ERR_ARG, "pe_autotune: bad problem");
+    const int mixed = p.prec == PE_MIXED ? 1 : 0;
+    // the widths a march meets: rank_max + 1 with the state, rank_max in the zero-state
+    // cycle, 1 past the window
+    for (int bw : {p.rank_max + 1, p.rank_max, 1}) {
+      if (bw < 1) continue;
+      const TuneKey key{tune_nlog2(p.op.n), bw, mixed};
+      if (ctx->tune.count(key)) continue;
+      TuneVal v;
+      const pe_status s = tune_one(ctx, p.op.n, bw, mixed, st, v);
+      if (s != PE_OK) return s;
+      ctx->tune[key] = v;
+      ++count;
+    }
+  }
+  if (tuned) *tuned = count;
+  if (cache_path) {
+    std::ofstream out(cache_path, std::ios::trunc);
+    if (!out) return pe_fail(ctx, PE_ERR_ARG, "pe_autotune: cannot write the cache file");
+    for (const auto& kv : ctx->tune)
+      out << kv.first.nlog2 << ' ' << kv.first.bw << ' ' << kv.first.mixed << ' ' << kv.second.rows_u << ' '
+          << kv.second.rows_p << '\n';
+  }
+  return PE_OK;
+}
+
+// the tuning table of the context as (nlog2, bw, mixed, rows_u, rows_p) rows
+int32_t pe_autotune_table(const pe_ctx* ctx, int32_t* rows, int32_t max_rows) {
+  if (!ctx) return 0;
+  int k = 0;
+  for (const auto& kv : ctx->tune) {
+    if (rows && k < max_rows) {
+      int32_t* r = rows + 5 * k;
+      r[0] = kv.first.nlog2;
+      r[1] = kv.first.bw;
+      r[2] = kv.first.mixed;
+      r[3] = kv.second.rows_u;
+      r[4] = kv.second.rows_p;
+    }
+    ++k;
+  }
+  return k;
 }
 
 pe_status pe_profile_enable(pe_ctx* ctx, const char* family) {
