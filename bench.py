@@ -22,21 +22,33 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 
+def _pmc_record(kernel, windows, krylov):
+    tag = (f"_paraexp{windows}" if windows > 1 else "") + ("_sai" if krylov == "sai" else "")
+    path = os.path.join(ROOT, "profiles", f"pmc_{kernel}_c2_n8192{tag}.txt")
+    try:
+        return json.loads(open(path).read().split("\n---\n", 1)[1])
+    except (OSError, IndexError, ValueError):
+        return None
+
+
 def measured_traffic(kernel, windows, krylov):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary of
     the same window split and Krylov space (FETCH_SIZE + WRITE_SIZE, scaled by a device
     copy of known size), or None when the summary is missing or was taken on a different
     kernel source."""
     import hashlib
-    tag = (f"_paraexp{windows}" if windows > 1 else "") + ("_sai" if krylov == "sai" else "")
-    path = os.path.join(ROOT, "profiles", f"pmc_{kernel}_c2_n8192{tag}.txt")
+    rec = _pmc_record(kernel, windows, krylov)
     src = os.path.join(ROOT, "paper_1509_04567_amd", "csrc", "kernels.hip")
-    try:
-        rec = json.loads(open(path).read().split("\n---\n", 1)[1])
-        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    except (OSError, IndexError, ValueError):
+    if rec is None:
         return None
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
     return rec["traffic_bytes_per_launch"] if rec.get("kernels_hip_sha256") == sha else None
+
+
+def measured_tiles(kernel, windows, krylov):
+    """The block-kernel tiling the counter summary was taken on (as bench.py reports it)."""
+    rec = _pmc_record(kernel, windows, krylov)
+    return rec.get("tiles") if rec else None
 
 
 def main():
@@ -63,6 +75,9 @@ def main():
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="run one device copy of this many MiB first (reference for memory counters)")
     ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work for the baseline")
+    ap.add_argument("--tiles", default="default",
+                    help="tiling of the block kernels: 'tuned' (pe_autotune on this GPU before any timed "
+                         "run), 'default' (the built-in choice) or a tile cache file of pe_autotune")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); this build has no multi-GPU path.",
@@ -88,6 +103,13 @@ def main():
         args.roofline_kernel = "block_proj" if (P > 1 and args.krylov == "poly") else "block_update"
     ctx = pe.Context(0)
     refs = {}
+    if args.tiles != "default":
+        rank_max = synth.config_c2(n=args.n).rank_max
+        precs = [args.precision] if args.no_compare else ["fp64", "mixed"]
+        tt = time.perf_counter()
+        ntuned = ctx.autotune([(args.n, rank_max, pe.PE_FP64 if pr == "fp64" else pe.PE_MIXED) for pr in precs],
+                              None if args.tiles == "tuned" else args.tiles)
+        print(f"autotune: {ntuned} keys timed in {time.perf_counter() - tt:.2f} s", file=sys.stderr, flush=True)
 
     def run(precision, windows, steps, warmup, profile, krylov):
         """Time `steps` solves of the workload at one precision, window split and Krylov
@@ -161,6 +183,16 @@ def main():
     # window at full width and later ones fewer, so that record is not the timed launches'
     traffic = (measured_traffic(args.roofline_kernel, P, args.krylov)
                if args.batch <= 1 and P == 1 and args.n == 8192 and args.precision == "fp64" else None)
+    # the tiling the timed run used for its block widths (rank + 1, rank, 1)
+    table = ctx.autotune_table()
+    nlog2 = max(0, (args.n - 1).bit_length())
+    mixed = 1 if args.precision == "mixed" else 0
+    tiles = {"mode": args.tiles}
+    for bw in sorted({main_run["report"]["rank"] + 1, max(1, main_run["report"]["rank"]), 1}):
+        if (nlog2, bw, mixed) in table:
+            tiles[f"width{bw}"] = {"rows_u": table[(nlog2, bw, mixed)][0], "rows_p": table[(nlog2, bw, mixed)][1]}
+    if traffic is not None and tiles != measured_tiles(args.roofline_kernel, P, args.krylov):
+        traffic = None  # the counters were taken on another tiling
     if launches > 0 and k_ms > 0:
         achieved = k_bytes / (k_ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -234,6 +266,7 @@ def main():
                    "precision": args.precision},
         "rel_l2_vs_oracle": err,
         "report": rep,
+        "tiles": tiles,
         "roofline": roof,
         "compare": compare,
         "cpu_baseline": cpu,

@@ -273,18 +273,18 @@ pe_status pe_wr_burgers(pe_ctx* ctx, const pe_wr_problem* wr, pe_report* reports
 
 /* Tile autotuning of the block orthogonalisation kernels (the batched pipeline of
  * Sec. 2.2: every window's and instance's block Arnoldi, eq. 2.4, runs on them).  For each
- * block width a march of the given problems can meet (rank_max + 1, rank_max, 1) and each
+ * block width a march of the given problems can meet (1 .. rank_max + 1) at the problem's
  * precision, times 12 block Arnoldi steps on a seeded random block of the problem's size
  * for every admissible pair (rows per update chunk in {64, 128, 256, 512}, rows per
- * projection chunk in {16, ..., 256} with rows x width <= 1024) and keeps the fastest in
- * ctx.  The key is (ceil(log2 n), block width, precision): later calls on ctx with grids
+ * projection chunk in {16, ..., 256} with rows x width <= 1024) and keeps in ctx the
+ * fastest if it beats the built-in tiling by 3%, else the built-in one.  The key is (ceil(log2 n), block width, precision): later calls on ctx with grids
  * of the same power-of-two bucket use the choice; keys already in ctx are not re-timed.
  * The choice changes only the partition of the rows into chunks (and so the rounding
  * order of the reductions), never the method.
  *   probs       host array of nprob; only op.n, rank_max and prec are read
  *   cache_path  text file of lines "log2n width mixed rows_u rows_p", or NULL; read before
- *               tuning (its entries are taken as tuned) and rewritten after with every
- *               entry of ctx
+ *               tuning (its entries are taken as tuned) and, when this call timed a new
+ *               key, rewritten after with every entry of ctx
  *   tuned       host, or NULL: the number of keys timed by this call
  * Uses the context workspace (grown on demand) and synchronises the stream.  Errors:
  * PE_ERR_ARG for n < 64, rank_max outside [0, 31] or an unwritable cache file. */

@@ -1167,7 +1167,7 @@ void launch_elementwise(ExpmDev* e, int op, int nprob, int64_t maxNN, hipStream_
 //   op 4: P = T A4 + c7 A3 + c6 A2 + c5 A + c4 I
 //   op 5: T = P A4 + c3 A3 + c2 A2 + c1 A + c0 I
 //   op 6: squaring number k: (k even) P = T T, (k odd) T = P P; skipped when k >= nsq
-constexpr int kGemmK = 64;  // K extent of one staged tile pair
+constexpr int kGemmPf = 4;  // k-steps of fragment loads in flight per wave
 __global__ __launch_bounds__(256) void k_gemm(const ExpmDev* __restrict__ E, int op, int k) {
   const ExpmDev e = E[blockIdx.y];  // by value: uniform, loaded once
   if (!e.active || e.prop) return;
@@ -1192,61 +1192,70 @@ __global__ __launch_bounds__(256) void k_gemm(const ExpmDev* __restrict__ E, int
       else { A = e.T; B = e.T; C = e.P; }
       break;
   }
-  // K-tiles of kGemmK: A tile 32 x kGemmK (k-major), B tile kGemmK x 32 (column-major)
-  constexpr int KT = kGemmK, EPT = 32 * KT / 256;  // elements of each tile per thread
-  __shared__ double As[KT][33];
-  __shared__ double Bs[32][KT + 1];
-  const int t = threadIdx.x;
-  const int lane = t & 63, w = t >> 6;
-  const int wi = w & 1, wj = w >> 1;
-  dbl4 acc = {0.0, 0.0, 0.0, 0.0};
-  // the next K-tile is loaded into registers (clamped addresses, unconditional loads)
-  // while the current one is multiplied from LDS
-  double ra[EPT], rb[EPT];
-  auto load_tile = [&](int kk) {
+  // Every wave computes the whole 32 x 32 tile over the k-steps (of 4) w, w + 4, ...:
+  // four 16 x 16 f64 MFMA accumulators, fragments loaded straight from memory (the
+  // matrices are L2-resident) with kGemmPf k-steps in flight and no barrier in the loop.
+  // The four partial tiles are then summed through LDS, wave w finishing 16 x 16 block w.
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int nks = (N + 3) / 4;
+  const int r0 = i0 + li, r1 = i0 + 16 + li, c0 = j0 + li, c1 = j0 + 16 + li;
+  const bool r0ok = r0 < N, r1ok = r1 < N, c0ok = c0 < N, c1ok = c1 < N;
+  const double* pa0 = A + (r0ok ? r0 : N - 1);  // clamped: every load is in bounds
+  const double* pa1 = A + (r1ok ? r1 : N - 1);
+  const double* pb0 = B + (int64_t)N * (c0ok ? c0 : N - 1);
+  const double* pb1 = B + (int64_t)N * (c1ok ? c1 : N - 1);
+  dbl4 acc[4];
 #pragma unroll
-    for (int h = 0; h < EPT; ++h) {
-      const int q = t + 256 * h;
-      {
-        const int kq = q >> 5, iq = q & 31;  // 32 consecutive rows of one column
-        const int gi = i0 + iq, gk = kk + kq;
-        const double v = A[(int64_t)(gi < N ? gi : N - 1) + (int64_t)N * (gk < N ? gk : N - 1)];
-        ra[h] = (gi < N && gk < N) ? v : 0.0;
-      }
-      {
-        const int jq = q / KT, kq = q % KT;  // KT consecutive k of one column
-        const int gj = j0 + jq, gk = kk + kq;
-        const double v = B[(int64_t)(gk < N ? gk : N - 1) + (int64_t)N * (gj < N ? gj : N - 1)];
-        rb[h] = (gj < N && gk < N) ? v : 0.0;
-      }
-    }
-  };
-  load_tile(0);
-  for (int kk = 0; kk < N; kk += KT) {
+  for (int q = 0; q < 4; ++q) acc[q] = dbl4{0.0, 0.0, 0.0, 0.0};
+  for (int ks0 = w; ks0 < nks; ks0 += 4 * kGemmPf) {
+    double a0[kGemmPf], a1[kGemmPf], b0[kGemmPf], b1[kGemmPf];
 #pragma unroll
-    for (int h = 0; h < EPT; ++h) {
-      const int q = t + 256 * h;
-      As[q >> 5][q & 31] = ra[h];
-      Bs[q / KT][q % KT] = rb[h];
+    for (int f = 0; f < kGemmPf; ++f) {
+      const int kq = 4 * (ks0 + 4 * f) + lk;
+      const bool kok = kq < N;
+      const int64_t kc = kok ? kq : N - 1;
+      const double x0 = pa0[(int64_t)N * kc], x1 = pa1[(int64_t)N * kc];
+      const double y0 = pb0[kc], y1 = pb1[kc];
+      a0[f] = (kok && r0ok) ? x0 : 0.0;
+      a1[f] = (kok && r1ok) ? x1 : 0.0;
+      b0[f] = (kok && c0ok) ? y0 : 0.0;
+      b1[f] = (kok && c1ok) ? y1 : 0.0;
     }
-    __syncthreads();
-    if (kk + KT < N) load_tile(kk + KT);
 #pragma unroll
-    for (int k4 = 0; k4 < KT; k4 += 4) {
-      const double a = As[k4 + (lane >> 4)][wi * 16 + (lane & 15)];
-      const double b = Bs[wj * 16 + (lane & 15)][k4 + (lane >> 4)];
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+    for (int f = 0; f < kGemmPf; ++f) {
+      acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[f], b0[f], acc[0], 0, 0, 0);
+      acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[f], b1[f], acc[1], 0, 0, 0);
+      acc[2] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[f], b0[f], acc[2], 0, 0, 0);
+      acc[3] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[f], b1[f], acc[3], 0, 0, 0);
     }
-    __syncthreads();
   }
+  // red[src wave][block][v * 64 + lane]: every wave holds the same fragment layout
+  __shared__ double red[4][4][256];
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+    if (q != w)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) red[w][q][v * 64 + lane] = acc[q][v];
+  __syncthreads();
+  dbl4 sum = acc[0];
+#pragma unroll
+  for (int q = 1; q < 4; ++q)
+    if (q == w) sum = acc[q];  // compile-time register indices: select, no run-time index
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+    if (q != w)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) sum[v] += red[q][w][v * 64 + lane];
+  const int bi = w >> 1, bj = w & 1;  // block w: rows 16 bi.., columns 16 bj..
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     // accumulator layout of the f64 16x16x4 MFMA: row = lane/16 + 4 v, column = lane % 16
-    const int i = i0 + wi * 16 + (lane >> 4) + 4 * v;
-    const int j = j0 + wj * 16 + (lane & 15);
+    const int i = i0 + bi * 16 + lk + 4 * v;
+    const int j = j0 + bj * 16 + li;
     if (i < N && j < N) {
       const int64_t o = (int64_t)i + (int64_t)N * j;
-      double val = acc[v];
+      double val = sum[v];
       if (ep >= 0)
         val += c_taylor[ep + 3] * e.A3[o] + c_taylor[ep + 2] * e.A2[o] + c_taylor[ep + 1] * e.A[o] +
                (i == j ? c_taylor[ep] : 0.0);

@@ -1890,8 +1890,10 @@ pe_status pe_workspace_query(pe_ctx* ctx, const pe_problem* probs, int32_t nprob
 // ---- pe_autotune: block-kernel tiling per (grid bucket, block width, precision) ------
 // Times kTuneSteps block Arnoldi steps of the polynomial space on a random block for
 // every admissible (rows per update chunk, rows per projection chunk) and keeps the
-// fastest; the choice applies to grids of the same power-of-two bucket.
+// fastest when it beats the built-in tiling by kTuneMargin; the choice applies to grids
+// of the same power-of-two bucket.
 constexpr int kTuneSteps = 12;
+constexpr double kTuneMargin = 0.97;  // a tiling replaces the built-in one when 3% faster
 
 pe_status tune_one(pe_ctx* ctx, int64_t n, int bw, int mixed, hipStream_t st, TuneVal& best) {
   const int L = kTuneSteps;
@@ -1935,46 +1937,60 @@ pe_status tune_one(pe_ctx* ctx, int64_t n, int bw, int mixed, hipStream_t st, Tu
   hipEvent_t e0, e1;
   HCK(hipEventCreate(&e0));
   HCK(hipEventCreate(&e1));
-  double best_ms = HUGE_VAL;
-  best = TuneVal{0, 0};
+  // time of L block steps (best of three passes; the first warms the caches) on a tiling,
+  // or HUGE_VAL when the tiling does not fit
+  auto time_tiling = [&](int ru, int rp) -> double {
+    int cg, ct;
+    if (ru > n || rp * bw > 1024 || rp > n || !update_chunks_for(n, bw, ru, cg, ct)) return HUGE_VAL;
+    d.bw = bw;
+    d.rows_u = ru;
+    d.rows_u_log2 = 0;
+    while ((1 << d.rows_u_log2) < ru) ++d.rows_u_log2;
+    d.Cu = (int)std::max<int64_t>(1, n / ru);
+    d.comb_global = cg;
+    d.comb_tree = ct;
+    d.rows_p = rp;
+    d.Cp = (int)((n + rp - 1) / rp);
+    if (!geometry_fits(d, caps, L + 1)) return HUGE_VAL;
+    HCK(hipMemsetAsync(d.cnt, 0, caps.cnt * sizeof(unsigned), st));
+    HCK(hipMemcpyAsync(dd, &d, sizeof(ProbDev), hipMemcpyHostToDevice, st));
+    const size_t smem_p = proj_smem(d), smem_u = update_smem(d);
+    double ms = HUGE_VAL;
+    for (int rep = 0; rep < 3; ++rep) {
+      HCK(hipEventRecord(e0, st));
+      pe::launch_block_update(dd, 1, d.Cu, smem_u, 0, 0, 1, pe::MODE_INIT, mixed, ct, st);
+      for (int j = 0; j < L; ++j) {
+        const int groups = (j + 1 + pe::kSlotGroup - 1) / pe::kSlotGroup;
+        StepCost cost;
+        run_block_step(ctx, dd, 1, d.Cp * groups, smem_p, d.Cu, smem_u, j, j + 1, pe::MODE_ARNOLDI, mixed, ct, cost,
+                       st);
+      }
+      HCK(hipEventRecord(e1, st));
+      HCK(hipEventSynchronize(e1));
+      float t = 0.0f;
+      HCK(hipEventElapsedTime(&t, e0, e1));
+      ms = std::min(ms, (double)t);
+    }
+    return ms;
+  };
+  // the built-in tiling is the prior: another replaces it only when clearly faster
+  int du, dcg, dct;
+  choose_update_chunks(n, bw, du, dcg, dct);
+  const int dp = rows_p_for(bw);
+  const double def_ms = time_tiling(du, dp);
+  best = TuneVal{du, dp};
+  double best_ms = def_ms;
   for (int ru : {64, 128, 256, 512})
     for (int rp : {16, 32, 64, 128, 256}) {
-      int cg, ct;
-      if (ru > n || rp * bw > 1024 || rp > n || !update_chunks_for(n, bw, ru, cg, ct)) continue;
-      d.bw = bw;
-      d.rows_u = ru;
-      d.rows_u_log2 = 0;
-      while ((1 << d.rows_u_log2) < ru) ++d.rows_u_log2;
-      d.Cu = (int)std::max<int64_t>(1, n / ru);
-      d.comb_global = cg;
-      d.comb_tree = ct;
-      d.rows_p = rp;
-      d.Cp = (int)((n + rp - 1) / rp);
-      if (!geometry_fits(d, caps, L + 1)) continue;
-      HCK(hipMemsetAsync(d.cnt, 0, caps.cnt * sizeof(unsigned), st));
-      HCK(hipMemcpyAsync(dd, &d, sizeof(ProbDev), hipMemcpyHostToDevice, st));
-      const size_t smem_p = proj_smem(d), smem_u = update_smem(d);
-      double ms = HUGE_VAL;
-      for (int rep = 0; rep < 2; ++rep) {  // the first pass warms the caches
-        HCK(hipEventRecord(e0, st));
-        pe::launch_block_update(dd, 1, d.Cu, smem_u, 0, 0, 1, pe::MODE_INIT, mixed, ct, st);
-        for (int j = 0; j < L; ++j) {
-          const int groups = (j + 1 + pe::kSlotGroup - 1) / pe::kSlotGroup;
-          StepCost cost;
-          run_block_step(ctx, dd, 1, d.Cp * groups, smem_p, d.Cu, smem_u, j, j + 1, pe::MODE_ARNOLDI, mixed, ct, cost,
-                         st);
-        }
-        HCK(hipEventRecord(e1, st));
-        HCK(hipEventSynchronize(e1));
-        float t = 0.0f;
-        HCK(hipEventElapsedTime(&t, e0, e1));
-        ms = std::min(ms, (double)t);
-      }
+      if (ru == du && rp == dp) continue;
+      const double ms = time_tiling(ru, rp);
       if (ms < best_ms) {
         best_ms = ms;
         best = TuneVal{ru, rp};
       }
     }
+  if (!(best_ms < kTuneMargin * def_ms) && def_ms < HUGE_VAL) best = TuneVal{du, dp};
+  if (!(best_ms < HUGE_VAL)) best = TuneVal{0, 0};
   hipEventDestroy(e0);
   hipEventDestroy(e1);
   HCK(hipGetLastError());
@@ -1998,10 +2014,9 @@ pe_status pe_autotune(pe_ctx* ctx, const pe_problem* probs, int32_t nprob, const
     const pe_problem& p = probs[i];
     if (p.op.n < 64 || p.rank_max < 0 || p.rank_max > 31) return pe_fail(ctx, PE_ERR_ARG, "pe_autotune: bad problem");
     const int mixed = p.prec == PE_MIXED ? 1 : 0;
-    // the widths a march meets: rank_max + 1 with the state, rank_max in the zero-state
-    // cycle, 1 past the window
-    for (int bw : {p.rank_max + 1, p.rank_max, 1}) {
-      if (bw < 1) continue;
+    // every width a march can meet: compressed rank m <= rank_max, m + 1 with the state,
+    // m in the zero-state cycle, 1 past the window
+    for (int bw = 1; bw <= p.rank_max + 1; ++bw) {
       const TuneKey key{tune_nlog2(p.op.n), bw, mixed};
       if (ctx->tune.count(key)) continue;
       TuneVal v;
@@ -2012,7 +2027,7 @@ pe_status pe_autotune(pe_ctx* ctx, const pe_problem* probs, int32_t nprob, const
     }
   }
   if (tuned) *tuned = count;
-  if (cache_path) {
+  if (cache_path && count > 0) {
     std::ofstream out(cache_path, std::ios::trunc);
     if (!out) return pe_fail(ctx, PE_ERR_ARG, "pe_autotune: cannot write the cache file");
     for (const auto& kv : ctx->tune)

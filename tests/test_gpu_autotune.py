@@ -39,11 +39,11 @@ def test_autotune_choices_are_admissible_and_cached(pe, tmp_path):
     ctx = pe.Context(0)
     try:
         shapes = [(8192, 16, pe.PE_FP64), (8192, 16, pe.PE_MIXED), (600, 3, pe.PE_FP64)]
-        assert ctx.autotune(shapes, cache) == 3 + 3 + 3
+        assert ctx.autotune(shapes, cache) == 17 + 17 + 4
         table = ctx.autotune_table()
         print("tuned tiles", table, flush=True)
-        assert set(table) == {(13, 17, 0), (13, 16, 0), (13, 1, 0), (13, 17, 1), (13, 16, 1), (13, 1, 1),
-                              (10, 4, 0), (10, 3, 0), (10, 1, 0)}
+        assert set(table) == ({(13, bw, mx) for bw in range(1, 18) for mx in (0, 1)}
+                              | {(10, bw, 0) for bw in range(1, 5)})
         for (nlog2, bw, _), (ru, rp) in table.items():
             assert ru in (64, 128, 256, 512) and ru <= 1 << nlog2
             assert rp in (16, 32, 64, 128, 256) and rp * bw <= 1024
