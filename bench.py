@@ -18,6 +18,7 @@ import sys
 import time
 
 HBM_PEAK_GBS = 8000.0  # MI355X published HBM3E bandwidth
+F64_MFMA_PEAK_TFS = 78.6  # MI355X published dense FP64 matrix rate
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -75,6 +76,8 @@ def main():
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="run one device copy of this many MiB first (reference for memory counters)")
     ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work for the baseline")
+    ap.add_argument("--no-kernels", action="store_true",
+                    help="skip the GEMM (MFMA) and stencil (HBM) kernel figures")
     ap.add_argument("--tiles", default="default",
                     help="tiling of the block kernels: 'tuned' (pe_autotune on this GPU before any timed "
                          "run), 'default' (the built-in choice) or a tile cache file of pe_autotune")
@@ -111,7 +114,7 @@ def main():
                               None if args.tiles == "tuned" else args.tiles)
         print(f"autotune: {ntuned} keys timed in {time.perf_counter() - tt:.2f} s", file=sys.stderr, flush=True)
 
-    def run(precision, windows, steps, warmup, profile, krylov):
+    def run(precision, windows, steps, warmup, profile, krylov, family=None):
         """Time `steps` solves of the workload at one precision, window split and Krylov
         space; returns the figures of that run (accuracy against the oracle checked
         outside the timing)."""
@@ -146,7 +149,7 @@ def main():
                   flush=True)
         torch.cuda.synchronize()
         if profile:  # per-launch HIP-event timing of the dominant kernel family, on the solve's stream
-            ctx.profile_enable(args.roofline_kernel)
+            ctx.profile_enable(family or args.roofline_kernel)
         t0 = time.perf_counter()
         for i in range(steps):
             ts = time.perf_counter()
@@ -225,6 +228,35 @@ def main():
         compare[f"speedup_{args.krylov}_over_{other_kr}"] = main_run["solves_per_s"] / pk["solves_per_s"]
     t_oracle = refs[(args.n, 2)][1]
 
+    # kernel figures beside the solve: the projected exponential's f64 MFMA products in the
+    # same solve (one timed step), and the stencil S0 alone on a 2^20 x 32 block (the
+    # long-grid, wide-block shape), each against its published peak
+    kernels = {}
+    if not args.no_kernels:
+        g = run(args.precision, P, 1, 0, True, args.krylov, family="gemm")["prof"]
+        if g["launches"] > 0 and g["ms"] > 0:
+            tfs = g["flops"] / (g["ms"] * 1e-3) / 1e12
+            kernels["gemm"] = {"bound": "mfma", "achieved": tfs, "peak": F64_MFMA_PEAK_TFS, "unit": "TFLOP/s",
+                               "frac": tfs / F64_MFMA_PEAK_TFS, "kernel": "k_gemm", "launches": g["launches"],
+                               "avg_launch_us": 1e3 * g["ms"] / g["launches"],
+                               "flops_per_launch": g["flops"] / g["launches"]}
+        ns, cols = 1 << 20, 32
+        X = torch.randn(cols, ns, dtype=torch.float64, device="cuda")
+        coeffs = [1.0, -2.0, 1.0]
+        ctx.stencil_apply(coeffs, X)  # warm
+        ctx.profile_enable("stencil")
+        for _ in range(20):
+            ctx.stencil_apply(coeffs, X)
+        sp = ctx.profile_read()
+        ctx.profile_enable(None)
+        del X
+        if sp["launches"] > 0 and sp["ms"] > 0:
+            gbs = sp["bytes"] / (sp["ms"] * 1e-3) / 1e9
+            kernels["stencil"] = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                  "frac": gbs / HBM_PEAK_GBS, "kernel": "k_stencil_cols", "n": ns, "columns": cols,
+                                  "avg_launch_us": 1e3 * sp["ms"] / sp["launches"],
+                                  "bytes_per_launch": sp["bytes"] / sp["launches"]}
+
     cpu = None
     if not args.no_cpu:
         reps_cpu, spent = 1, t_oracle
@@ -268,6 +300,7 @@ def main():
         "report": rep,
         "tiles": tiles,
         "roofline": roof,
+        "kernels": kernels,
         "compare": compare,
         "cpu_baseline": cpu,
     }

@@ -297,7 +297,8 @@ int32_t pe_autotune_table(const pe_ctx* ctx, int32_t* rows, int32_t max_rows);
 /* Kernel timing for roofline measurements.  Enables HIP-event timing, on the stream of
  * each call, of one kernel family: "block_update" (block Gram-Schmidt update + chunk QR
  * + TSQR combine) or "block_proj" (block projections) -- the first orthogonalisation
- * pass of every block Arnoldi step, which always runs in full -- or "stencil"
+ * pass of every block Arnoldi step, which always runs in full -- or "gemm" (the f64 MFMA
+ * products of the projected exponential, 2 N^3 flops per problem multiplied) or "stencil"
  * (pe_stencil_apply), or NULL to switch timing off.  Resets the accumulators.  Timing
  * adds two event records per timed launch; within a march every restart cycle is timed
  * (all of its block steps). */

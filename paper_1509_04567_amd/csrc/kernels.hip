@@ -321,7 +321,7 @@ void launch_add_column(int64_t n, int s, const double* G, int64_t ldG, const dou
 // Block orthogonalisation.  Per block step and pass:
 //   k_block_proj:   S_i = V_i^T X over row chunks, for a group of GS slots per workgroup;
 //                   the last workgroup of a group reduces the chunk partials into S.
-//   k_block_update: X -= sum_i V_i S_i on one row chunk, wave-level MGS2 of the chunk,
+//   k_block_update: X -= sum_i V_i S_i on one row chunk, wave-level QR of the chunk,
 //                   and the TSQR combine by the last workgroup.
 // The input block X of a pass is
 //   pass 0, MODE_ARNOLDI: W = L V_j, V_j given by the previous TSQR (Qloc2, Qs2);

@@ -1234,19 +1234,34 @@ pe_status march_batch(pe_ctx* ctx, const pe_problem* probs, const int* idx, int 
       }
       if (npend == 0) break;
       HCK(hipMemcpyAsync(ed, he.data(), sizeof(ExpmDev) * nb_prob, hipMemcpyHostToDevice, st));
+      // one timed GEMM launch: 2 N^3 flops and 3 N^2 doubles (A, B read, C written; the
+      // Paterson-Stockmeyer epilogue reads three more) per problem it multiplies for
+      auto gemm = [&](int op, int k) {
+        double fl = 0.0, by = 0.0;
+        for (int ii = 0; ii < nb_prob; ++ii) {
+          const ExpmDev& e = he[ii];
+          if (!e.active || e.prop || (op == 6 && k >= e.nsq)) continue;
+          const double NN = (double)e.N * e.N;
+          fl += 2.0 * NN * e.N;
+          by += 8.0 * NN * (op >= 3 && op <= 5 ? 6.0 : 3.0);
+        }
+        const int ev = prof_begin(ctx, "gemm", st);
+        pe::launch_gemm(ed, op, k, nb_prob, tiles * tiles, st);
+        prof_end(ctx, ev, by, fl, st);
+      };
       if (nfull > 0) {
         pe::launch_elementwise(ed, 0, nb_prob, maxNN, st);
-        pe::launch_gemm(ed, 0, 0, nb_prob, tiles * tiles, st);
-        pe::launch_gemm(ed, 1, 0, nb_prob, tiles * tiles, st);
-        pe::launch_gemm(ed, 2, 0, nb_prob, tiles * tiles, st);
+        gemm(0, 0);
+        gemm(1, 0);
+        gemm(2, 0);
         pe::launch_elementwise(ed, 1, nb_prob, maxNN, st);
-        pe::launch_gemm(ed, 3, 0, nb_prob, tiles * tiles, st);
-        pe::launch_gemm(ed, 4, 0, nb_prob, tiles * tiles, st);
-        pe::launch_gemm(ed, 5, 0, nb_prob, tiles * tiles, st);
+        gemm(3, 0);
+        gemm(4, 0);
+        gemm(5, 0);
       }
       pe::launch_expm_apply(ed, 0, nb_prob, mb_N, st);
       for (int k = 0; k < maxsq; ++k) {
-        pe::launch_gemm(ed, 6, k, nb_prob, tiles * tiles, st);
+        gemm(6, k);
         pe::launch_expm_apply(ed, k + 1, nb_prob, mb_N, st);
       }
       for (int ii = 0; ii < nb_prob; ++ii)
@@ -2058,7 +2073,7 @@ int32_t pe_autotune_table(const pe_ctx* ctx, int32_t* rows, int32_t max_rows) {
 pe_status pe_profile_enable(pe_ctx* ctx, const char* family) {
   if (!ctx) return PE_ERR_ARG;
   if (family && std::strcmp(family, "block_update") && std::strcmp(family, "block_proj") &&
-      std::strcmp(family, "stencil"))
+      std::strcmp(family, "stencil") && std::strcmp(family, "gemm"))
     return pe_fail(ctx, PE_ERR_ARG, "pe_profile_enable: unknown kernel family");
   ctx->prof_name = family ? family : "";
   ctx->prof_launches = 0;
