@@ -59,8 +59,10 @@ void launch_expm_apply(ExpmDev* e, int level, int nprob, int maxN, hipStream_t s
 // LDS of the solve kernel (doubles, within gfx950's 160 KiB per workgroup); chunks per
 // workgroup of the solve and whether their rows are staged in LDS
 constexpr int kSaiLdsDoubles = 20000;
+// (64 sweeping threads per workgroup: more workgroups share the staging loads, which
+// dominate the solve at one problem)
 __host__ __device__ inline int sai_chunks_per_group(int R, int bw) {
-  const int by_threads = 256 / bw, by_lds = kSaiLdsDoubles / ((R + 2) * (bw + 3)) - 1;
+  const int by_threads = bw <= 64 ? 64 / bw : 1, by_lds = kSaiLdsDoubles / ((R + 2) * (bw + 3)) - 1;
   const int c = by_threads < by_lds ? by_threads : by_lds;
   return c < 1 ? 1 : c;
 }

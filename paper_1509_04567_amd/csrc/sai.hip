@@ -257,7 +257,7 @@ __device__ void pcr_solve(int C, int bw, const double* __restrict__ red, double*
     }
 }
 
-// W = T^{-1} V_j (V_j committed): a workgroup takes cpw consecutive chunks (cpw bw <= 256
+// W = T^{-1} V_j (V_j committed): a workgroup takes cpw consecutive chunks (cpw bw <= 64
 // threads); when their rows of V_j fit in LDS they are staged there -- each chunk in its
 // own region, padded by two doubles so that the chunks a wave works on start in different
 // LDS banks -- and thread (chunk, column) eliminates its chunk in LDS, otherwise it works
@@ -509,6 +509,34 @@ __device__ __forceinline__ double lane_bcast(double v, int src) {
   return __hiloint2double(hi, lo);
 }
 
+// (value, index) maximum over the wave, the smallest index among equal values, returned
+// to every lane: the DPP pattern of wave_sum (rows of 16 lanes, then the row broadcasts
+// into lane 63) with a compare-select in place of the add; lanes outside a stage's
+// row mask keep their own pair
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ void argmax_stage(double& best, int& bi) {
+  const int lo = __builtin_amdgcn_update_dpp(__double2loint(best), __double2loint(best), CTRL, ROW_MASK, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(__double2hiint(best), __double2hiint(best), CTRL, ROW_MASK, 0xF, false);
+  const int oi = __builtin_amdgcn_update_dpp(bi, bi, CTRL, ROW_MASK, 0xF, false);
+  const double ob = __hiloint2double(hi, lo);
+  if (ob > best || (ob == best && oi < bi)) {
+    best = ob;
+    bi = oi;
+  }
+}
+__device__ __forceinline__ void wave_argmax(double& best, int& bi) {
+  argmax_stage<0xB1, 0xF>(best, bi);
+  argmax_stage<0x4E, 0xF>(best, bi);
+  argmax_stage<0x124, 0xF>(best, bi);
+  argmax_stage<0x128, 0xF>(best, bi);
+  argmax_stage<0x142, 0xA>(best, bi);
+  argmax_stage<0x143, 0xC>(best, bi);
+  const int lo = __builtin_amdgcn_readlane(__double2loint(best), 63);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(best), 63);
+  bi = __builtin_amdgcn_readlane(bi, 63);
+  best = __hiloint2double(hi, lo);
+}
+
 // panel jb: rows [k0, pe) (at most 2 bw <= 64), columns [k0, k1); lane q holds row k0 + q
 __global__ __launch_bounds__(64) void k_lu_panel(const TriDev* __restrict__ tds, int jb) {
   const TriDev t = tds[blockIdx.x];
@@ -527,14 +555,7 @@ __global__ __launch_bounds__(64) void k_lu_panel(const TriDev* __restrict__ tds,
     double best = (lane >= kq && lane < nb) ? fabs(P[lane * LD + kq]) : -1.0;
     if (!(best >= 0.0)) best = -1.0;
     int bi = lane;
-    for (int off = 32; off >= 1; off >>= 1) {
-      const double ob = __shfl_xor(best, off);
-      const int oi = __shfl_xor(bi, off);
-      if (ob > best || (ob == best && oi < bi)) {
-        best = ob;
-        bi = oi;
-      }
-    }
+    wave_argmax(best, bi);
     if (!(best > 0.0)) {
       // zero column: a deflated basis direction when row kq is zero as well (unit pivot)
       int nz = 0;
