@@ -300,23 +300,26 @@ __global__ __launch_bounds__(256) void k_sai_solve(const ProbDev* __restrict__ p
       const int nrows = (int)(chunk_end(t, c1 - 1) - rs);
       const int rbw = R * bw;
       bulk_load<16>(
-          (int64_t)nrows * bw, [&](int64_t q) -> double { return (double)V[rs * bw + q]; },
-          [&](int64_t q, double v) {
+          (int64_t)nrows * bw, [=](int64_t q) -> double { return (double)V[rs * bw + q]; },
+          [=](int64_t q, double v) {
             const int k = min((int)q / rbw, nch - 1);
             xv0[q + 2 * k] = v;
           });
+      // the three coefficient rows as offsets from the first (arithmetic selection: a
+      // select among pointers compiles to a table in scratch memory)
+      const double* ta = t.ta;
+      const int64_t o1 = t.tinv - t.ta, o2 = t.tc - t.ta;
+      const int64_t x1 = xi0 - xa0, x2 = xc0 - xa0;
       bulk_load<16>(
           3 * (int64_t)nrows,
-          [&](int64_t q) -> double {
+          [=](int64_t q) -> double {
             const int a = (int)q / nrows, r = (int)q - a * nrows;
-            const double* src = a == 0 ? t.ta : (a == 1 ? t.tinv : t.tc);
-            return src[rs + r];
+            return ta[(a == 1 ? o1 : 0) + (a == 2 ? o2 : 0) + rs + r];
           },
-          [&](int64_t q, double v) {
+          [=](int64_t q, double v) {
             const int a = (int)q / nrows, r = (int)q - a * nrows;
             const int k = min(r / R, nch - 1);
-            double* dst = a == 0 ? xa0 : (a == 1 ? xi0 : xc0);
-            dst[r + 2 * k] = v;
+            xa0[(a == 1 ? x1 : 0) + (a == 2 ? x2 : 0) + r + 2 * k] = v;
           });
       lds_barrier();
       if (mine) {
@@ -397,7 +400,8 @@ __global__ __launch_bounds__(256) void k_sai_solve(const ProbDev* __restrict__ p
   if (2 * nf <= kSaiLdsDoubles) {
     double* f = xs;
     double* g = xs + nf;
-    bulk_load(nf, [&](int64_t e) -> double { return t.rrhs[e]; }, [&](int64_t e, double v) { f[e] = v; });
+    const double* rrhs = t.rrhs;
+    bulk_load(nf, [=](int64_t e) -> double { return rrhs[e]; }, [=](int64_t e, double v) { f[e] = v; });
     __syncthreads();
     pcr_solve<true>(C, bw, t.red, f, g, t.ru);
   } else {
@@ -538,11 +542,69 @@ __device__ __forceinline__ void wave_argmax(double& best, int& bi) {
 }
 
 // panel jb: rows [k0, pe) (at most 2 bw <= 64), columns [k0, k1); lane q holds row k0 + q
-__global__ __launch_bounds__(64) void k_lu_panel(const TriDev* __restrict__ tds, int jb) {
-  const TriDev t = tds[blockIdx.x];
-  if (!t.active) return;
-  const int N0 = t.N0, bw = t.bw, lane = threadIdx.x;
-  if (jb >= N0 / bw) return;
+// in registers (BWM >= bw columns, compile-time register indices), the pivot row and the
+// interchanged rows broadcast by readlane
+template <int BWM>
+__device__ __forceinline__ void lu_panel_regs(const TriDev& t, int jb, int lane) {
+  const int N0 = t.N0, bw = t.bw;
+  double* A = t.LU;
+  const int k0 = jb * bw, k1 = k0 + bw, pe = min(N0, k1 + bw), nb = pe - k0, nc = bw;
+  double xr[BWM];
+#pragma unroll
+  for (int c = 0; c < BWM; ++c) {
+    const double v = A[(int64_t)(k0 + (lane < nb ? lane : nb - 1)) + (int64_t)N0 * (k0 + (c < nc ? c : nc - 1))];
+    xr[c] = (lane < nb && c < nc) ? v : 0.0;
+  }
+  int bad = 0;
+#pragma unroll
+  for (int kq = 0; kq < BWM; ++kq) {
+    if (kq >= nc) break;
+    // pivot: the largest |entry| of column kq in rows kq..nb-1, the smallest row among equals
+    double best = (lane >= kq && lane < nb) ? fabs(xr[kq]) : -1.0;
+    if (!(best >= 0.0)) best = -1.0;
+    int bi = lane;
+    wave_argmax(best, bi);
+    if (!(best > 0.0)) {
+      // zero column: a deflated basis direction when row kq is zero as well (unit pivot)
+      int nz = 0;
+#pragma unroll
+      for (int c = kq + 1; c < BWM; ++c)
+        if (c < nc) nz |= (lane_bcast(xr[c], kq) != 0.0);
+      for (int c = k1 + lane; c < N0; c += 64) nz |= (A[(int64_t)(k0 + kq) + (int64_t)N0 * c] != 0.0);
+      bad |= __any(nz);
+      if (lane == kq) xr[kq] = 1.0;
+      if (lane == 0) t.piv[k0 + kq] = k0 + kq;
+      continue;
+    }
+    if (lane == 0) t.piv[k0 + kq] = k0 + bi;
+    if (bi != kq) {  // exchange rows kq and bi in columns >= kq (multipliers stay in place)
+#pragma unroll
+      for (int c = kq; c < BWM; ++c) {
+        const double a = lane_bcast(xr[c], kq), b = lane_bcast(xr[c], bi);
+        if (lane == kq) xr[c] = b;
+        else if (lane == bi) xr[c] = a;
+      }
+    }
+    double prow[BWM];
+#pragma unroll
+    for (int c = kq; c < BWM; ++c) prow[c] = lane_bcast(xr[c], kq);
+    if (lane > kq && lane < nb) {
+      const double m = xr[kq] / prow[kq];
+      xr[kq] = m;
+#pragma unroll
+      for (int c = kq + 1; c < BWM; ++c) xr[c] -= m * prow[c];
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < BWM; ++c)
+    if (lane < nb && c < nc) A[(int64_t)(k0 + lane) + (int64_t)N0 * (k0 + c)] = xr[c];
+  // a zero pivot column with a nonzero row: K is singular (row 0 is final by now)
+  if (lane == 0 && bad) A[0] = __longlong_as_double(0x7ff8000000000000LL);
+}
+
+// wider panels (bw > 16): the panel in LDS, one lane per row
+__device__ __forceinline__ void lu_panel_lds(const TriDev& t, int jb, int lane) {
+  const int N0 = t.N0, bw = t.bw;
   constexpr int LD = 33;
   __shared__ double P[64 * LD];
   double* A = t.LU;
@@ -589,6 +651,19 @@ __global__ __launch_bounds__(64) void k_lu_panel(const TriDev* __restrict__ tds,
     if (lane < nb) A[(int64_t)(k0 + lane) + (int64_t)N0 * (k0 + c)] = P[lane * LD + c];
   // a zero pivot column with a nonzero row: K is singular (row 0 is final by now)
   if (lane == 0 && bad) A[0] = __longlong_as_double(0x7ff8000000000000LL);
+}
+
+__global__ __launch_bounds__(64) void k_lu_panel(const TriDev* __restrict__ tds, int jb) {
+  const TriDev t = tds[blockIdx.x];
+  if (!t.active) return;
+  if (jb >= t.N0 / t.bw) return;
+  const int lane = threadIdx.x;
+  if (t.bw <= 8)
+    lu_panel_regs<8>(t, jb, lane);
+  else if (t.bw <= 16)
+    lu_panel_regs<16>(t, jb, lane);
+  else
+    lu_panel_lds(t, jb, lane);
 }
 
 // trailing columns of panel jb: the interchanges and eliminations in order
