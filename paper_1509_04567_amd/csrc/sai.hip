@@ -10,7 +10,7 @@
 //   k_tri_factor / k_tri_reduce_factor  factor T = I - gamma L (periodic tridiagonal) by
 //                                        partition: per-chunk elimination, spikes, and the
 //                                        periodic block-tridiagonal interface system
-//   k_sai_solve / k_sai_recon           W = T^{-1} V_j for the Arnoldi step j (V_j formed
+//   k_sai_solve / k_sai_pcr / k_sai_recon   W = T^{-1} V_j for the Arnoldi step j (V_j formed
 //                                        from its TSQR factors and committed to the basis)
 //   k_sai_gram                          Gram of (I - gamma L) V_l for the residual estimate
 //   k_lu_panel / k_lu_trail / k_hess_inv   K_l^{-1} by LU with row interchanges
@@ -262,8 +262,8 @@ __device__ void pcr_solve(int C, int bw, const double* __restrict__ red, double*
 // own region, padded by two doubles so that the chunks a wave works on start in different
 // LDS banks -- and thread (chunk, column) eliminates its chunk in LDS, otherwise it works
 // on W in global memory.  The chunk solutions y go to W and their end values to rrhs
-// (column-major interface vectors, see pcr_solve).  The last workgroup of the problem
-// solves the interface system.
+// (column-major interface vectors, see pcr_solve); k_sai_pcr then solves the interface
+// system, one workgroup per column.
 template <typename TS>
 __global__ __launch_bounds__(256) void k_sai_solve(const ProbDev* __restrict__ pds, const TriDev* __restrict__ tds,
                                                    int j) {
@@ -271,7 +271,6 @@ __global__ __launch_bounds__(256) void k_sai_solve(const ProbDev* __restrict__ p
   const TriDev t = tds[blockIdx.y];
   if (!p.active || !t.active || j >= p.l) return;
   extern __shared__ double xs[];
-  __shared__ int flag;
   const int bw = p.bw, tid = threadIdx.x, R = t.R;
   const int cpw = sai_chunks_per_group(R, bw);
   const bool lds = sai_stage_in_lds(R, bw);
@@ -392,21 +391,27 @@ __global__ __launch_bounds__(256) void k_sai_solve(const ProbDev* __restrict__ p
       st_agent(t.rrhs + col * ld + 2 * c, y);
     }
   }
-  if (!arrive_last(t.cnt, gridDim.x, &flag)) return;
-  if (tid == 0) atomicExch(t.cnt, 0u);
-  const int C = t.C;
-  const int64_t nf = 2 * (int64_t)C * bw;
+}
+
+// launch bounds of the interface solve: chunks (sai_chunking) and block width
+constexpr int kSaiMaxC = 256;
+constexpr int kSaiMaxBw = 32;
+
+// The interface system of one column (k_sai_solve wrote its right-hand sides): one
+// workgroup per (column, problem), thread c for chunk c, ping-pong buffers in LDS.
+// Per column the arithmetic is that of a multi-column sweep, in the same order.
+__global__ __launch_bounds__(256) void k_sai_pcr(const TriDev* __restrict__ tds) {
+  const TriDev t = tds[blockIdx.y];
+  const int col = blockIdx.x;
+  if (!t.active || col >= t.bw) return;
+  extern __shared__ double xs[];
+  const int64_t ld = 2 * (int64_t)t.C;
+  double* f = xs;
+  double* g = xs + ld;
+  const double* src = t.rrhs + col * ld;
+  bulk_load(ld, [=](int64_t e) -> double { return src[e]; }, [=](int64_t e, double v) { f[e] = v; });
   __syncthreads();
-  if (2 * nf <= kSaiLdsDoubles) {
-    double* f = xs;
-    double* g = xs + nf;
-    const double* rrhs = t.rrhs;
-    bulk_load(nf, [=](int64_t e) -> double { return rrhs[e]; }, [=](int64_t e, double v) { f[e] = v; });
-    __syncthreads();
-    pcr_solve<true>(C, bw, t.red, f, g, t.ru);
-  } else {
-    pcr_solve<false>(C, bw, t.red, t.rrhs, t.ru, t.ru);  // ping-pong in global memory (wide blocks)
-  }
+  pcr_solve<true>(t.C, 1, t.red, f, g, t.ru + col * ld);
 }
 
 // W[r, col] -= G_{c-1} vL[r] + F_{c+1} vR[r]: the chunk solutions coupled to the
@@ -802,6 +807,8 @@ void launch_sai_solve(ProbDev* d, TriDev* td, int nprob, int groups, int64_t max
     hipLaunchKernelGGL(k_sai_solve<float>, gs, dim3(256), lds, st, d, td, j);
   else
     hipLaunchKernelGGL(k_sai_solve<double>, gs, dim3(256), lds, st, d, td, j);
+  hipLaunchKernelGGL(k_sai_pcr, dim3((unsigned)kSaiMaxBw, (unsigned)nprob), dim3(256),
+                     sizeof(double) * 4 * kSaiMaxC, st, td);
   hipLaunchKernelGGL(k_sai_recon, ge, dim3(256), 0, st, td);
 }
 
