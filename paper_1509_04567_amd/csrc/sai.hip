@@ -206,24 +206,34 @@ __global__ __launch_bounds__(256) void k_sai_commit(const ProbDev* __restrict__ 
 // workgroup barrier orders the levels.
 template <bool kLdsBuf>
 __device__ void pcr_solve(int C, int bw, const double* __restrict__ red, double* f, double* g, double* u) {
+  constexpr int kMaxLev = 8;  // C <= 256 chunks
   const int nlev = sai_levels(C);
   const int c = threadIdx.x;
   const bool act = c < C;
   const int64_t ld = 2 * (int64_t)C;
-  double ab[8], nx[8];
+  // the chunk's coefficients of every level and its final 2 x 2 block, all loads issued
+  // at once (clamped indices); the levels then wait only on LDS
+  double abl[kMaxLev][8], fin[4];
 #pragma unroll
-  for (int k = 0; k < 8; ++k) ab[k] = (act && nlev > 0) ? red[(int64_t)c * 8 + k] : 0.0;
-  for (int lev = 0; lev < nlev; ++lev) {
-    const int s = 1 << lev;
-    if (lev + 1 < nlev) {
+  for (int lev = 0; lev < kMaxLev; ++lev)
 #pragma unroll
-      for (int k = 0; k < 8; ++k) nx[k] = act ? red[((int64_t)(lev + 1) * C + c) * 8 + k] : 0.0;
-    } else {
-#pragma unroll
-      for (int k = 0; k < 4; ++k) nx[k] = act ? red[((int64_t)nlev * C) * 8 + 4 * (int64_t)c + k] : 0.0;
+    for (int k = 0; k < 8; ++k) {
+      const bool ok = act && lev < nlev;
+      const double v = red[ok ? ((int64_t)lev * C + c) * 8 + k : 0];
+      abl[lev][k] = ok ? v : 0.0;
     }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const double v = red[act ? (int64_t)nlev * C * 8 + 4 * (int64_t)c + k : 0];
+    fin[k] = act ? v : 0.0;
+  }
+#pragma unroll
+  for (int lev = 0; lev < kMaxLev; ++lev) {
+    if (lev >= nlev) break;
+    const int s = 1 << lev;
+    const double* ab = abl[lev];
     if (act) {
-      const int m = (c - s + C) % C, p = (c + s) % C;
+      const int m = (c - s) & (C - 1), p = (c + s) & (C - 1);  // C is a power of two
 #pragma unroll 4
       for (int col = 0; col < bw; ++col) {
         const double* fc = f + col * ld;
@@ -234,7 +244,6 @@ __device__ void pcr_solve(int C, int bw, const double* __restrict__ red, double*
         g[col * ld + 2 * c + 1] = f1 - (ab[2] * m0 + ab[3] * m1) - (ab[6] * p0 + ab[7] * p1);
       }
     }
-    // LDS buffers: the barrier leaves the coefficient fetch of the next level in flight
     if (kLdsBuf)
       lds_barrier();
     else
@@ -242,18 +251,12 @@ __device__ void pcr_solve(int C, int bw, const double* __restrict__ red, double*
     double* tmp = f;
     f = g;
     g = tmp;
-#pragma unroll
-    for (int k = 0; k < 8; ++k) ab[k] = nx[k];
-  }
-  if (nlev == 0) {
-#pragma unroll
-    for (int k = 0; k < 4; ++k) ab[k] = act ? red[4 * (int64_t)c + k] : 0.0;
   }
   if (act)
-    for (int col = 0; col < bw; ++col) {  // u_c = E_c f_c, E_c now in ab[0..3]
+    for (int col = 0; col < bw; ++col) {  // u_c = E_c f_c, E_c the final block
       const double f0 = f[col * ld + 2 * c], f1 = f[col * ld + 2 * c + 1];
-      u[col * ld + 2 * c] = ab[0] * f0 + ab[1] * f1;
-      u[col * ld + 2 * c + 1] = ab[2] * f0 + ab[3] * f1;
+      u[col * ld + 2 * c] = fin[0] * f0 + fin[1] * f1;
+      u[col * ld + 2 * c + 1] = fin[2] * f0 + fin[3] * f1;
     }
 }
 
