@@ -197,13 +197,12 @@ __global__ __launch_bounds__(256) void k_sai_commit(const ProbDev* __restrict__ 
   if (!std::is_same<TS, double>::value && j == 0) p.V[e] = v;
 }
 
-// The interface system by cyclic reduction (the last workgroup of the solve): f, g are
+// The interface system by cyclic reduction (k_sai_pcr, one workgroup per column): f, g are
 // ping-pong buffers of bw interface vectors, column-major (entry (2c + k) of column col at
 // col 2C + 2c + k: F_c for k = 0, G_c for k = 1; consecutive chunks are consecutive in
 // memory, so a wave's accesses spread over the LDS banks); the result goes to u (same
-// layout).  Thread c < C takes chunk c for every column; a level's coefficients are
-// fetched one level ahead, so their latency hides behind the current level.  The
-// workgroup barrier orders the levels.
+// layout).  Thread c < C takes chunk c for every column; every level's coefficients are
+// loaded up front.  The workgroup barrier orders the levels.
 template <bool kLdsBuf>
 __device__ void pcr_solve(int C, int bw, const double* __restrict__ red, double* f, double* g, double* u) {
   constexpr int kMaxLev = 8;  // C <= 256 chunks
