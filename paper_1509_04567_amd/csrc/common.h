@@ -97,7 +97,7 @@ struct TriDev {
   double* W;               // n x bw row-major: the solution block
   double* GW;              // bw x bw: Gram of (I - gamma L) V_l (residual estimate)
   int32_t* piv;            // row interchanges of the projected matrix's LU
-  unsigned* cnt;           // 2 counters (solve, Gram)
+  unsigned* cnt;           // 2 counters ([1]: the Gram's last-workgroup hand-off; [0] unused)
   double* LU;              // N0 x N0 (ld N0) work: LU factors of the projected matrix
   double* Kinv;            // N0 x N0 (ld N0): its inverse
   const double* H;         // projected matrix (Arnoldi Hessenberg of the shifted inverse)

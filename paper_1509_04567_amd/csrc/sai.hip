@@ -197,13 +197,12 @@ __global__ __launch_bounds__(256) void k_sai_commit(const ProbDev* __restrict__ 
   if (!std::is_same<TS, double>::value && j == 0) p.V[e] = v;
 }
 
-// The interface system by cyclic reduction (k_sai_pcr, one workgroup per column): f, g are
+// The interface system by cyclic reduction (k_sai_pcr, one workgroup per column): f, g are LDS
 // ping-pong buffers of bw interface vectors, column-major (entry (2c + k) of column col at
 // col 2C + 2c + k: F_c for k = 0, G_c for k = 1; consecutive chunks are consecutive in
 // memory, so a wave's accesses spread over the LDS banks); the result goes to u (same
 // layout).  Thread c < C takes chunk c for every column; every level's coefficients are
 // loaded up front.  The workgroup barrier orders the levels.
-template <bool kLdsBuf>
 __device__ void pcr_solve(int C, int bw, const double* __restrict__ red, double* f, double* g, double* u) {
   constexpr int kMaxLev = 8;  // C <= 256 chunks
   const int nlev = sai_levels(C);
@@ -243,10 +242,7 @@ __device__ void pcr_solve(int C, int bw, const double* __restrict__ red, double*
         g[col * ld + 2 * c + 1] = f1 - (ab[2] * m0 + ab[3] * m1) - (ab[6] * p0 + ab[7] * p1);
       }
     }
-    if (kLdsBuf)
-      lds_barrier();
-    else
-      __syncthreads();
+    lds_barrier();
     double* tmp = f;
     f = g;
     g = tmp;
@@ -413,7 +409,7 @@ __global__ __launch_bounds__(256) void k_sai_pcr(const TriDev* __restrict__ tds)
   const double* src = t.rrhs + col * ld;
   bulk_load(ld, [=](int64_t e) -> double { return src[e]; }, [=](int64_t e, double v) { f[e] = v; });
   __syncthreads();
-  pcr_solve<true>(t.C, 1, t.red, f, g, t.ru + col * ld);
+  pcr_solve(t.C, 1, t.red, f, g, t.ru + col * ld);
 }
 
 // W[r, col] -= G_{c-1} vL[r] + F_{c+1} vR[r]: the chunk solutions coupled to the
