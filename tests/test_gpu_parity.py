@@ -333,3 +333,19 @@ def test_repeated_solve_is_bitwise_identical(ctx):
     o2, r2 = ctx.solve_batch([p])
     assert r1 == r2
     assert np.array_equal(gpu_out(o1[0]), gpu_out(o2[0]))
+
+
+@pytest.mark.parametrize("krylov", [0, 1])
+def test_repeated_batch_is_bitwise_identical_in_both_spaces(ctx, krylov):
+    # every cross-workgroup reduction (TSQR combine, projection partials, the shifted
+    # solve's interface system, GEMM partial tiles) sums in a fixed order: a batch of
+    # ragged windows gives the same bits on every call
+    probs = [synth.random_ade_problem(40 + i, n, modes=3, deg=7, s=25, krylov_steps=14, n_out=4)
+             for i, n in enumerate((300, 517, 1024))]
+    for q in probs:
+        q.krylov = krylov
+    o1, r1 = ctx.solve_batch(probs)
+    o2, r2 = ctx.solve_batch(probs)
+    assert r1 == r2
+    for a, b in zip(o1, o2):
+        assert np.array_equal(gpu_out(a), gpu_out(b))
