@@ -283,10 +283,12 @@ pe_status pe_wr_burgers(pe_ctx* ctx, const pe_wr_problem* wr, pe_report* reports
  * order of the reductions), never the method.
  *   probs       host array of nprob; only op.n, rank_max and prec are read
  *   cache_path  text file of lines "log2n width mixed rows_u rows_p", or NULL; read before
- *               tuning (its entries are taken as tuned) and, when this call timed a new
- *               key, rewritten after with every entry of ctx
+ *               tuning (its entries are taken as tuned; lines whose chunk heights are not
+ *               powers of two in [64, 4096] and [16, 1024] are skipped) and, when this call
+ *               timed a new key, rewritten after with every entry of ctx
  *   tuned       host, or NULL: the number of keys timed by this call
- * Uses the context workspace (grown on demand) and synchronises the stream.  Errors:
+ * Uses the context workspace (grown on demand) and synchronises the stream; each key
+ * costs up to 20 timed runs, seconds per key on grids of 10^6 points.  Errors:
  * PE_ERR_ARG for n < 64, rank_max outside [0, 31] or an unwritable cache file. */
 pe_status pe_autotune(pe_ctx* ctx, const pe_problem* probs, int32_t nprob, const char* cache_path,
                       int32_t* tuned, void* stream);

@@ -360,13 +360,15 @@ void set_geometry(ProbDev& d, int64_t n, int bw) {
     auto it = g_tune->find(TuneKey{tune_nlog2(n), bw, d.mixed});
     if (it != g_tune->end()) {
       int cg, ct;
-      if (it->second.rows_u >= 64 && it->second.rows_u <= 4096 && it->second.rows_u <= n &&
-          update_chunks_for(n, bw, it->second.rows_u, cg, ct)) {
-        d.rows_u = it->second.rows_u;
+      // chunk heights are powers of two (chunk_of shifts by rows_u_log2); anything else
+      // in the table is ignored
+      const int ru = it->second.rows_u, rp = it->second.rows_p;
+      if (ru >= 64 && ru <= 4096 && (ru & (ru - 1)) == 0 && ru <= n && update_chunks_for(n, bw, ru, cg, ct)) {
+        d.rows_u = ru;
         d.comb_global = cg;
         d.comb_tree = ct;
       }
-      if (it->second.rows_p >= 16 && it->second.rows_p * bw <= 1024) tuned_p = it->second.rows_p;
+      if (rp >= 16 && (rp & (rp - 1)) == 0 && rp * bw <= 1024) tuned_p = rp;
     }
   }
   d.rows_u_log2 = 0;
@@ -2022,7 +2024,9 @@ pe_status pe_autotune(pe_ctx* ctx, const pe_problem* probs, int32_t nprob, const
     std::ifstream in(cache_path);
     int a, b, c, ru, rp;
     while (in >> a >> b >> c >> ru >> rp)
-      if (a > 0 && a < 48 && b >= 1 && b <= 32 && (c == 0 || c == 1)) ctx->tune[TuneKey{a, b, c}] = TuneVal{ru, rp};
+      if (a > 0 && a < 48 && b >= 1 && b <= 32 && (c == 0 || c == 1) && ru >= 64 && ru <= 4096 && (ru & (ru - 1)) == 0 &&
+          rp >= 16 && rp <= 1024 && (rp & (rp - 1)) == 0)
+        ctx->tune[TuneKey{a, b, c}] = TuneVal{ru, rp};
   }
   int count = 0;
   for (int i = 0; i < nprob; ++i) {

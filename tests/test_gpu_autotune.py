@@ -94,3 +94,14 @@ def test_c2_full_size_on_tuned_tiles(pe, prec):
         ctx.close()
     assert not reps[0]["flags"] & 1, reps[0]
     assert rel(gpu_out(outs[0]), ref) < (FP64_TOL if prec == "fp64" else MIXED_TOL), reps[0]
+
+
+def test_cache_lines_with_invalid_chunk_heights_are_skipped(pe, tmp_path):
+    cache = tmp_path / "tiles.txt"
+    cache.write_text("10 4 0 100 16\n10 3 0 256 20\n10 2 0 128 32\n10 5 0 8192 32\n")
+    ctx = pe.Context(0)
+    try:
+        assert ctx.autotune([], str(cache)) == 0
+        assert ctx.autotune_table() == {(10, 2, 0): (128, 32)}
+    finally:
+        ctx.close()
