@@ -87,7 +87,8 @@ typedef struct {
   const double* coeffs;
 } pe_stencil;
 
-/* One window subproblem (Sec. 2.1-2.2; Fig. 2.1 "Given: A, u0, g(t)").
+/* One window subproblem (Sec. 2.1-2.2; the inputs of the linear algorithm of Fig. 2.1:
+ * the operator, the initial value and the source).
  *   u0        device, n: initial condition of the whole problem (shifted: used for L u0)
  *   t0, t1    window; the source acts on [t0, t1] and is zero after t1
  *   t_samples host, s ascending, t_samples[0] = t0, t_samples[s-1] = t1, s >= 1
