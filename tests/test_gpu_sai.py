@@ -69,7 +69,13 @@ def test_sai_c2_full_size_fp64(ctx):
     p = sai(synth.config_c2())
     ref, _ = oracle.solve_window(p, "spectral")
     outs, reps = ctx.solve_batch([p])
-    assert rel(gpu_out(outs[0]), ref) < FP64_TOL, reps[0]
+    got = gpu_out(outs[0])
+    assert rel(got, ref) < FP64_TOL, reps[0]
+    # every output time on its own, against the largest output's norm (the step control
+    # bounds the error relative to the solution's scale, not to each v(t_k))
+    scale = np.linalg.norm(ref, axis=0).max()
+    per_out = np.linalg.norm(got - ref, axis=0) / scale
+    assert per_out.max() < FP64_TOL, per_out
     assert reps[0]["cycles"] <= 100, reps[0]
     per_t = np.linalg.norm(gpu_out(outs[0]) - ref, axis=0) / np.linalg.norm(ref, axis=0)
     assert per_t.max() < 10 * FP64_TOL
@@ -80,7 +86,10 @@ def test_sai_c2_full_size_mixed(ctx):
     p = sai(synth.config_c2(tol=1e-8))
     ref, _ = oracle.solve_window(p, "spectral")
     outs, reps = ctx.solve_batch([p], precision=pe.PE_MIXED)
-    assert rel(gpu_out(outs[0]), ref) < MIXED_TOL, reps[0]
+    got = gpu_out(outs[0])
+    assert rel(got, ref) < MIXED_TOL, reps[0]
+    per_out = np.linalg.norm(got - ref, axis=0) / np.linalg.norm(ref, axis=0).max()
+    assert per_out.max() < MIXED_TOL, per_out
 
 
 def test_sai_paraexp_windows_and_mixed_batch(ctx):
